@@ -1,0 +1,129 @@
+/*
+ * zpm -- exact multiplication of dense polynomials with integer coefficients on
+ * MI355X (gfx950), by the method of "Parallel Integer Polynomial Multiplication"
+ * (Chen, Covanov, Mansouri, Moreno Maza, Xie, Xie): each coefficient is split
+ * into K limbs of M bits, the bivariate product is obtained from a cyclic
+ * convolution mod x^K - 1 and a negacyclic convolution mod x^K + 1 computed with
+ * two-dimensional number-theoretic transforms modulo word-size Fourier primes,
+ * and the coefficients are recovered by CRT and evaluation at x = 2^M.
+ *
+ * Problem statement (Section 1): given a(y), b(y) in Z[y], compute c = a b.
+ *
+ * Coefficient encoding (Section 2.3 layout, Relation (definingN) for the range):
+ * a polynomial with d coefficients of bound N is d * ceil(N/64) little-endian
+ * uint64 words; coefficient i occupies words [i*w, (i+1)*w), w = ceil(N/64), as
+ * N-bit two's complement.  Only bits [0, N) are read: the value is sign-extended
+ * from bit N-1 and higher bits in the top word are ignored.
+ *
+ * The product has da + db - 1 coefficients.  Coefficient i is written at
+ * c + i*wc as wc words of two's complement; wc must be at least
+ * ceil(zpm_out_bits(da, Na, db, Nb) / 64) and extra words hold the sign.
+ *
+ * Memory: a, b and c are DEVICE pointers owned by the caller (for example
+ * torch tensors' data_ptr()); c must not overlap a or b.  The context owns its
+ * tables and workspace.  All calls taking a stream are stream-ordered: they
+ * enqueue work and return; argument errors are reported before anything is
+ * enqueued and leave c untouched.  Errors raised by the device are reported by
+ * zpm_sync.  One context must not be used from two host threads at once, and
+ * calls that share a context run in the order they are enqueued on ONE stream
+ * (the workspace is shared); use one context per stream for concurrency.
+ */
+#ifndef ZPM_H
+#define ZPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ZPM_OK 0
+#define ZPM_EINVAL (-1)      /* bad argument (null pointer, size, output width) */
+#define ZPM_ENOMEM (-2)      /* device allocation failed; the context stays usable */
+#define ZPM_EDEVICE (-3)     /* HIP runtime or kernel error */
+#define ZPM_EUNSUPPORTED (-5) /* sizes beyond what the prime table supports */
+#define ZPM_EBUSY (-7)       /* server: no capacity for the request right now */
+#define ZPM_ENOTFOUND (-8)   /* server: unknown ticket */
+
+typedef struct zpm_ctx zpm_ctx;
+
+/* Parameters the planner chose for a product (Section 2.3, DetermineBase and
+ * RecoveryPrime): N padded to K*M, K limbs of M bits, np primes p_k < 2^31 with
+ * prod p_k > 4 d K 2^(2M) (Relation (recoveryModulo) with the product of the
+ * primes in the role of p), y-transform length L = 2^log2_L >= da + db - 1. */
+typedef struct zpm_plan_info {
+  int64_t da, db;
+  int32_t Na, Nb;
+  int32_t K, M, np;
+  int32_t log2_L;        /* cyclic length along y */
+  int32_t log2_L1;       /* inner y factor done inside the row-convolution kernel */
+  int32_t ncol;          /* strided column passes of the y-transform */
+  int32_t col_log2n[4];  /* their lengths, outermost first */
+  int32_t W;             /* 32-bit words of each CRT value */
+  int32_t log2P;         /* bit length of the prime product */
+  int32_t nout_bits;     /* == zpm_out_bits(...) */
+  int64_t workspace_bytes;
+} zpm_plan_info;
+
+/* Library version, e.g. 100 for 0.1.0. */
+int zpm_version(void);
+
+/* Human-readable text for an error code (static storage). */
+const char *zpm_strerror(int err);
+
+/* Two's complement width that holds every coefficient of the product:
+ * |c_i| <= min(da, db) 2^(Na+Nb-2) (Relation (citighterbound) with the exact
+ * number of terms), so Na + Nb - 1 + bitlength(min(da, db)).  Host only. */
+int32_t zpm_out_bits(int64_t da, int32_t Na, int64_t db, int32_t Nb);
+
+/* Planner (host only, needs no GPU).  K and np: 0 = choose, otherwise forced
+ * (ZPM_EUNSUPPORTED if no feasible plan has them). */
+int zpm_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np,
+             zpm_plan_info *out);
+
+/* Prime table (host only): the k-th Fourier prime (largest first) and a
+ * primitive 2^21-th root of unity modulo it.  ZPM_EINVAL if k is out of range. */
+int zpm_prime(int32_t k, uint32_t *p, uint32_t *root);
+
+/* Create a context on HIP device `device`.  Tables and workspace are allocated
+ * on first use and grown as needed. */
+int zpm_create(zpm_ctx **out, int device);
+void zpm_destroy(zpm_ctx *ctx);
+
+/* c = a * b (the algorithm of Section 2.3).  `stream` is a hipStream_t (NULL =
+ * default stream).  da or db == 0 gives an empty product (nothing written). */
+int zpm_mul(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
+            int64_t db, int32_t Nb, uint64_t *c, int32_t wc, void *stream);
+
+/* zpm_mul with a forced plan and an optional stop point, for tests and tuning.
+ * K, np: as in zpm_plan.  stop_after: 0 = full product; 1..4 = stop after
+ * convert-in, the forward column passes, the row convolutions or the inverse
+ * column passes, and copy the workspace (np*2K*L uint32 residues, column
+ * (k, j) at [(k*2K + j)*L, ...)) to the device buffer ws_out, which must hold
+ * zpm_plan_info.workspace_bytes. */
+int zpm_mul_ex(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
+               int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t K, int32_t np,
+               int32_t stop_after, uint32_t *ws_out, void *stream);
+
+/* Per-kernel timing.  Between zpm_profile_begin and zpm_profile_end every kernel
+ * the context launches is bracketed by HIP events recorded on its stream.
+ * zpm_profile_end waits for those events and returns, per kernel kind, the
+ * number of launches and the summed GPU time; it writes at most max_out
+ * entries and sets *n_out to the number of kinds seen. */
+typedef struct zpm_kernel_time {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} zpm_kernel_time;
+int zpm_profile_begin(zpm_ctx *ctx);
+int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t *n_out);
+
+/* Wait for the stream and report any device error raised by earlier calls. */
+int zpm_sync(zpm_ctx *ctx, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZPM_H */

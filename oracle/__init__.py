@@ -32,7 +32,7 @@ def build(force: bool = True) -> str:
     """Compile the C schoolbook into ``oracle/liboracle.so`` with gcc + OpenMP."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared",
+        cmd = ["gcc", "-O3", "-march=x86-64-v3", "-mtune=generic", "-fopenmp", "-fPIC", "-shared",
                "-std=c11", "-Wall", "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)

@@ -1,0 +1,84 @@
+"""ctypes binding of ``libzpm.so`` (the C-ABI declared in ``include/zpm.h``).
+
+Argument marshalling only: every step of a product runs in the library's HIP
+kernels.  Importing this module fails loudly when the library is not built;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libzpm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1612_05778_amd.build` "
+        "(hipcc, gfx950). There is no CPU fallback.")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+c_i32, c_i64, c_u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+c_vp = ctypes.c_void_p
+
+ZPM_OK = 0
+ZPM_EINVAL = -1
+ZPM_ENOMEM = -2
+ZPM_EDEVICE = -3
+ZPM_EUNSUPPORTED = -5
+ZPM_EBUSY = -7
+ZPM_ENOTFOUND = -8
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("da", c_i64), ("db", c_i64), ("Na", c_i32), ("Nb", c_i32),
+        ("K", c_i32), ("M", c_i32), ("np", c_i32),
+        ("log2_L", c_i32), ("log2_L1", c_i32), ("ncol", c_i32), ("col_log2n", c_i32 * 4),
+        ("W", c_i32), ("log2P", c_i32), ("nout_bits", c_i32),
+        ("workspace_bytes", c_i64),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["col_log2n"] = list(self.col_log2n)[: self.ncol]
+        return d
+
+
+def _sig(name, res, args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+zpm_version = _sig("zpm_version", ctypes.c_int, [])
+zpm_strerror = _sig("zpm_strerror", ctypes.c_char_p, [ctypes.c_int])
+zpm_out_bits = _sig("zpm_out_bits", c_i32, [c_i64, c_i32, c_i64, c_i32])
+zpm_plan = _sig("zpm_plan", ctypes.c_int,
+                [c_i64, c_i32, c_i64, c_i32, c_i32, c_i32, ctypes.POINTER(PlanInfo)])
+zpm_prime = _sig("zpm_prime", ctypes.c_int,
+                 [c_i32, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)])
+zpm_create = _sig("zpm_create", ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.c_int])
+zpm_destroy = _sig("zpm_destroy", None, [c_vp])
+zpm_mul = _sig("zpm_mul", ctypes.c_int,
+               [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_vp])
+zpm_mul_ex = _sig("zpm_mul_ex", ctypes.c_int,
+                  [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32,
+                   c_i32, c_i32, c_i32, c_vp, c_vp])
+zpm_sync = _sig("zpm_sync", ctypes.c_int, [c_vp, c_vp])
+
+EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
+           "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync"]
+
+
+class ZpmError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {zpm_strerror(code).decode()} ({code})")
+
+
+def check(code: int, what: str = "zpm") -> None:
+    if code != ZPM_OK:
+        raise ZpmError(code, what)

@@ -1,0 +1,114 @@
+"""Python API over the C-ABI.  PyTorch provides device memory and streams only.
+
+>>> ctx = Context(0)
+>>> c = ctx.mul(a, Na, b, Nb)      # a: (da, ceil(Na/64)) int64 CUDA tensor, ...
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native as nat
+
+
+def out_bits(da: int, Na: int, db: int, Nb: int) -> int:
+    return int(nat.zpm_out_bits(da, Na, db, Nb))
+
+
+def out_words(da: int, Na: int, db: int, Nb: int) -> int:
+    return (out_bits(da, Na, db, Nb) + 63) // 64
+
+
+def plan(da: int, Na: int, db: int, Nb: int, K: int = 0, np: int = 0) -> dict:
+    info = nat.PlanInfo()
+    nat.check(nat.zpm_plan(da, Na, db, Nb, K, np, ctypes.byref(info)), "zpm_plan")
+    return info.as_dict()
+
+
+def prime(k: int) -> tuple[int, int]:
+    p, r = nat.c_u32(), nat.c_u32()
+    nat.check(nat.zpm_prime(k, ctypes.byref(p), ctypes.byref(r)), "zpm_prime")
+    return p.value, r.value
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _check_operand(t: torch.Tensor, N: int, name: str) -> int:
+    if t.dtype != torch.int64 or not t.is_cuda or t.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D int64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.shape[1] != (N + 63) // 64:
+        raise ValueError(f"{name} has {t.shape[1]} words per coefficient, N={N} needs {(N + 63) // 64}")
+    return t.shape[0]
+
+
+class Context:
+    """A zpm context on one device (tables, plan constants and workspace)."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = nat.c_vp()
+        nat.check(nat.zpm_create(ctypes.byref(h), device), "zpm_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            nat.zpm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def mul(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int, wc: int | None = None,
+            out: torch.Tensor | None = None, stream=None, K: int = 0, np: int = 0) -> torch.Tensor:
+        """Exact product: (da+db-1, wc) int64 tensor of two's complement words."""
+        da = _check_operand(a, Na, "a")
+        db = _check_operand(b, Nb, "b")
+        need = out_words(da, Na, db, Nb) if (da and db) else 1
+        wc = need if wc is None else wc
+        n = da + db - 1 if (da and db) else 0
+        if out is None:
+            out = torch.empty((n, wc), dtype=torch.int64, device=a.device)
+        elif out.shape != (n, wc) or out.dtype != torch.int64 or not out.is_contiguous():
+            raise ValueError("out has the wrong shape or dtype")
+        st = _stream_handle(stream)
+        if K or np:
+            rc = nat.zpm_mul_ex(self._h, a.data_ptr(), da, Na, b.data_ptr(), db, Nb,
+                                out.data_ptr() if n else None, wc, K, np, 0, None, st)
+        else:
+            rc = nat.zpm_mul(self._h, a.data_ptr(), da, Na, b.data_ptr(), db, Nb,
+                             out.data_ptr() if n else None, wc, st)
+        nat.check(rc, "zpm_mul")
+        return out
+
+    def mul_stage(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int, stop_after: int,
+                  K: int = 0, np: int = 0, stream=None) -> tuple[torch.Tensor, dict]:
+        """Run the product up to a stage and return the workspace (np, 2K, L) uint32 as int64."""
+        da = _check_operand(a, Na, "a")
+        db = _check_operand(b, Nb, "b")
+        info = plan(da, Na, db, Nb, K, np)
+        ws = torch.empty(info["workspace_bytes"] // 4, dtype=torch.int32, device=a.device)
+        wc = out_words(da, Na, db, Nb)
+        out = torch.empty((da + db - 1, wc), dtype=torch.int64, device=a.device)
+        rc = nat.zpm_mul_ex(self._h, a.data_ptr(), da, Na, b.data_ptr(), db, Nb, out.data_ptr(), wc,
+                            info["K"], info["np"], stop_after, ws.data_ptr(), _stream_handle(stream))
+        nat.check(rc, "zpm_mul_ex")
+        L = 1 << info["log2_L"]
+        w = ws.to(torch.int64) & 0xFFFFFFFF
+        return w.view(info["np"], 2 * info["K"], L), info
+
+    def sync(self, stream=None) -> None:
+        nat.check(nat.zpm_sync(self._h, _stream_handle(stream)), "zpm_sync")

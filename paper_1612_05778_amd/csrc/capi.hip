@@ -1,0 +1,293 @@
+// C-ABI of the zpm library: context, planner queries and the multiply entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/zpm.h"
+#include "ctx.hpp"
+#include "kernels.hpp"
+#include "nt.hpp"
+#include "plan.hpp"
+
+using namespace zpm;
+
+static void fill_info(const Plan &pl, zpm_plan_info *o) {
+  std::memset(o, 0, sizeof(*o));
+  o->da = pl.da; o->db = pl.db; o->Na = pl.Na; o->Nb = pl.Nb;
+  o->K = pl.K; o->M = pl.M; o->np = pl.np;
+  o->log2_L = pl.logL; o->log2_L1 = pl.logL1; o->ncol = pl.ncol;
+  for (int c = 0; c < pl.ncol && c < 4; ++c) o->col_log2n[c] = pl.col[c].logn;
+  o->W = pl.W; o->log2P = pl.log2P; o->nout_bits = pl.nout_bits;
+  o->workspace_bytes = pl.ws_words * 4;
+}
+
+namespace zpm {
+
+int Ctx::ensure_tables(int np, int64_t H) {
+  H = std::max<int64_t>(H, 2);
+  if (np <= np_built && H <= H_built) return ZPM_OK;
+  const int np2 = std::max(np, np_built);
+  const int64_t H2 = std::max(H, H_built);
+  if (hipDeviceSynchronize() != hipSuccess) return ZPM_EDEVICE;
+  std::vector<uint2> host((size_t)np2 * 2 * H2);
+  for (int k = 0; k < np2; ++k)
+    fill_heap(k, (int)H2, &host[(size_t)k * 2 * H2], &host[(size_t)k * 2 * H2 + H2]);
+  uint2 *dev = nullptr;
+  if (hipMalloc(&dev, host.size() * sizeof(uint2)) != hipSuccess) return ZPM_ENOMEM;
+  if (hipMemcpy(dev, host.data(), host.size() * sizeof(uint2), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(dev);
+    return ZPM_EDEVICE;
+  }
+  if (heaps) (void)hipFree(heaps);
+  heaps = dev;
+  np_built = np2;
+  H_built = H2;
+  std::vector<PrimeDev> pd(MAXNP);
+  const auto &T = prime_table();
+  for (int k = 0; k < MAXNP; ++k) {
+    std::memset(&pd[k], 0, sizeof(PrimeDev));
+    pd[k].p = T[k].p;
+    pd[k].pinv = T[k].pinv;
+    pd[k].c32 = T[k].c32;
+    pd[k].c32s = T[k].c32s;
+    pd[k].ones = T[k].ones;
+    if (k < np2) {
+      pd[k].hf = heaps + (size_t)k * 2 * H2;
+      pd[k].hi = heaps + (size_t)k * 2 * H2 + H2;
+    }
+  }
+  if (hipMemcpy(primes, pd.data(), sizeof(PrimeDev) * MAXNP, hipMemcpyHostToDevice) != hipSuccess)
+    return ZPM_EDEVICE;
+  return ZPM_OK;
+}
+
+int Ctx::plan_consts(const Plan &pl, PlanDev **out) {
+  auto key = std::make_tuple(pl.np, pl.K, pl.M, pl.logL);
+  auto it = consts.find(key);
+  if (it != consts.end()) { *out = it->second; return ZPM_OK; }
+  PlanDev h;
+  std::memset(&h, 0, sizeof(h));
+  crt_constants(pl.np, h);
+  scale_constants(pl.np, pl.K, pl.M, pl.logL, h);
+  PlanDev *d = nullptr;
+  if (hipMalloc(&d, sizeof(PlanDev)) != hipSuccess) return ZPM_ENOMEM;
+  if (hipMemcpy(d, &h, sizeof(PlanDev), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return ZPM_EDEVICE;
+  }
+  consts[key] = d;
+  *out = d;
+  return ZPM_OK;
+}
+
+int Ctx::ensure_ws(int64_t words) {
+  if (words <= ws_words) return ZPM_OK;
+  if (hipDeviceSynchronize() != hipSuccess) return ZPM_EDEVICE;
+  if (ws) (void)hipFree(ws);
+  ws = nullptr;
+  ws_words = 0;
+  if (hipMalloc(&ws, (size_t)words * 4) != hipSuccess) return ZPM_ENOMEM;
+  ws_words = words;
+  return ZPM_OK;
+}
+
+int Ctx::get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np,
+                  Plan *out) {
+  auto key = std::make_tuple(da, Na, db, Nb, K, np);
+  auto it = plans.find(key);
+  if (it != plans.end()) { *out = it->second; return ZPM_OK; }
+  Plan pl;
+  const char *why = nullptr;
+  if (!make_plan(da, Na, db, Nb, K, np, pl, &why)) return ZPM_EUNSUPPORTED;
+  if (plans.size() > 65536) plans.clear();
+  plans[key] = pl;
+  *out = pl;
+  return ZPM_OK;
+}
+
+int Ctx::prepare(const Plan &pl, DevState *ds) {
+  int rc;
+  const int64_t H = std::max<int64_t>((int64_t)1 << pl.logL, 2 * (int64_t)pl.K);
+  if ((rc = ensure_tables(pl.np, H)) != ZPM_OK) return rc;
+  PlanDev *pd = nullptr;
+  if ((rc = plan_consts(pl, &pd)) != ZPM_OK) return rc;
+  if ((rc = ensure_ws(pl.ws_words)) != ZPM_OK) return rc;
+  ds->X = ws;
+  ds->primes = primes;
+  ds->plan = pd;
+  return ZPM_OK;
+}
+
+Ctx::~Ctx() {
+  (void)hipSetDevice(device);
+  (void)hipDeviceSynchronize();
+  if (ws) (void)hipFree(ws);
+  if (heaps) (void)hipFree(heaps);
+  if (primes) (void)hipFree(primes);
+  for (auto &kv : consts) (void)hipFree(kv.second);
+}
+
+}  // namespace zpm
+
+extern "C" {
+
+int zpm_version(void) { return 100; }
+
+const char *zpm_strerror(int err) {
+  switch (err) {
+    case ZPM_OK: return "ok";
+    case ZPM_EINVAL: return "invalid argument";
+    case ZPM_ENOMEM: return "device allocation failed";
+    case ZPM_EDEVICE: return "HIP device or runtime error";
+    case ZPM_EUNSUPPORTED: return "sizes not supported by the prime table";
+    case ZPM_EBUSY: return "no capacity right now";
+    case ZPM_ENOTFOUND: return "unknown ticket";
+    default: return "unknown error";
+  }
+}
+
+int32_t zpm_out_bits(int64_t da, int32_t Na, int64_t db, int32_t Nb) {
+  if (da < 1 || db < 1 || Na < 1 || Nb < 1) return 0;
+  return out_bits(da, Na, db, Nb);
+}
+
+int zpm_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np,
+             zpm_plan_info *out) {
+  if (!out || da < 1 || db < 1 || Na < 1 || Nb < 1 || K < 0 || np < 0) return ZPM_EINVAL;
+  Plan pl;
+  const char *why = nullptr;
+  if (!make_plan(da, Na, db, Nb, K, np, pl, &why)) return ZPM_EUNSUPPORTED;
+  fill_info(pl, out);
+  return ZPM_OK;
+}
+
+int zpm_prime(int32_t k, uint32_t *p, uint32_t *root) {
+  if (k < 0 || k >= MAXNP || !p || !root) return ZPM_EINVAL;
+  const auto &T = prime_table();
+  if (k >= (int)T.size()) return ZPM_EINVAL;
+  *p = T[k].p;
+  *root = T[k].root;
+  return ZPM_OK;
+}
+
+int zpm_create(zpm_ctx **out, int device) {
+  if (!out) return ZPM_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ZPM_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return ZPM_EDEVICE;
+  Ctx *c = new (std::nothrow) Ctx();
+  if (!c) return ZPM_ENOMEM;
+  c->device = device;
+  if (prime_table().size() < (size_t)MAXNP) { delete c; return ZPM_EUNSUPPORTED; }
+  if (hipMalloc(&c->primes, sizeof(PrimeDev) * MAXNP) != hipSuccess) { delete c; return ZPM_ENOMEM; }
+  *out = reinterpret_cast<zpm_ctx *>(c);
+  return ZPM_OK;
+}
+
+void zpm_destroy(zpm_ctx *ctx) { delete reinterpret_cast<Ctx *>(ctx); }
+
+static int check_mul_args(const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b, int64_t db,
+                          int32_t Nb, uint64_t *c, int32_t wc) {
+  if (da < 0 || db < 0 || Na < 1 || Nb < 1) return ZPM_EINVAL;
+  if (da == 0 || db == 0) return ZPM_OK;
+  if (!a || !b || !c) return ZPM_EINVAL;
+  const int32_t nb = out_bits(da, Na, db, Nb);
+  if (wc < (nb + 63) / 64) return ZPM_EINVAL;
+  // the output must not overlap either input
+  const uint64_t *c_end = c + (size_t)(da + db - 1) * wc;
+  const uint64_t *a_end = a + (size_t)da * ((Na + 63) / 64);
+  const uint64_t *b_end = b + (size_t)db * ((Nb + 63) / 64);
+  if (c < a_end && a < c_end) return ZPM_EINVAL;
+  if (c < b_end && b < c_end) return ZPM_EINVAL;
+  return ZPM_OK;
+}
+
+int zpm_mul_ex(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
+               int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t K, int32_t np,
+               int32_t stop_after, uint32_t *ws_out, void *stream) {
+  if (!ctx || K < 0 || np < 0 || stop_after < 0 || stop_after > 4) return ZPM_EINVAL;
+  if (stop_after && !ws_out) return ZPM_EINVAL;
+  int rc = check_mul_args(a, da, Na, b, db, Nb, c, wc);
+  if (rc != ZPM_OK) return rc;
+  if (da == 0 || db == 0) return ZPM_OK;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  std::lock_guard<std::mutex> lock(cx->mu);
+  if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  Plan pl;
+  if ((rc = cx->get_plan(da, Na, db, Nb, K, np, &pl)) != ZPM_OK) return rc;
+  DevState ds;
+  if ((rc = cx->prepare(pl, &ds)) != ZPM_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (launch_mul(pl, ds, a, b, c, wc, stop_after, st, &cx->prof) != hipSuccess) return ZPM_EDEVICE;
+  if (stop_after) {
+    if (hipMemcpyAsync(ws_out, ds.X, (size_t)pl.ws_words * 4, hipMemcpyDeviceToDevice, st) !=
+        hipSuccess)
+      return ZPM_EDEVICE;
+  }
+  return ZPM_OK;
+}
+
+int zpm_mul(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b, int64_t db,
+            int32_t Nb, uint64_t *c, int32_t wc, void *stream) {
+  return zpm_mul_ex(ctx, a, da, Na, b, db, Nb, c, wc, 0, 0, 0, nullptr, stream);
+}
+
+int zpm_profile_begin(zpm_ctx *ctx) {
+  if (!ctx) return ZPM_EINVAL;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  std::lock_guard<std::mutex> lock(cx->mu);
+  cx->prof.reset();
+  cx->prof.on = true;
+  return ZPM_OK;
+}
+
+int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t *n_out) {
+  if (!ctx || !n_out || (max_out > 0 && !out)) return ZPM_EINVAL;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  std::lock_guard<std::mutex> lock(cx->mu);
+  static const char *names[KK_COUNT] = {"bivariate_representation", "col_pass_fwd",
+                                        "convolve_rows", "col_pass_inv",
+                                        "recovering_product", "batch"};
+  double ms[KK_COUNT] = {0};
+  int64_t cnt[KK_COUNT] = {0};
+  int rc = ZPM_OK;
+  for (auto &r : cx->prof.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) { rc = ZPM_EDEVICE; break; }
+    float t = 0;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) { rc = ZPM_EDEVICE; break; }
+    ms[r.kind] += t;
+    cnt[r.kind] += 1;
+  }
+  cx->prof.on = false;
+  cx->prof.reset();
+  int n = 0;
+  for (int k = 0; k < KK_COUNT; ++k) {
+    if (!cnt[k]) continue;
+    if (n < max_out) {
+      std::memset(&out[n], 0, sizeof(zpm_kernel_time));
+      std::strncpy(out[n].name, names[k], sizeof(out[n].name) - 1);
+      out[n].launches = cnt[k];
+      out[n].total_ms = ms[k];
+    }
+    ++n;
+  }
+  *n_out = n;
+  return rc;
+}
+
+int zpm_sync(zpm_ctx *ctx, void *stream) {
+  if (!ctx) return ZPM_EINVAL;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return ZPM_EDEVICE;
+  if (hipGetLastError() != hipSuccess) return ZPM_EDEVICE;
+  return ZPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// Planner: the DetermineBase and RecoveryPrime steps of the algorithm of
+// Section 2.3, made into a table-free search.
+//
+// For every power-of-two K (K >= 2) the limb width is M = max(2, ceil(N/K)) so
+// that K M >= N (Relation (minimalConditionsForN) with N padded up to K M; sign
+// extension keeps the value).  The prime count np is the smallest whose product
+// exceeds 4 d K 2^(2M), Relation (recoveryModulo) with the product of the primes
+// playing the role of p (Section 4).  The transform length along y is the power
+// of two L >= da + db - 1, and L and 2K must divide p - 1 (Section 2.1).
+//
+// Among the feasible K the planner keeps the one with the lowest modelled time,
+// from the butterfly count of the row-column transforms (Section 3.3: K
+// transforms of length L along y, 2L convolutions of length K along x, for the
+// cyclic and the negacyclic product) plus CRT and memory traffic.  This follows
+// the remark of Section 4 that the word-prime variant gains from a large M.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "nt.hpp"
+#include "plan.hpp"
+
+namespace zpm {
+
+static int ceil_log2(int64_t x) {
+  int r = 0;
+  while (((int64_t)1 << r) < x) ++r;
+  return r;
+}
+
+int32_t out_bits(int64_t da, int32_t Na, int64_t db, int32_t Nb) {
+  // |c_i| <= min(da, db) 2^(Na+Nb-2), Relation (citighterbound) with the exact term count
+  int64_t t = std::min(da, db);
+  if (t <= 0) return 1;
+  int bl = 0;
+  while (((int64_t)1 << bl) <= t) ++bl;   // bit length of t
+  return Na + Nb - 1 + bl;
+}
+
+// Split of the y-transform: innermost factor L1 inside the fused kernel, the rest
+// into strided column passes of length <= 2^10 each.
+static bool split_y(Plan &pl) {
+  const int logK = ceil_log2(pl.K);
+  // the fused kernel holds two 2K x L1 tiles: 4 K L1 <= LDS_WORDS
+  int logcap = 0;
+  while ((4ll << (logK + logcap + 1)) <= LDS_WORDS) ++logcap;
+  if ((4ll << (logK + logcap)) > LDS_WORDS) return false;     // K too large even for L1 = 1
+  pl.logL1 = std::min(pl.logL, logcap);
+  int rest = pl.logL - pl.logL1;
+  int npass = (rest + 9) / 10;
+  if (npass > MAX_COL_PASSES) return false;
+  pl.ncol = npass;
+  int64_t S = (int64_t)1 << pl.logL;
+  for (int c = 0; c < npass; ++c) {
+    int take = rest / (npass - c);   // outermost passes get the smaller share
+    rest -= take;
+    pl.col[c].logn = take;
+    S >>= take;
+    pl.col[c].S = S;
+    // inner indices per workgroup: T * n <= LDS_WORDS, T <= S, T <= 64
+    int64_t T = std::min<int64_t>(S, std::min<int64_t>(64, LDS_WORDS >> take));
+    pl.col_tile[c] = (int32_t)std::max<int64_t>(T, 1);
+  }
+  return true;
+}
+
+static bool finish(Plan &pl) {
+  pl.log2P = bitlen_product(pl.np);
+  pl.W = (pl.log2P + 1 + 31) / 32;
+  if (pl.W > MAXW) return false;
+  const int wa = (pl.Na + 63) / 64, wb = (pl.Nb + 63) / 64;
+  const int wmax = std::max(wa, wb);
+  int ti = 64;
+  while (ti > 1 && ti * (2 * wmax + 1) > LDS_WORDS) ti >>= 1;
+  if (ti * (2 * wmax + 1) > LDS_WORDS) return false;
+  pl.ti_in = ti;
+  const int64_t J = 2 * (int64_t)pl.K - 1;
+  const int64_t nw32 = 2 * (int64_t)((pl.nout_bits + 63) / 64);
+  int64_t room = LDS_WORDS - 4 * nw32;
+  if (room < J * pl.W) return false;
+  pl.ti_out = (int32_t)std::min<int64_t>(64, room / (J * pl.W));
+  pl.ws_words = (int64_t)pl.np * 2 * pl.K << pl.logL;
+  return true;
+}
+
+static double model_cost(const Plan &pl) {
+  // butterflies of the row-column transforms (forward on both operands, inverse
+  // on the product) and the pointwise products, in units of one radix-2 butterfly
+  const double K = pl.K, L = std::ldexp(1.0, pl.logL), np = pl.np;
+  const double logK2 = std::log2(2.0 * K);
+  double bfly = np * (K * L * pl.logL            // forward y, two operands, K columns each
+                      + K * L * pl.logL           // inverse y, 2K columns
+                      + 3.0 * L * K * logK2       // forward x (two operands) + inverse x
+                      + 2.0 * K * L);             // pointwise
+  double alu = bfly * 12.0;
+  const double J = 2.0 * K - 1.0;
+  alu += (double)pl.nout * J * (np * 4.0 + (np + 1.0) * pl.W * 3.0);   // CRT
+  double words = np * 2.0 * K * L;
+  double bytes = 4.0 * words * 2.0 * (1 + pl.ncol * 1.5) + 4.0 * words;   // passes over the spectra
+  bytes += 8.0 * (pl.da * ((pl.Na + 63) / 64) + pl.db * ((pl.Nb + 63) / 64) +
+                  pl.nout * ((pl.nout_bits + 63) / 64));
+  double t_alu = alu / 39.3e12, t_mem = bytes / 5.0e12;
+  // coalescing penalty for strided passes with narrow tiles
+  for (int c = 0; c < pl.ncol; ++c)
+    if (pl.col_tile[c] < 16) t_mem *= 16.0 / pl.col_tile[c];
+  return t_alu + t_mem + 4e-6 * (4 + 3 * pl.ncol);
+}
+
+bool make_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, int32_t np_force,
+               Plan &out, const char **why) {
+  static const char *dummy;
+  if (!why) why = &dummy;
+  *why = nullptr;
+  if (da < 1 || db < 1 || Na < 1 || Nb < 1) { *why = "sizes must be positive"; return false; }
+  const int64_t nout = da + db - 1;
+  const int logL = ceil_log2(nout);
+  if (logL > LOG2_ROOT_ORDER) { *why = "da + db - 1 exceeds 2^21"; return false; }
+  const int32_t N = std::max(std::max(Na, Nb), 2);
+  const int64_t d = std::max(da, db);
+  bool found = false;
+  Plan best;
+  for (int logK = 1; logK <= 20; ++logK) {
+    const int32_t K = 1 << logK;
+    if (K_force && K != K_force) continue;
+    if (!K_force && K > 2 * (int64_t)N) break;     // limbs of 2 bits or less: no point going further
+    if (logK + 1 > LOG2_ROOT_ORDER) break;
+    Plan pl;
+    std::memset(&pl, 0, sizeof(pl));
+    pl.da = da; pl.db = db; pl.Na = Na; pl.Nb = Nb;
+    pl.nout = nout;
+    pl.nout_bits = out_bits(da, Na, db, Nb);
+    pl.K = K;
+    pl.M = std::max<int32_t>(2, (N + K - 1) / K);
+    pl.logL = logL;
+    if ((double)d * K > 4e18) continue;
+    int np = 0;
+    if (np_force) {
+      if (np_force > MAXNP || !primes_cover(np_force, d, K, pl.M)) continue;
+      np = np_force;
+    } else {
+      for (int t = 1; t <= MAXNP; ++t)
+        if (primes_cover(t, d, K, pl.M)) { np = t; break; }
+      if (!np) continue;
+    }
+    pl.np = np;
+    if (!split_y(pl) || !finish(pl)) continue;
+    pl.cost = model_cost(pl);
+    if (!found || pl.cost < best.cost) { best = pl; found = true; }
+  }
+  if (!found) { *why = "no feasible (K, M, np) for these sizes"; return false; }
+  out = best;
+  return true;
+}
+
+}  // namespace zpm

@@ -1,0 +1,67 @@
+// Internal structures shared by the host planner and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+#include <stddef.h>
+
+namespace zpm {
+
+// Word-size Fourier primes p < 2^31 with 2^LOG2_ROOT_ORDER | p - 1 (Section 2.1,
+// Relation (HavingAppropriatePrimitiveRootsOfUnity): the transform lengths along
+// y and the 2K-th root theta along x must divide p - 1).
+constexpr int MAXNP = 48;               // largest prime count a plan may use
+constexpr int LOG2_ROOT_ORDER = 21;     // every prime has a primitive 2^21-th root
+constexpr int MAXW = 48;                // 32-bit words of a CRT value (> 31*MAXNP + 2 bits)
+constexpr int BLOCK = 256;              // threads per workgroup of every kernel
+constexpr int LDS_WORDS = 16384;        // 64 KiB of LDS staging per workgroup
+constexpr int MAX_COL_PASSES = 4;
+
+// Per-prime constants resident on the device.
+struct PrimeDev {
+  uint32_t p;          // the prime
+  uint32_t pinv;       // p^{-1} mod 2^32 (Montgomery)
+  uint32_t c32, c32s;  // 2^32 mod p and its Shoup companion floor(c32 * 2^32 / p)
+  uint32_t ones;       // floor(2^32 / p): Shoup companion of 1 (plain reduction)
+  uint32_t pad[3];
+  const uint2 *hf;     // forward heap: hf[h + j] = (w^j, shoup) with w a primitive 2h-th root
+  const uint2 *hi;     // inverse heap: hi[h + j] = (w^-j, shoup)
+};
+
+// Per-plan constants (np primes, transform sizes) resident on the device.
+struct PlanDev {
+  uint2 scale[MAXNP];      // Montgomery-corrected 1/(2K L): 2^32 (2 K L)^{-1} mod p, Shoup pair
+  uint32_t pow2M[MAXNP];   // 2^M mod p (weight of the sign bit of the top limb)
+  uint2 crt_inv[MAXNP];    // (P/p_k)^{-1} mod p_k, Shoup pair
+  double crt_rcp[MAXNP];   // 1/p_k
+  uint32_t crt_q[MAXNP][MAXW];  // P/p_k, little-endian 32-bit words
+  uint32_t crt_p[MAXW];         // P
+};
+
+// A factor of the y-transform done by a strided column pass: index
+// i = inner + S (e + n outer), transform along e (length n = 2^logn).
+struct ColPass {
+  int32_t logn;
+  int64_t S;      // stride of e, in elements
+};
+
+struct Plan {
+  // caller-visible problem
+  int64_t da, db;
+  int32_t Na, Nb;
+  int64_t nout;        // da + db - 1
+  int32_t nout_bits;   // two's complement width that holds every c_i
+  // method parameters (Section 2: N = K M, beta = 2^M; Section 2.1: primes)
+  int32_t K, M, np;
+  int32_t logL;        // L = 2^logL >= da + db - 1, the cyclic length along y
+  int32_t logL1;       // innermost y factor handled inside the fused convolution kernel
+  int32_t ncol;        // number of strided column passes (outermost first)
+  ColPass col[MAX_COL_PASSES];
+  int32_t col_tile[MAX_COL_PASSES];  // inner indices per workgroup of each column pass
+  int32_t W;           // 32-bit words of each CRT value c_{i,j}
+  int32_t log2P;       // floor(log2(P)) + 1
+  int32_t ti_in;       // coefficients per workgroup in convert-in
+  int32_t ti_out;      // coefficients per workgroup in recovery
+  int64_t ws_words;    // workspace size in 32-bit words: np * 2K * L
+  double cost;         // planner's cost estimate (arbitrary units)
+};
+
+}  // namespace zpm

@@ -1,0 +1,106 @@
+"""Host-side logic of the HIP library (CPU only, no kernels run).
+
+* The C-ABI library loads and exports every function ``include/zpm.h`` declares.
+* The prime table: primes (sympy), 2^21 | p - 1, the stored root has order 2^21.
+* The planner (DetermineBase + RecoveryPrime of Section 2.3): K M >= N, the
+  prime product exceeds 4 d K 2^(2M) (Relation (recoveryModulo)), L >= da+db-1,
+  2K and L divide p - 1, CRT words hold P; checked with Python integers.
+* Output width (Relation (citighterbound)) agrees with the extreme cases.
+"""
+import os
+import re
+
+import pytest
+import sympy
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_1612_05778_amd import _native
+    return _native
+
+
+def test_exports_match_header(nat):
+    hdr = open(os.path.join(ROOT, "include", "zpm.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = set(re.findall(r"\b(zpm_[a-z_0-9]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    for name in sorted(declared):
+        assert hasattr(nat.lib, name), f"{name} declared in zpm.h but not exported"
+    assert nat.zpm_version() >= 100
+
+
+def test_prime_table(nat):
+    from paper_1612_05778_amd import api
+    ps = []
+    for k in range(48):
+        p, r = api.prime(k)
+        assert p < 2**31 and sympy.isprime(p) and (p - 1) % 2**21 == 0
+        assert pow(r, 2**20, p) == p - 1          # order exactly 2^21
+        ps.append(p)
+    assert ps == sorted(ps, reverse=True) and len(set(ps)) == 48
+    with pytest.raises(Exception):
+        api.prime(48)
+
+
+PLAN_CASES = [
+    (1024, 64, 1024, 64),          # signed 64-bit, 1024 coefficients
+    (65536, 4097, 65536, 4097),    # 4096-bit magnitudes, 2^16 coefficients
+    (262144, 16385, 262144, 16385),
+    (64, 33, 8192, 2049),
+    (1, 1, 1, 1),
+    (1, 5000, 3, 7),
+    (16, 8193, 16, 8193),
+    (5000, 2, 7, 300),
+]
+
+
+@pytest.mark.parametrize("da,Na,db,Nb", PLAN_CASES)
+def test_plan_invariants(nat, da, Na, db, Nb):
+    from paper_1612_05778_amd import api
+    pl = api.plan(da, Na, db, Nb)
+    K, M, np_ = pl["K"], pl["M"], pl["np"]
+    N = max(Na, Nb, 2)
+    assert K >= 2 and M >= 2 and K & (K - 1) == 0 and K * M >= N
+    d = max(da, db)
+    P = 1
+    for k in range(np_):
+        P *= api.prime(k)[0]
+    assert P > 4 * d * K * 2 ** (2 * M)
+    L = 1 << pl["log2_L"]
+    assert L >= da + db - 1 and (L == 1 or L // 2 < da + db - 1)
+    assert max(L, 2 * K) <= 2**21
+    assert pl["log2P"] == P.bit_length()
+    assert 32 * pl["W"] >= P.bit_length() + 1
+    # y-transform split: inner factor times the column passes is L
+    assert pl["log2_L1"] + sum(pl["col_log2n"]) == pl["log2_L"]
+    assert pl["workspace_bytes"] == 4 * np_ * 2 * K * L
+    assert pl["nout_bits"] == api.out_bits(da, Na, db, Nb)
+
+
+def test_forced_plans(nat):
+    from paper_1612_05778_amd import api
+    for K in (2, 4, 8, 16, 32, 64):
+        pl = api.plan(300, 500, 200, 400, K=K)
+        assert pl["K"] == K and pl["K"] * pl["M"] >= 500
+    pl = api.plan(300, 500, 200, 400, K=8, np=40)
+    assert pl["np"] == 40
+    with pytest.raises(nat.ZpmError):
+        api.plan(300, 500, 200, 400, K=2, np=1)     # one prime cannot hold 2^(2*250)
+    with pytest.raises(nat.ZpmError):
+        api.plan(0, 5, 3, 5)
+
+
+def test_out_bits_extremes(nat):
+    from paper_1612_05778_amd import api
+    for da, Na, db, Nb in [(1, 1, 1, 1), (3, 64, 5, 64), (4, 10, 4, 10), (1024, 64, 1024, 64),
+                           (65536, 4097, 65536, 4097)]:
+        nb = api.out_bits(da, Na, db, Nb)
+        t = min(da, db)
+        extreme = t * 2 ** (Na + Nb - 2)             # (-2^(Na-1)) (-2^(Nb-1)) summed t times
+        assert extreme <= 2 ** (nb - 1) - 1
+        assert nb == Na + Nb - 1 + t.bit_length()
+    assert api.out_bits(1024, 64, 1024, 64) == 138
+    assert api.out_bits(65536, 4097, 65536, 4097) == 8210
