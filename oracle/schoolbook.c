@@ -148,7 +148,7 @@ int oracle_polymul_rows(const uint64_t *a, int64_t da, int32_t Na,
             bad = 1;
         } else {
 #ifdef _OPENMP
-#pragma omp for schedule(dynamic, 16)
+#pragma omp for schedule(dynamic, 1)
 #endif
             for (int64_t r = 0; r < nrows; ++r) {
                 int64_t i = rows ? rows[r] : r;

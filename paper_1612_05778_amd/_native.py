@@ -69,8 +69,18 @@ zpm_mul_ex = _sig("zpm_mul_ex", ctypes.c_int,
                    c_i32, c_i32, c_i32, c_vp, c_vp])
 zpm_sync = _sig("zpm_sync", ctypes.c_int, [c_vp, c_vp])
 
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_i64), ("total_ms", ctypes.c_double)]
+
+
+zpm_profile_begin = _sig("zpm_profile_begin", ctypes.c_int, [c_vp])
+zpm_profile_end = _sig("zpm_profile_end", ctypes.c_int,
+                       [c_vp, ctypes.POINTER(KernelTime), c_i32, ctypes.POINTER(c_i32)])
+
 EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
-           "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync"]
+           "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync",
+           "zpm_profile_begin", "zpm_profile_end"]
 
 
 class ZpmError(RuntimeError):

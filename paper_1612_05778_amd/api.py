@@ -110,5 +110,15 @@ class Context:
         w = ws.to(torch.int64) & 0xFFFFFFFF
         return w.view(info["np"], 2 * info["K"], L), info
 
+    def profile_begin(self) -> None:
+        nat.check(nat.zpm_profile_begin(self._h), "zpm_profile_begin")
+
+    def profile_end(self) -> dict:
+        """{kernel name: (launches, total GPU ms)} since profile_begin."""
+        buf = (nat.KernelTime * 16)()
+        n = nat.c_i32()
+        nat.check(nat.zpm_profile_end(self._h, buf, 16, ctypes.byref(n)), "zpm_profile_end")
+        return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(n.value, 16))}
+
     def sync(self, stream=None) -> None:
         nat.check(nat.zpm_sync(self._h, _stream_handle(stream)), "zpm_sync")

@@ -1,0 +1,90 @@
+"""Parity at full size, in the launch configuration bench.py times (default plan).
+
+The oracle cannot redo a whole 2^16 x 4096-bit product in test time, so:
+
+* sampled output coefficients (first, last, middle and random indices) are
+  recomputed by the oracle one by one and compared bit for bit;
+* every coefficient is covered by the evaluation identities
+  a(r) b(r) = c(r) mod q for 61-bit primes q and random r, and exactly at
+  y = 1 and y = -1 (a wrong coefficient passes one modular check with
+  probability about (da + db) / q);
+* every coefficient satisfies |c_i| <= min(da, db) 2^(Na+Nb-2) and its words
+  above Nout bits are pure sign extension.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1612_05778_amd import synth
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+Q = [2305843009213693951, 2305843009213693921]
+
+
+def to_ints(words: np.ndarray) -> list[int]:
+    return [int.from_bytes(row.tobytes(), "little", signed=True) for row in words]
+
+
+def eval_mod(vals, r, q):
+    acc = 0
+    for x in reversed(vals):
+        acc = (acc * r + x) % q
+    return acc
+
+
+def full_checks(prod, got, nsample, seed):
+    da, db = prod.da, prod.db
+    nout = da + db - 1
+    rng = np.random.default_rng(seed)
+    rows = sorted(set([0, 1, da - 1, da, nout // 2, nout - 2, nout - 1] +
+                      rng.choice(nout, size=nsample, replace=False).tolist()))
+    print(f"[fullsize] oracle on {len(rows)} sampled rows", flush=True)
+    ref = oracle.polymul_rows(prod.a, da, prod.Na, prod.b, db, prod.Nb, rows, wc=got.shape[1])
+    assert np.array_equal(got[rows], ref), "sampled coefficients differ from the oracle"
+    print("[fullsize] evaluation identities", flush=True)
+    a = to_ints(prod.a)
+    b = to_ints(prod.b)
+    # inputs are sign-extended encodings, so from_bytes(signed) gives their values
+    c = to_ints(got)
+    bound = min(da, db) << (prod.Na + prod.Nb - 2)
+    nb = oracle.out_bits(da, prod.Na, db, prod.Nb)
+    assert all(-bound <= x <= bound for x in c)
+    assert all(-(1 << (nb - 1)) <= x < (1 << (nb - 1)) for x in c)
+    assert sum(a) * sum(b) == sum(c)
+    alt = lambda v: sum(v[0::2]) - sum(v[1::2])
+    assert alt(a) * alt(b) == alt(c)
+    r = int(rng.integers(2, 2**61))
+    for q in Q:
+        assert eval_mod(a, r, q) * eval_mod(b, r, q) % q == eval_mod(c, r, q)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1612_05778_amd.api import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def test_bits4096_64k(ctx):
+    prod = synth.bits4096_64k()
+    print("[fullsize] d=2^16 N=4097 on GPU", flush=True)
+    out = ctx.mul(dev(prod.a), prod.Na, dev(prod.b), prod.Nb)
+    torch.cuda.synchronize()
+    got = host(out)
+    del out
+    full_checks(prod, got, 40, 7)
+
+
+def test_bits16384_256k(ctx):
+    prod = synth.bits16384_256k()
+    print("[fullsize] d=2^18 N=16385 on GPU", flush=True)
+    out = ctx.mul(dev(prod.a), prod.Na, dev(prod.b), prod.Nb)
+    torch.cuda.synchronize()
+    got = host(out)
+    del out
+    torch.cuda.empty_cache()
+    full_checks(prod, got, 8, 8)
