@@ -85,6 +85,8 @@ def main() -> int:
     ap.add_argument("--workload", default="bits4096_64k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -97,6 +99,14 @@ def main() -> int:
     from paper_1612_05778_amd.workmodel import INT32_PEAK, HBM_PEAK, kernel_work, product_bits
 
     print(f"[bench] workload {args.workload}: generating", file=sys.stderr, flush=True)
+    if args.copy_mib:
+        n = args.copy_mib << 17                     # int64 elements
+        src = torch.ones(n, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prod = make_workload(args.workload)
     a = torch.from_numpy(prod.a.view(np.int64).copy()).cuda()
     b = torch.from_numpy(prod.b.view(np.int64).copy()).cuda()

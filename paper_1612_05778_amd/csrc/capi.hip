@@ -28,15 +28,27 @@ static void fill_info(const Plan &pl, zpm_plan_info *o) {
 
 namespace zpm {
 
-int Ctx::ensure_tables(int np, int64_t H) {
+int Ctx::ensure_tables(int np, int64_t H, int64_t TP) {
   H = std::max<int64_t>(H, 2);
-  if (np <= np_built && H <= H_built) return ZPM_OK;
+  TP = std::max<int64_t>(TP, 64);
+  if (np <= np_built && H <= H_built && TP <= TP_built) return ZPM_OK;
   const int np2 = std::max(np, np_built);
   const int64_t H2 = std::max(H, H_built);
+  const int64_t TP2 = std::max(TP, TP_built);
+  const int64_t per = 2 * H2 + TP2;          // forward heap, inverse heap, powers of 2^32
   if (hipDeviceSynchronize() != hipSuccess) return ZPM_EDEVICE;
-  std::vector<uint2> host((size_t)np2 * 2 * H2);
-  for (int k = 0; k < np2; ++k)
-    fill_heap(k, (int)H2, &host[(size_t)k * 2 * H2], &host[(size_t)k * 2 * H2 + H2]);
+  std::vector<uint2> host((size_t)np2 * per);
+  const auto &PT = prime_table();
+  for (int k = 0; k < np2; ++k) {
+    uint2 *blk = &host[(size_t)k * per];
+    fill_heap(k, (int)H2, blk, blk + H2);
+    const uint32_t p = PT[k].p;
+    uint32_t x = 1;
+    for (int64_t t = 0; t < TP2; ++t) {
+      blk[2 * H2 + t] = make_uint2(x, shoup(x, p));
+      x = mulmod(x, PT[k].c32, p);
+    }
+  }
   uint2 *dev = nullptr;
   if (hipMalloc(&dev, host.size() * sizeof(uint2)) != hipSuccess) return ZPM_ENOMEM;
   if (hipMemcpy(dev, host.data(), host.size() * sizeof(uint2), hipMemcpyHostToDevice) != hipSuccess) {
@@ -47,6 +59,7 @@ int Ctx::ensure_tables(int np, int64_t H) {
   heaps = dev;
   np_built = np2;
   H_built = H2;
+  TP_built = TP2;
   std::vector<PrimeDev> pd(MAXNP);
   const auto &T = prime_table();
   for (int k = 0; k < MAXNP; ++k) {
@@ -57,8 +70,9 @@ int Ctx::ensure_tables(int np, int64_t H) {
     pd[k].c32s = T[k].c32s;
     pd[k].ones = T[k].ones;
     if (k < np2) {
-      pd[k].hf = heaps + (size_t)k * 2 * H2;
-      pd[k].hi = heaps + (size_t)k * 2 * H2 + H2;
+      pd[k].hf = heaps + (size_t)k * per;
+      pd[k].hi = heaps + (size_t)k * per + H2;
+      pd[k].pow32 = heaps + (size_t)k * per + 2 * H2;
     }
   }
   if (hipMemcpy(primes, pd.data(), sizeof(PrimeDev) * MAXNP, hipMemcpyHostToDevice) != hipSuccess)
@@ -113,7 +127,7 @@ int Ctx::get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int
 int Ctx::prepare(const Plan &pl, DevState *ds) {
   int rc;
   const int64_t H = std::max<int64_t>((int64_t)1 << pl.logL, 2 * (int64_t)pl.K);
-  if ((rc = ensure_tables(pl.np, H)) != ZPM_OK) return rc;
+  if ((rc = ensure_tables(pl.np, H, (pl.M + 31) / 32 + 1)) != ZPM_OK) return rc;
   PlanDev *pd = nullptr;
   if ((rc = plan_consts(pl, &pd)) != ZPM_OK) return rc;
   if ((rc = ensure_ws(pl.ws_words)) != ZPM_OK) return rc;

@@ -79,7 +79,9 @@ __device__ void dif_group(uint32_t *s, const LdsShape &sh, int logh0, const uint
   const int hl = 1 << loghl;
   const int lgpt = sh.logn - R;                       // groups per transform (log)
   const int total = 1 << (sh.logntr + sh.logops + lgpt);
-  const bool tfast = sh.ts < sh.es;
+  // lanes run over transforms when those are adjacent in LDS, or when the element
+  // stride inside the group is small (which would put a wave on few banks)
+  const bool tfast = sh.ts < sh.es || ((sh.ts & 1) && hl * sh.es < 16 && sh.logntr + sh.logops >= 4);
   for (int g = threadIdx.x; g < total; g += BLOCK) {
     int t, q;
     if (tfast) {
@@ -124,7 +126,7 @@ __device__ void dit_group(uint32_t *s, const LdsShape &sh, int logh0, const uint
   const int loghr = logh0 + R - 1;
   const int lgpt = sh.logn - R;
   const int total = 1 << (sh.logntr + sh.logops + lgpt);
-  const bool tfast = sh.ts < sh.es;
+  const bool tfast = sh.ts < sh.es || ((sh.ts & 1) && h0 * sh.es < 16 && sh.logntr + sh.logops >= 4);
   for (int g = threadIdx.x; g < total; g += BLOCK) {
     int t, q;
     if (tfast) {
@@ -205,12 +207,26 @@ __device__ __forceinline__ uint32_t get32(const uint32_t *row, int nw, uint32_t 
   return (lo >> sh) | (hi << (32 - sh));
 }
 
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run
+// of tiles so that neighbouring tiles share that XCD's L2.  The grid has 8 * chunk
+// blocks; tiles >= ntiles are idle.
+__device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
+  const int64_t chunk = (ntiles + 7) >> 3;
+  return (int64_t)(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+}
+static inline int64_t xcd_grid(int64_t ntiles) { return 8 * ((ntiles + 7) >> 3); }
+
+// NP = np exactly: per-prime accumulators stay in registers, loops fully unrolled.
+template <int NP>
 __global__ __launch_bounds__(BLOCK) void k_bivariate_representation(
     const uint64_t *__restrict__ src, int64_t d, int32_t N, int32_t w, int32_t K, int32_t M,
-    int32_t np, uint32_t *__restrict__ X, int64_t L, int32_t col_off, int32_t TI,
+    int32_t np, uint32_t *__restrict__ X, int64_t L, int32_t col_off, int32_t logTI,
     const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd) {
   extern __shared__ uint32_t s[];
-  const int64_t i0 = (int64_t)blockIdx.x * TI;
+  const int TI = 1 << logTI;
+  const int64_t tile_id = xcd_tile((d + TI - 1) >> logTI);
+  const int64_t i0 = tile_id << logTI;
+  if (i0 >= d) return;
   const int ti = (int)min<int64_t>(TI, d - i0);
   const int nw = 2 * w;
   const int stride = nw + 1;
@@ -239,24 +255,48 @@ __global__ __launch_bounds__(BLOCK) void k_bivariate_representation(
   const int nchunks = (M + 31) >> 5;
   const uint32_t lastmask = (M & 31) ? ((1u << (M & 31)) - 1u) : 0xFFFFFFFFu;
   const int64_t twoK = 2 * (int64_t)K;
-  for (int idx = threadIdx.x; idx < ti * K; idx += BLOCK) {
-    const int il = idx % ti;
-    const int j = idx / ti;
+  // 2^(32 t) mod p_k with Shoup companions, [t][k], after the staged tile
+  uint2 *pw = reinterpret_cast<uint2 *>(s + (((ti * stride) + 1) & ~1));
+  for (int idx = threadIdx.x; idx < nchunks * np; idx += BLOCK) {
+    const int t = idx / np, k = idx - t * np;
+    pw[idx] = primes[k].pow32[t];
+  }
+  __syncthreads();
+  uint32_t pk[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) pk[k] = primes[k].p;
+  for (int idx = threadIdx.x; idx < (K << logTI); idx += BLOCK) {
+    const int il = idx & (TI - 1);
+    const int j = idx >> logTI;
+    if (il >= ti) continue;
     const uint32_t *row = s + il * stride;
     const uint32_t sgn = (uint32_t)((int32_t)row[nw - 1] >> 31);
     const int64_t b = (int64_t)M * j;
-    const bool neg_top = (j == K - 1) && ((get32(row, nw, sgn, b + M - 1) & 1u) != 0);
-    for (int k = 0; k < np; ++k) {
-      const PrimeDev pr = primes[k];
-      const uint2 c32 = make_uint2(pr.c32, pr.c32s);
-      const uint2 one = make_uint2(1u, pr.ones);
-      uint32_t r = 0;
-      for (int t = nchunks - 1; t >= 0; --t) {
-        uint32_t c = get32(row, nw, sgn, b + 32 * (int64_t)t);
-        if (t == nchunks - 1) c &= lastmask;
-        r = add_mod(mul_shoup(r, c32, pr.p), mul_shoup(c, one, pr.p), pr.p);
+    // unsigned value of bits [b, b + M): sum_t chunk_t 2^(32 t), reduced lazily per prime
+    uint64_t acc[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = 0;
+    for (int t = 0; t < nchunks; ++t) {
+      uint32_t c = get32(row, nw, sgn, b + 32 * (int64_t)t);
+      if (t == nchunks - 1) c &= lastmask;
+      const uint2 *pwt = pw + t * NP;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const uint2 w2 = pwt[k];
+        const uint32_t q = __umulhi(c, w2.y);
+        acc[k] += (uint32_t)(c * w2.x - q * pk[k]);   // in [0, 2p)
       }
-      if (neg_top) r = sub_mod(r, pd->pow2M[k], pr.p);
+    }
+    // the top limb is signed: subtract 2^M when its top bit (bit M K - 1) is set
+    const bool neg_top = (j == K - 1) && ((get32(row, nw, sgn, b + M - 1) & 1u) != 0);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const uint32_t p = pk[k];
+      const uint2 one = make_uint2(1u, primes[k].ones);
+      const uint2 c32 = make_uint2(primes[k].c32, primes[k].c32s);
+      uint32_t r = add_mod(mul_shoup((uint32_t)acc[k], one, p),
+                           mul_shoup((uint32_t)(acc[k] >> 32), c32, p), p);
+      if (neg_top) r = sub_mod(r, pd->pow2M[k], p);
       X[((int64_t)k * twoK + col_off + j) * L + i0 + il] = r;
     }
   }
@@ -264,9 +304,11 @@ __global__ __launch_bounds__(BLOCK) void k_bivariate_representation(
 
 // ------------------------------------------------------------------------------------
 // Strided column passes of the y-transform (outer factors of a four-step split).
-// Index i = inner + S (e + n outer); the pass transforms along e.  Forward: DIF,
-// then multiply position e (frequency k = bitrev(e)) by w_{nS}^(inner k).
-// Inverse: multiply by w_{nS}^(-inner k), then DIT.
+// Index i = inner + S (e + n outer); the pass transforms along e and leaves the
+// frequencies in natural order.  Forward: DIF, then multiply frequency k by
+// w_{nS}^(inner k).  Inverse: multiply by w_{nS}^(-inner k), then DIT.  Each thread
+// meets the frequencies k = e0, e0 + de, ... of one column, so its twiddles form a
+// geometric progression kept in Montgomery form (no table gathers).
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_col_pass(
     uint32_t *__restrict__ X, int64_t L, int32_t twoK, int32_t logn, int64_t S, int32_t logT,
@@ -285,34 +327,54 @@ __global__ __launch_bounds__(BLOCK) void k_col_pass(
   const int jc = (int)(col - (int64_t)k * twoK);
   const PrimeDev pr = primes[k];
   const uint32_t p = pr.p;
-  uint32_t *base = X + col * L + inner0 + S * (int64_t)n * outer;
+  const int64_t first = inner0 + S * (int64_t)n * outer;   // y index of (t = 0, e = 0)
+  uint32_t *base = X + col * L + first;
   const int64_t nz = inverse ? L : (jc < K ? nz_a : nz_b);
-  const int64_t first = inner0 + S * (int64_t)n * outer;   // index of (t=0, e=0)
   const int64_t m = (int64_t)n * S;
-  for (int idx = threadIdx.x; idx < (n << logT); idx += BLOCK) {
-    const int t = idx & (T - 1), e = idx >> logT;
-    const int64_t off = t + S * (int64_t)e;
-    uint32_t v = (first + off < nz) ? base[off] : 0u;
-    if (inverse) {
-      const int64_t ex = (inner0 + t) * (int64_t)bitrev(e, logn);
-      v = mul_shoup(v, heap_root(pr.hi, m, ex, p), p);
+  const int t = threadIdx.x & (T - 1);
+  const int e0 = threadIdx.x >> logT, de = BLOCK >> logT;
+  const int64_t inner = inner0 + t;
+  const uint2 *tab = inverse ? pr.hi : pr.hf;
+  const uint32_t R = pr.c32;   // 2^32 mod p
+  uint32_t cur = mul_shoup(R, heap_root(tab, m, (inner * e0) & (m - 1), p), p);
+  const uint32_t step = mul_shoup(R, heap_root(tab, m, (inner * de) & (m - 1), p), p);
+  if (!inverse) {
+    for (int idx = threadIdx.x; idx < (n << logT); idx += BLOCK) {
+      const int tt = idx & (T - 1), e = idx >> logT;
+      const int64_t off = tt + S * (int64_t)e;
+      s[idx] = (first + off < nz) ? base[off] : 0u;
     }
-    s[idx] = v;
-  }
-  __syncthreads();
-  LdsShape sh{logT, logn, 1, T, 0, 0};
-  if (inverse) lds_dit(s, sh, pr.hi, p);
-  else lds_dif(s, sh, pr.hf, p);
-  for (int idx = threadIdx.x; idx < (n << logT); idx += BLOCK) {
-    const int t = idx & (T - 1), e = idx >> logT;
-    const int64_t off = t + S * (int64_t)e;
-    uint32_t v = s[idx];
-    if (!inverse) {
-      const int64_t ex = (inner0 + t) * (int64_t)bitrev(e, logn);
-      v = mul_shoup(v, heap_root(pr.hf, m, ex, p), p);
-      base[off] = v;
-    } else if (first + off < nlimit) {
-      base[off] = v;
+    __syncthreads();
+    lds_dif(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hf, p);
+    for (int e = e0; e < n; e += de) {
+      const uint32_t v = mont_mul(s[(bitrev(e, logn) << logT) + t], cur, p, pr.pinv);
+      cur = mont_mul(cur, step, p, pr.pinv);
+      base[t + S * (int64_t)e] = v;
+    }
+  } else {
+    // eight independent loads in flight per thread, then the twiddle progression
+    for (int e = e0; e < n; e += 8 * de) {
+      uint32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ee = e + u * de;
+        v[u] = ee < n ? base[t + S * (int64_t)ee] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ee = e + u * de;
+        if (ee < n) {
+          s[(bitrev(ee, logn) << logT) + t] = mont_mul(v[u], cur, p, pr.pinv);
+          cur = mont_mul(cur, step, p, pr.pinv);
+        }
+      }
+    }
+    __syncthreads();
+    lds_dit(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hi, p);
+    for (int idx = threadIdx.x; idx < (n << logT); idx += BLOCK) {
+      const int tt = idx & (T - 1), e = idx >> logT;
+      const int64_t off = tt + S * (int64_t)e;
+      if (first + off < nlimit) base[off] = s[idx];
     }
   }
 }
@@ -370,6 +432,103 @@ __global__ __launch_bounds__(BLOCK) void k_convolve_rows(
 }
 
 // ------------------------------------------------------------------------------------
+// Same convolutions with each 2K-point x-transform held in one thread's registers
+// (K <= 32): the column's K limbs of a and of b are transformed, multiplied and
+// transformed back without touching LDS.  Twiddle offsets are compile-time.
+// ------------------------------------------------------------------------------------
+template <int LOGK>
+__device__ __forceinline__ void reg_dif(uint32_t (&x)[2 << LOGK], const uint2 *__restrict__ tw,
+                                        uint32_t p) {
+  constexpr int N2 = 2 << LOGK;
+  // first stage: the upper half is zero, so x[j + K] = x[j] theta^j (the twist)
+#pragma unroll
+  for (int j = 0; j < N2 / 2; ++j) x[j + N2 / 2] = j ? mul_shoup(x[j], tw[N2 / 2 + j], p) : x[j];
+#pragma unroll
+  for (int h = N2 / 4; h >= 1; h >>= 1) {
+#pragma unroll
+    for (int blk = 0; blk < N2; blk += 2 * h) {
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        const uint32_t u = x[blk + j], v = x[blk + j + h];
+        x[blk + j] = add_mod(u, v, p);
+        x[blk + j + h] = j ? mul_shoup(u - v + p, tw[h + j], p) : sub_mod(u, v, p);
+      }
+    }
+  }
+}
+
+template <int LOGK>
+__device__ __forceinline__ void reg_dit(uint32_t (&x)[2 << LOGK], const uint2 *__restrict__ tw,
+                                        uint32_t p) {
+  constexpr int N2 = 2 << LOGK;
+#pragma unroll
+  for (int h = 1; h < N2; h <<= 1) {
+#pragma unroll
+    for (int blk = 0; blk < N2; blk += 2 * h) {
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        const uint32_t u = x[blk + j];
+        const uint32_t v = j ? mul_shoup(x[blk + j + h], tw[h + j], p) : x[blk + j + h];
+        x[blk + j] = add_mod(u, v, p);
+        x[blk + j + h] = sub_mod(u, v, p);
+      }
+    }
+  }
+}
+
+template <int LOGK>
+__global__ __launch_bounds__(BLOCK) void k_convolve_rows_reg(
+    uint32_t *__restrict__ X, int64_t L, int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
+    const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd) {
+  extern __shared__ uint32_t s[];
+  constexpr int K = 1 << LOGK, K2 = 2 * K;
+  const int L1 = 1 << logL1, RS = L1 + 1;      // odd row stride: rows fall on distinct banks
+  const int64_t nrb = L >> logL1;
+  const int k = (int)(blockIdx.x / nrb);
+  const int64_t rb = blockIdx.x - (int64_t)k * nrb;
+  const PrimeDev pr = primes[k];
+  const uint32_t p = pr.p;
+  uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
+  const int64_t y0 = rb * L1;
+  // rows 0..K-1: limbs of a; rows K..2K-1: limbs of b
+  for (int idx = threadIdx.x; idx < (K2 << logL1); idx += BLOCK) {
+    const int j = idx >> logL1, e = idx & (L1 - 1);
+    const int64_t nz = j < K ? nz_a : nz_b;
+    s[j * RS + e] = (y0 + e < nz) ? base[(int64_t)j * L + e] : 0u;
+  }
+  __syncthreads();
+  lds_dif(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
+  const uint2 sc = pd->scale[k];
+  for (int e = threadIdx.x; e < L1; e += BLOCK) {
+    // the column of a is transformed and parked back in LDS (this thread owns column e)
+    // before b is transformed, so that at most 3K values are live in registers
+    uint32_t b[K2];
+#pragma unroll
+    for (int j = 0; j < K; ++j) b[j] = s[(K + j) * RS + e];
+    {
+      uint32_t a[K2];
+#pragma unroll
+      for (int j = 0; j < K; ++j) a[j] = s[j * RS + e];
+      reg_dif<LOGK>(a, pr.hf, p);
+#pragma unroll
+      for (int j = 0; j < K2; ++j) s[j * RS + e] = a[j];
+    }
+    reg_dif<LOGK>(b, pr.hf, p);
+#pragma unroll
+    for (int j = 0; j < K2; ++j) b[j] = mul_shoup(mont_mul(s[j * RS + e], b[j], p, pr.pinv), sc, p);
+    reg_dit<LOGK>(b, pr.hi, p);
+#pragma unroll
+    for (int j = 0; j < K2; ++j) s[j * RS + e] = b[j];
+  }
+  __syncthreads();
+  lds_dit(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hi, p);
+  for (int idx = threadIdx.x; idx < (K2 << logL1); idx += BLOCK) {
+    const int j = idx >> logL1, e = idx & (L1 - 1);
+    if (y0 + e < nlimit) base[(int64_t)j * L + e] = s[j * RS + e];
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // RecoveringProduct.  For each output coefficient i and each j < 2K-1:
 //   c_{i,j} from its np residues by CRT into (-P/2, P/2) (exact because
 //   |c_{i,j}| < d K 2^(2M) < P/4), as W-word two's complement;
@@ -384,94 +543,107 @@ __device__ __forceinline__ int fcompose(int g, int f) {   // g after f
   return r;
 }
 
-template <int WT>
+// NP = np exactly and W = NP words per CRT value (32 NP >= log2 P + 1 since every
+// prime is below 2^31).  Per workgroup: TI consecutive coefficients; S holds their
+// output words as 64-bit partial sums.
+template <int NP>
 __global__ __launch_bounds__(BLOCK) void k_recovering_product(
-    const uint32_t *__restrict__ X, int64_t L, int32_t K, int32_t M, int32_t np, int32_t W,
-    int64_t nout, int32_t nw32, int32_t wc, int32_t TI, const PrimeDev *__restrict__ primes,
-    const PlanDev *__restrict__ pd, uint64_t *__restrict__ out) {
-  extern __shared__ uint32_t s[];
-  const int J = 2 * K - 1;
+    const uint32_t *__restrict__ X, int64_t L, int32_t K, int32_t M, int64_t nout, int32_t nw32,
+    int32_t wc, int32_t logTI, const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd,
+    uint64_t *__restrict__ out) {
+  constexpr int W = NP;
+  constexpr int NPE = (NP + 1) & ~1;  // primes padded to a pair
+  extern __shared__ uint64_t S[];     // TI x nw32 partial sums, then the CRT constants
+  const int TI = 1 << logTI;
+  const int J = 2 * K - 1;            // c_{i,2K-1} = 0
   const int64_t twoK = 2 * (int64_t)K;
-  const int64_t i0 = (int64_t)blockIdx.x * TI;
+  const int64_t tile_id = xcd_tile((nout + TI - 1) >> logTI);
+  const int64_t i0 = tile_id << logTI;
+  if (i0 >= nout) return;
   const int ti = (int)min<int64_t>(TI, nout - i0);
-  uint32_t *V = s;                          // ti x J x W
-  uint32_t *rows = s + (int64_t)TI * J * W;  // 4 waves x nw32
-  // ---- CRT ----
-  for (int idx = threadIdx.x; idx < ti * J; idx += BLOCK) {
-    const int il = idx % ti, j = idx / ti;
+  // CRT constants, read by every lane: P/p_k as [u][k] (W x NPE words), P (W words),
+  // per prime (c_k Shoup pair, p_k), and 1/p_k
+  uint32_t *cq = reinterpret_cast<uint32_t *>(S + ((int64_t)nw32 << logTI));
+  uint32_t *cp = cq + NPE * W;
+  uint32_t *ci = cp + W;
+  double *cr = reinterpret_cast<double *>(ci + ((3 * NP + 1) & ~1));
+  for (int idx = threadIdx.x; idx < NPE * W; idx += BLOCK) {
+    const int u = idx / NPE, kk = idx - u * NPE;
+    cq[idx] = kk < NP ? pd->crt_q[kk][u] : 0u;
+  }
+  for (int idx = threadIdx.x; idx < W; idx += BLOCK) cp[idx] = pd->crt_p[idx];
+  for (int idx = threadIdx.x; idx < NP; idx += BLOCK) {
+    ci[3 * idx] = pd->crt_inv[idx].x;
+    ci[3 * idx + 1] = pd->crt_inv[idx].y;
+    ci[3 * idx + 2] = primes[idx].p;
+    cr[idx] = pd->crt_rcp[idx];
+  }
+  for (int idx = threadIdx.x; idx < ti * nw32; idx += BLOCK) S[idx] = 0;
+  __syncthreads();
+  // ---- CRT of each c_{i,j}, then add c_{i,j} 2^(M j) into the output words ----
+  for (int idx = threadIdx.x; idx < (J << logTI); idx += BLOCK) {
+    const int il = idx & (TI - 1), j = idx >> logTI;
+    if (il >= ti) continue;
     const int64_t i = i0 + il;
-    uint32_t acc[WT];
+    uint32_t cc[NPE];
 #pragma unroll
-    for (int u = 0; u < WT; ++u) acc[u] = 0;
+    for (int k = 0; k < NP; ++k) cc[k] = X[((int64_t)k * twoK + j) * L + i];
+    if (NPE > NP) cc[NPE - 1] = 0;
     double f = 0.0;
-    for (int k = 0; k < np; ++k) {
-      const uint32_t p = primes[k].p;
-      const uint32_t r = X[((int64_t)k * twoK + j) * L + i];
-      const uint32_t c = mul_shoup(r, pd->crt_inv[k], p);
-      f += (double)c * pd->crt_rcp[k];
-      const uint32_t *q = pd->crt_q[k];
-      uint64_t carry = 0;
 #pragma unroll
-      for (int u = 0; u < WT; ++u) {
-        if (u < W) {
-          const uint64_t t = (uint64_t)c * q[u] + acc[u] + carry;
-          acc[u] = (uint32_t)t;
-          carry = t >> 32;
-        }
-      }
+    for (int k = 0; k < NP; ++k) {
+      cc[k] = mul_shoup(cc[k], make_uint2(ci[3 * k], ci[3 * k + 1]), ci[3 * k + 2]);
+      f += (double)cc[k] * cr[k];
     }
-    // sum_k c_k P/p_k = c + t P with |c| < P/4, so t = round(sum_k c_k / p_k)
-    const uint32_t t = (uint32_t)__double2int_rn(f);
-    uint64_t borrow = 0;
+    // c_{i,j} = sum_k c_k (P/p_k) - t P, where sum_k c_k P/p_k = c + t P with |c| < P/4,
+    // so t = round(sum_k c_k / p_k).  The value is produced one 32-bit word u at a time
+    // (column sums of the products, primes taken in pairs so that each pair's sum stays
+    // below 2^64, a signed carry between words) and its shifted digits are added into
+    // the output words at once.
+    const uint32_t tq = (uint32_t)__double2int_rn(f);
+    const int64_t bit = (int64_t)M * j;
+    const int64_t q0 = bit >> 5;
+    const int sh = (int)(bit & 31);
+    uint64_t *Si = S + (int64_t)il * nw32;
+    int64_t carry = 0;
+    uint32_t prev = 0;
 #pragma unroll
-    for (int u = 0; u < WT; ++u) {
-      if (u < W) {
-        const uint64_t sub = (uint64_t)t * pd->crt_p[u] + borrow;
-        const uint32_t lo = (uint32_t)sub;
-        borrow = (sub >> 32) + (acc[u] < lo ? 1 : 0);
-        acc[u] = acc[u] - lo;
+    for (int u = 0; u < W; ++u) {
+      uint64_t lo = 0;
+      uint32_t hi = 0;
+#pragma unroll
+      for (int k = 0; k < NPE; k += 2) {
+        const uint2 qq = *reinterpret_cast<const uint2 *>(cq + u * NPE + k);
+        uint64_t pr2 = (uint64_t)cc[k + 1] * qq.y;
+        pr2 += (uint64_t)cc[k] * qq.x;
+        lo += pr2;
+        hi += lo < pr2 ? 1u : 0u;
       }
+      const uint64_t tp = (uint64_t)tq * cp[u];
+      const uint64_t D = lo - tp;
+      int64_t H = (int64_t)hi - (lo < tp ? 1 : 0);
+      const uint64_t D2 = D + (uint64_t)carry;
+      H += (D2 < D ? 1 : 0) - (carry < 0 ? 1 : 0);
+      const uint32_t wd = (uint32_t)D2;                 // word u of c_{i,j}, two's complement
+      carry = (int64_t)((uint64_t)H << 32) + (int64_t)(D2 >> 32);
+      const uint32_t dgt = sh ? ((wd << sh) | (prev >> (32 - sh))) : wd;
+      prev = wd;
+      if (q0 + u < nw32 && dgt) atomicAdd((unsigned long long *)&Si[q0 + u], (unsigned long long)dgt);
     }
-    uint32_t *dst = V + ((int64_t)il * J + j) * W;
-#pragma unroll
-    for (int u = 0; u < WT; ++u)
-      if (u < W) dst[u] = acc[u];
+    const int64_t top = sh ? (int64_t)((int32_t)prev >> (32 - sh)) : -(int64_t)(prev >> 31);
+    if (q0 + W < nw32 && top) atomicAdd((unsigned long long *)&Si[q0 + W], (unsigned long long)top);
   }
   __syncthreads();
-  // ---- evaluation at 2^M and carries, one wave per coefficient ----
+  // ---- carries, one wave per coefficient ----
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint32_t *row = rows + wave * nw32;
   const int per = (nw32 + 63) >> 6;
   const int w_lo = min(lane * per, nw32), w_hi = min(w_lo + per, nw32);
-  const int64_t topbits = 32 * (int64_t)W;
   for (int il = wave; il < ti; il += BLOCK / 64) {
-    const uint32_t *Vi = V + (int64_t)il * J * W;
+    uint64_t *Si = S + (int64_t)il * nw32;
     int64_t carry = 0;
     for (int w = w_lo; w < w_hi; ++w) {
-      const int64_t wb = 32 * (int64_t)w;
-      int64_t S = 0;
-      const int64_t jl = wb - topbits > 0 ? (wb - topbits) / M : 0;
-      const int64_t jh = min<int64_t>(J - 1, (wb + 31) / M);
-      for (int64_t j = jl; j <= jh; ++j) {
-        const uint32_t *v = Vi + j * W;
-        const int64_t pos = wb - (int64_t)M * j;
-        uint32_t win = 0;
-        if (pos >= topbits || pos <= -32) {
-          win = 0;
-        } else if (pos >= 0) {
-          const int q = (int)(pos >> 5), sh = (int)(pos & 31);
-          const uint32_t lo = v[q];
-          const uint32_t hi = (q + 1 < W) ? v[q + 1] : 0u;
-          win = sh ? ((lo >> sh) | (hi << (32 - sh))) : lo;
-        } else {
-          win = v[0] << (int)(-pos);
-        }
-        S += win;
-        if ((int32_t)v[W - 1] < 0 && ((topbits + (int64_t)M * j) >> 5) == w)
-          S -= (int64_t)1 << ((topbits + (int64_t)M * j) & 31);
-      }
-      const int64_t tsum = S + carry;
-      row[w] = (uint32_t)tsum;
+      const int64_t tsum = (int64_t)Si[w] + carry;
+      Si[w] = (uint32_t)tsum;
       carry = tsum >> 32;
     }
     // pass the local carry to the next lane and normalise
@@ -480,11 +652,11 @@ __global__ __launch_bounds__(BLOCK) void k_recovering_product(
     int64_t x = cin;
     bool allz = true, allo = true;
     for (int w = w_lo; w < w_hi; ++w) {
-      const int64_t tsum = (int64_t)row[w] + x;
-      row[w] = (uint32_t)tsum;
+      const int64_t tsum = (int64_t)Si[w] + x;
+      Si[w] = (uint32_t)tsum;
       x = tsum >> 32;
-      allz = allz && row[w] == 0u;
-      allo = allo && row[w] == 0xFFFFFFFFu;
+      allz = allz && (uint32_t)tsum == 0u;
+      allo = allo && (uint32_t)tsum == 0xFFFFFFFFu;
     }
     int code;
     if (w_lo >= w_hi) {
@@ -500,24 +672,20 @@ __global__ __launch_bounds__(BLOCK) void k_recovering_product(
       const int other = __shfl_up(code, off, 64);
       if (lane >= off) code = fcompose(code, other);
     }
-    int prev = __shfl_up(code, 1, 64);
-    int y = lane == 0 ? 0 : fapply(prev, 0);
+    const int prevc = __shfl_up(code, 1, 64);
+    int y = lane == 0 ? 0 : fapply(prevc, 0);
     for (int w = w_lo; w < w_hi && y != 0; ++w) {
-      const int64_t tsum = (int64_t)row[w] + y;
-      row[w] = (uint32_t)tsum;
+      const int64_t tsum = (int64_t)Si[w] + y;
+      Si[w] = (uint32_t)tsum;
       y = (int)(tsum >> 32);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const uint64_t fill = ((int32_t)row[nw32 - 1] < 0) ? ~0ull : 0ull;
+    const uint64_t fill = ((int32_t)(uint32_t)Si[nw32 - 1] < 0) ? ~0ull : 0ull;
     uint64_t *o = out + (i0 + il) * (int64_t)wc;
-    for (int u = lane; u < wc; u += 64) {
-      o[u] = (2 * u + 1 < nw32) ? ((uint64_t)row[2 * u] | ((uint64_t)row[2 * u + 1] << 32)) : fill;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (int u = lane; u < wc; u += 64)
+      o[u] = (2 * u + 1 < nw32) ? ((Si[2 * u] & 0xFFFFFFFFull) | (Si[2 * u + 1] << 32)) : fill;
   }
 }
 
@@ -530,15 +698,30 @@ static inline int ilog2(int64_t x) {
   return r;
 }
 
+#define ZPM_NP_CASES(X_) \
+  X_(1) X_(2) X_(3) X_(4) X_(5) X_(6) X_(7) X_(8) X_(9) X_(10) X_(11) X_(12) X_(13) X_(14) \
+  X_(15) X_(16) X_(17) X_(18) X_(19) X_(20) X_(21) X_(22) X_(23) X_(24) X_(26) X_(28) X_(30) \
+  X_(32) X_(36) X_(40) X_(44) X_(48)
+
 hipError_t launch_convert_in(const Plan &pl, const DevState &ds, const uint64_t *src, int64_t d,
                              int32_t N, int32_t col_off, hipStream_t st) {
   const int w = (N + 63) / 64;
-  const int TI = pl.ti_in;
-  const int64_t blocks = (d + TI - 1) / TI;
-  const size_t lds = sizeof(uint32_t) * (size_t)TI * (2 * w + 1);
-  hipLaunchKernelGGL(k_bivariate_representation, dim3((unsigned)blocks), dim3(BLOCK), lds, st, src,
-                     d, N, w, pl.K, pl.M, pl.np, ds.X, (int64_t)1 << pl.logL, col_off, TI, ds.primes,
-                     ds.plan);
+  const int logTI = pl.log_ti_in;
+  const int64_t blocks = xcd_grid((d + (1 << logTI) - 1) >> logTI);
+  const int nchunks = (pl.M + 31) >> 5;
+  const size_t lds = sizeof(uint32_t) * ((((size_t)1 << logTI) * (2 * w + 1) + 1) & ~(size_t)1) +
+                     sizeof(uint2) * (size_t)nchunks * pl.np;
+#define ZPM_CIN(NP_)                                                                          \
+  case NP_:                                                                                   \
+    hipLaunchKernelGGL(k_bivariate_representation<NP_>, dim3((unsigned)blocks), dim3(BLOCK),  \
+                       lds, st, src, d, N, w, pl.K, pl.M, pl.np, ds.X, (int64_t)1 << pl.logL,  \
+                       col_off, logTI, ds.primes, ds.plan);                                   \
+    break;
+  switch (pl.np) {
+    ZPM_NP_CASES(ZPM_CIN)
+    default: return hipErrorInvalidValue;
+  }
+#undef ZPM_CIN
   return hipGetLastError();
 }
 
@@ -562,11 +745,26 @@ hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, h
 hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st) {
   const int64_t L = (int64_t)1 << pl.logL;
   const int64_t blocks = (int64_t)pl.np * (L >> pl.logL1);
-  const size_t lds = sizeof(uint32_t) * (size_t)4 * pl.K << pl.logL1;
   const bool direct = pl.ncol == 0;
+  const int64_t nz_a = direct ? pl.da : L, nz_b = direct ? pl.db : L, nl = direct ? pl.nout : L;
+  if (pl.conv_reg) {
+    const size_t lds = sizeof(uint32_t) * (size_t)(2 * pl.K) * (((size_t)1 << pl.logL1) + 1);
+#define ZPM_CONV(LK_)                                                                           \
+  hipLaunchKernelGGL(k_convolve_rows_reg<LK_>, dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, \
+                     L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan)
+    switch (ilog2(pl.K)) {
+      case 1: ZPM_CONV(1); break;
+      case 2: ZPM_CONV(2); break;
+      case 3: ZPM_CONV(3); break;
+      case 4: ZPM_CONV(4); break;
+      default: ZPM_CONV(5); break;
+    }
+#undef ZPM_CONV
+    return hipGetLastError();
+  }
+  const size_t lds = sizeof(uint32_t) * (size_t)4 * pl.K << pl.logL1;
   hipLaunchKernelGGL(k_convolve_rows, dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, L, pl.K,
-                     ilog2(pl.K), pl.logL1, direct ? pl.da : L, direct ? pl.db : L,
-                     direct ? pl.nout : L, ds.primes, ds.plan);
+                     ilog2(pl.K), pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan);
   return hipGetLastError();
 }
 
@@ -574,20 +772,20 @@ hipError_t launch_recover(const Plan &pl, const DevState &ds, uint64_t *out, int
                           hipStream_t st) {
   const int64_t L = (int64_t)1 << pl.logL;
   const int nw32 = 2 * ((pl.nout_bits + 63) / 64);
-  const int TI = pl.ti_out;
-  const int64_t blocks = (pl.nout + TI - 1) / TI;
-  const size_t lds = sizeof(uint32_t) * ((size_t)TI * (2 * pl.K - 1) * pl.W + 4 * (size_t)nw32);
-#define ZPM_REC(WT_)                                                                              \
-  hipLaunchKernelGGL(k_recovering_product<WT_>, dim3((unsigned)blocks), dim3(BLOCK), lds, st,    \
-                     ds.X, L, pl.K, pl.M, pl.np, pl.W, pl.nout, nw32, wc, TI, ds.primes, ds.plan, \
-                     out)
-  if (pl.W <= 4) ZPM_REC(4);
-  else if (pl.W <= 8) ZPM_REC(8);
-  else if (pl.W <= 12) ZPM_REC(12);
-  else if (pl.W <= 16) ZPM_REC(16);
-  else if (pl.W <= 24) ZPM_REC(24);
-  else if (pl.W <= 32) ZPM_REC(32);
-  else ZPM_REC(48);
+  const int logTI = pl.log_ti_out;
+  const int64_t blocks = xcd_grid((pl.nout + (1 << logTI) - 1) >> logTI);
+  const size_t lds = sizeof(uint64_t) * ((size_t)nw32 << logTI) +
+                     sizeof(uint32_t) * ((size_t)((pl.np + 1) & ~1) * pl.np + pl.np + ((3 * pl.np + 1) & ~1)) +
+                     sizeof(double) * pl.np;
+#define ZPM_REC(NP_)                                                                           \
+  case NP_:                                                                                    \
+    hipLaunchKernelGGL(k_recovering_product<NP_>, dim3((unsigned)blocks), dim3(BLOCK), lds, st, \
+                       ds.X, L, pl.K, pl.M, pl.nout, nw32, wc, logTI, ds.primes, ds.plan, out); \
+    break;
+  switch (pl.np) {
+    ZPM_NP_CASES(ZPM_REC)
+    default: return hipErrorInvalidValue;
+  }
 #undef ZPM_REC
   return hipGetLastError();
 }

@@ -41,10 +41,16 @@ int32_t out_bits(int64_t da, int32_t Na, int64_t db, int32_t Nb) {
 // into strided column passes of length <= 2^10 each.
 static bool split_y(Plan &pl) {
   const int logK = ceil_log2(pl.K);
-  // the fused kernel holds two 2K x L1 tiles: 4 K L1 <= LDS_WORDS
   int logcap = 0;
-  while ((4ll << (logK + logcap + 1)) <= LDS_WORDS) ++logcap;
-  if ((4ll << (logK + logcap)) > LDS_WORDS) return false;     // K too large even for L1 = 1
+  pl.conv_reg = pl.K <= 32 ? 1 : 0;
+  if (pl.conv_reg) {
+    // 2K rows of L1 + 1 words (x-transforms in registers)
+    while (2ll * pl.K * ((1ll << (logcap + 1)) + 1) <= LDS_WORDS) ++logcap;
+  } else {
+    // two 2K x L1 tiles: 4 K L1 <= LDS_WORDS
+    while ((4ll << (logK + logcap + 1)) <= LDS_WORDS) ++logcap;
+    if ((4ll << (logK + logcap)) > LDS_WORDS) return false;     // K too large even for L1 = 1
+  }
   pl.logL1 = std::min(pl.logL, logcap);
   int rest = pl.logL - pl.logL1;
   int npass = (rest + 9) / 10;
@@ -66,19 +72,24 @@ static bool split_y(Plan &pl) {
 
 static bool finish(Plan &pl) {
   pl.log2P = bitlen_product(pl.np);
-  pl.W = (pl.log2P + 1 + 31) / 32;
+  pl.W = pl.np;                      // >= (log2P + 1) / 32: every prime is below 2^31
   if (pl.W > MAXW) return false;
   const int wa = (pl.Na + 63) / 64, wb = (pl.Nb + 63) / 64;
   const int wmax = std::max(wa, wb);
-  int ti = 64;
-  while (ti > 1 && ti * (2 * wmax + 1) > LDS_WORDS) ti >>= 1;
-  if (ti * (2 * wmax + 1) > LDS_WORDS) return false;
-  pl.ti_in = ti;
+  // convert-in: stage TI coefficients (2w+1 words each) in LDS
+  const int pw_words = 2 * ((pl.M + 31) / 32) * pl.np + 2;   // staged 2^(32t) mod p table
+  int lt = 6;
+  while (lt > 0 && ((2 * wmax + 1) << lt) + pw_words > LDS_WORDS) --lt;
+  if (((2 * wmax + 1) << lt) + pw_words > LDS_WORDS) return false;
+  pl.log_ti_in = lt;
+  // recovery: TI coefficients x nw32 64-bit partial sums (<= 48 KiB), about 256-1024 items
   const int64_t J = 2 * (int64_t)pl.K - 1;
   const int64_t nw32 = 2 * (int64_t)((pl.nout_bits + 63) / 64);
-  int64_t room = LDS_WORDS - 4 * nw32;
-  if (room < J * pl.W) return false;
-  pl.ti_out = (int32_t)std::min<int64_t>(64, room / (J * pl.W));
+  lt = 6;
+  const int64_t crt_words = (int64_t)(pl.np + 1) * pl.W + pl.W + 5 * pl.np + 2;
+  while (lt > 0 && ((nw32 << lt) * 2 > 12288 || (J << lt) > 1024)) --lt;
+  if ((nw32 << lt) * 2 + crt_words > LDS_WORDS) return false;
+  pl.log_ti_out = lt;
   pl.ws_words = (int64_t)pl.np * 2 * pl.K << pl.logL;
   return true;
 }
@@ -135,12 +146,15 @@ bool make_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, 
     if ((double)d * K > 4e18) continue;
     int np = 0;
     if (np_force) {
-      if (np_force > MAXNP || !primes_cover(np_force, d, K, pl.M)) continue;
+      if (np_force > MAXNP || np_compiled(np_force) != np_force ||
+          !primes_cover(np_force, d, K, pl.M))
+        continue;
       np = np_force;
     } else {
       for (int t = 1; t <= MAXNP; ++t)
         if (primes_cover(t, d, K, pl.M)) { np = t; break; }
       if (!np) continue;
+      np = np_compiled(np);
     }
     pl.np = np;
     if (!split_y(pl) || !finish(pl)) continue;

@@ -15,6 +15,16 @@ constexpr int BLOCK = 256;              // threads per workgroup of every kernel
 constexpr int LDS_WORDS = 16384;        // 64 KiB of LDS staging per workgroup
 constexpr int MAX_COL_PASSES = 4;
 
+// Prime counts with compiled kernels (per-prime loops are unrolled at compile time);
+// a plan's prime count is rounded up to one of these.
+constexpr int NP_SET[] = {1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 11, 12, 13, 14, 15, 16,
+                          17, 18, 19, 20, 21, 22, 23, 24, 26, 28, 30, 32, 36, 40, 44, 48};
+inline int np_compiled(int np) {
+  for (int v : NP_SET)
+    if (v >= np) return v;
+  return 0;
+}
+
 // Per-prime constants resident on the device.
 struct PrimeDev {
   uint32_t p;          // the prime
@@ -24,6 +34,7 @@ struct PrimeDev {
   uint32_t pad[3];
   const uint2 *hf;     // forward heap: hf[h + j] = (w^j, shoup) with w a primitive 2h-th root
   const uint2 *hi;     // inverse heap: hi[h + j] = (w^-j, shoup)
+  const uint2 *pow32;  // pow32[t] = (2^(32 t) mod p, shoup)
 };
 
 // Per-plan constants (np primes, transform sizes) resident on the device.
@@ -53,13 +64,14 @@ struct Plan {
   int32_t K, M, np;
   int32_t logL;        // L = 2^logL >= da + db - 1, the cyclic length along y
   int32_t logL1;       // innermost y factor handled inside the fused convolution kernel
+  int32_t conv_reg;    // 1: x-transforms in registers (K <= 32), 0: in LDS
   int32_t ncol;        // number of strided column passes (outermost first)
   ColPass col[MAX_COL_PASSES];
   int32_t col_tile[MAX_COL_PASSES];  // inner indices per workgroup of each column pass
-  int32_t W;           // 32-bit words of each CRT value c_{i,j}
+  int32_t W;           // 32-bit words of each CRT value c_{i,j} (= np)
   int32_t log2P;       // floor(log2(P)) + 1
-  int32_t ti_in;       // coefficients per workgroup in convert-in
-  int32_t ti_out;      // coefficients per workgroup in recovery
+  int32_t log_ti_in;   // log2 coefficients per workgroup in convert-in
+  int32_t log_ti_out;  // log2 coefficients per workgroup in recovery
   int64_t ws_words;    // workspace size in 32-bit words: np * 2K * L
   double cost;         // planner's cost estimate (arbitrary units)
 };
