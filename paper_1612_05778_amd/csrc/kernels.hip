@@ -192,6 +192,26 @@ __device__ __forceinline__ int bitrev(int x, int logn) {
   return logn ? (int)(__brev((unsigned)x) >> (32 - logn)) : 0;
 }
 
+// Element-wise staging between global memory and LDS: for idx = threadIdx.x, +BLOCK, ...
+// below `total`, put(idx, load(idx)).  U loads are issued before their results are
+// used, so a thread keeps U global reads in flight instead of one.
+template <int U, typename T, typename LD, typename ST>
+__device__ __forceinline__ void staged(int total, LD load, ST put) {
+  for (int i0 = threadIdx.x; i0 < total; i0 += U * BLOCK) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = i0 + u * BLOCK;
+      v[u] = idx < total ? load(idx) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = i0 + u * BLOCK;
+      if (idx < total) put(idx, v[u]);
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // BivariateRepresentation: coefficient i of a (N-bit two's complement, w words) is
 // split into K limbs of M bits, a_i = sum_j a_{i,j} 2^(M j) (Section 2).  Lower limbs
@@ -232,12 +252,11 @@ __global__ __launch_bounds__(BLOCK) void k_bivariate_representation(
   const int stride = nw + 1;
   // stage the tile's words (one contiguous block of ti * w words)
   const uint64_t *tile = src + i0 * w;
-  for (int idx = threadIdx.x; idx < ti * w; idx += BLOCK) {
+  staged<8, uint64_t>(ti * w, [&](int idx) { return tile[idx]; }, [&](int idx, uint64_t v) {
     const int il = idx / w, u = idx - il * w;
-    const uint64_t v = tile[idx];
     s[il * stride + 2 * u] = (uint32_t)v;
     s[il * stride + 2 * u + 1] = (uint32_t)(v >> 32);
-  }
+  });
   __syncthreads();
   // sign-extend from bit N-1: bits >= N are not part of the value
   const int tq = (N - 1) >> 5, tb = (N - 1) & 31;
@@ -339,11 +358,11 @@ __global__ __launch_bounds__(BLOCK) void k_col_pass(
   uint32_t cur = mul_shoup(R, heap_root(tab, m, (inner * e0) & (m - 1), p), p);
   const uint32_t step = mul_shoup(R, heap_root(tab, m, (inner * de) & (m - 1), p), p);
   if (!inverse) {
-    for (int idx = threadIdx.x; idx < (n << logT); idx += BLOCK) {
+    staged<8, uint32_t>(n << logT, [&](int idx) {
       const int tt = idx & (T - 1), e = idx >> logT;
       const int64_t off = tt + S * (int64_t)e;
-      s[idx] = (first + off < nz) ? base[off] : 0u;
-    }
+      return (first + off < nz) ? base[off] : 0u;
+    }, [&](int idx, uint32_t v) { s[idx] = v; });
     __syncthreads();
     lds_dif(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hf, p);
     for (int e = e0; e < n; e += de) {
@@ -371,11 +390,11 @@ __global__ __launch_bounds__(BLOCK) void k_col_pass(
     }
     __syncthreads();
     lds_dit(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hi, p);
-    for (int idx = threadIdx.x; idx < (n << logT); idx += BLOCK) {
+    staged<8, uint32_t>(n << logT, [&](int idx) { return s[idx]; }, [&](int idx, uint32_t v) {
       const int tt = idx & (T - 1), e = idx >> logT;
       const int64_t off = tt + S * (int64_t)e;
-      if (first + off < nlimit) base[off] = s[idx];
-    }
+      if (first + off < nlimit) base[off] = v;
+    });
   }
 }
 
@@ -406,14 +425,14 @@ __global__ __launch_bounds__(BLOCK) void k_convolve_rows(
   uint32_t *B = s + twoK * L1;          // 2K rows x L1
   uint32_t *base = X + (int64_t)k * twoK * L + rb * L1;
   const int64_t y0 = rb * L1;
-  for (int idx = threadIdx.x; idx < (K << logL1); idx += BLOCK) {
+  staged<8, uint32_t>(K << logL1, [&](int idx) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
-    const int64_t i = y0 + e;
-    A[idx] = (i < nz_a) ? base[(int64_t)j * L + e] : 0u;
-    B[idx] = (i < nz_b) ? base[(int64_t)(K + j) * L + e] : 0u;
-    A[(K << logL1) + idx] = 0u;
-    B[(K << logL1) + idx] = 0u;
-  }
+    return (y0 + e < nz_a) ? base[(int64_t)j * L + e] : 0u;
+  }, [&](int idx, uint32_t v) { A[idx] = v; A[(K << logL1) + idx] = 0u; });
+  staged<8, uint32_t>(K << logL1, [&](int idx) {
+    const int j = idx >> logL1, e = idx & (L1 - 1);
+    return (y0 + e < nz_b) ? base[(int64_t)(K + j) * L + e] : 0u;
+  }, [&](int idx, uint32_t v) { B[idx] = v; B[(K << logL1) + idx] = 0u; });
   __syncthreads();
   // innermost y factor on the K limb rows of both operands
   lds_dif(s, LdsShape{logK, logL1, L1, 1, twoK * L1, 1}, pr.hf, p);
@@ -425,10 +444,10 @@ __global__ __launch_bounds__(BLOCK) void k_convolve_rows(
   __syncthreads();
   lds_dit(s, LdsShape{logL1, logK + 1, 1, L1, 0, 0}, pr.hi, p);
   lds_dit(s, LdsShape{logK + 1, logL1, L1, 1, 0, 0}, pr.hi, p);
-  for (int idx = threadIdx.x; idx < (twoK << logL1); idx += BLOCK) {
+  staged<8, uint32_t>(twoK << logL1, [&](int idx) { return A[idx]; }, [&](int idx, uint32_t v) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
-    if (y0 + e < nlimit) base[(int64_t)j * L + e] = A[idx];
-  }
+    if (y0 + e < nlimit) base[(int64_t)j * L + e] = v;
+  });
 }
 
 // ------------------------------------------------------------------------------------
@@ -491,11 +510,11 @@ __global__ __launch_bounds__(BLOCK) void k_convolve_rows_reg(
   uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
   const int64_t y0 = rb * L1;
   // rows 0..K-1: limbs of a; rows K..2K-1: limbs of b
-  for (int idx = threadIdx.x; idx < (K2 << logL1); idx += BLOCK) {
+  staged<8, uint32_t>(K2 << logL1, [&](int idx) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
     const int64_t nz = j < K ? nz_a : nz_b;
-    s[j * RS + e] = (y0 + e < nz) ? base[(int64_t)j * L + e] : 0u;
-  }
+    return (y0 + e < nz) ? base[(int64_t)j * L + e] : 0u;
+  }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
   __syncthreads();
   lds_dif(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
   const uint2 sc = pd->scale[k];
@@ -522,10 +541,12 @@ __global__ __launch_bounds__(BLOCK) void k_convolve_rows_reg(
   }
   __syncthreads();
   lds_dit(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hi, p);
-  for (int idx = threadIdx.x; idx < (K2 << logL1); idx += BLOCK) {
+  staged<8, uint32_t>(K2 << logL1, [&](int idx) {
+    return s[(idx >> logL1) * RS + (idx & (L1 - 1))];
+  }, [&](int idx, uint32_t v) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
-    if (y0 + e < nlimit) base[(int64_t)j * L + e] = s[j * RS + e];
-  }
+    if (y0 + e < nlimit) base[(int64_t)j * L + e] = v;
+  });
 }
 
 // ------------------------------------------------------------------------------------

@@ -15,6 +15,7 @@
 // the remark of Section 4 that the word-prime variant gains from a large M.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "nt.hpp"
@@ -39,6 +40,17 @@ int32_t out_bits(int64_t da, int32_t Na, int64_t db, int32_t Nb) {
 
 // Split of the y-transform: innermost factor L1 inside the fused kernel, the rest
 // into strided column passes of length <= 2^10 each.
+// Widest column tile of a strided pass (inner indices per workgroup); ZPM_COL_TILE
+// overrides the default of 16 (64-byte runs; more workgroups per CU beat longer runs).
+static int64_t col_tile_max() {
+  static const int64_t v = [] {
+    const char *e = std::getenv("ZPM_COL_TILE");
+    const long x = e ? std::atol(e) : 0;
+    return (int64_t)(x >= 1 && x <= 64 && !(x & (x - 1)) ? x : 16);
+  }();
+  return v;
+}
+
 static bool split_y(Plan &pl) {
   const int logK = ceil_log2(pl.K);
   int logcap = 0;
@@ -64,7 +76,7 @@ static bool split_y(Plan &pl) {
     S >>= take;
     pl.col[c].S = S;
     // inner indices per workgroup: T * n <= LDS_WORDS, T <= S, T <= 64
-    int64_t T = std::min<int64_t>(S, std::min<int64_t>(64, LDS_WORDS >> take));
+    int64_t T = std::min<int64_t>(S, std::min<int64_t>(col_tile_max(), LDS_WORDS >> take));
     pl.col_tile[c] = (int32_t)std::max<int64_t>(T, 1);
   }
   return true;
