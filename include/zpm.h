@@ -86,6 +86,9 @@ int zpm_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t 
  * primitive 2^21-th root of unity modulo it.  ZPM_EINVAL if k is out of range. */
 int zpm_prime(int32_t k, uint32_t *p, uint32_t *root);
 
+/* Compute units and LDS limits (bytes per workgroup, per CU) of a HIP device. */
+int zpm_device_limits(int device, int32_t *ncu, int64_t *lds_per_block, int64_t *lds_per_cu);
+
 /* Create a context on HIP device `device`.  Tables and workspace are allocated
  * on first use and grown as needed. */
 int zpm_create(zpm_ctx **out, int device);
@@ -105,6 +108,41 @@ int zpm_mul(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint6
 int zpm_mul_ex(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
                int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t K, int32_t np,
                int32_t stop_after, uint32_t *ws_out, void *stream);
+
+/* Batched products: many independent products of uneven degree and bit size in
+ * one call.  Each job is one product c = a * b with the encoding and ownership rules
+ * of zpm_mul; jobs must not write overlapping outputs.  Every product gets its own
+ * plan (from zpm_tune's table when one covers its size class, otherwise the cost
+ * model restricted to at most 16 primes and K <= 16 for the register x-transform).
+ * The products run level by level: level s is the s-th stage of every product, and
+ * the tiles of one level that share a stage kind and a compiled variant run in one
+ * launch (a few launches per level, whatever the number of products).  Stream-ordered
+ * like zpm_mul.  ZPM_BATCH_GRAPH captures the whole sequence (descriptor upload and
+ * launches) in a HIP graph and replays it when the same job array is passed again.
+ * ZPM_BATCH_PERSISTENT (all levels in one persistent launch) is not available:
+ * the call returns ZPM_EUNSUPPORTED. */
+typedef struct zpm_job {
+  const uint64_t *a;
+  int64_t da;
+  int32_t Na;
+  const uint64_t *b;
+  int64_t db;
+  int32_t Nb;
+  uint64_t *c;
+  int32_t wc;
+} zpm_job;
+#define ZPM_BATCH_GRAPH 1
+#define ZPM_BATCH_PERSISTENT 2
+int zpm_mul_batch(zpm_ctx *ctx, const zpm_job *jobs, int64_t n, int32_t flags, void *stream);
+/* zpm_mul_batch with every product forced to limb count K (0 = choose). */
+int zpm_mul_batch_ex(zpm_ctx *ctx, const zpm_job *jobs, int64_t n, int32_t flags, int32_t K,
+                     void *stream);
+/* Host-only: the launches zpm_mul_batch would make (no device work; the pointers in
+ * jobs may be NULL).  Sets *nlaunch and writes up to cap launches, 6 int64 each:
+ * level, stage kind (0 convert-in, 1 forward column pass, 2 row convolutions,
+ * 3 inverse column pass, 4 recovery), compiled variant, products, blocks, LDS bytes. */
+int zpm_batch_schedule(const zpm_job *jobs, int64_t n, int32_t K, int64_t *nlaunch, int64_t *out,
+                       int64_t cap);
 
 /* Per-kernel timing.  Between zpm_profile_begin and zpm_profile_end every kernel
  * the context launches is bracketed by HIP events recorded on its stream.

@@ -17,6 +17,11 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -m paper_1612_05778_amd.build` "
         "(hipcc, gfx950). There is no CPU fallback.")
 
+# One HIP runtime per process: torch ships its own libamdhip64, and the library must
+# bind to that same copy (same SONAME).  Loading libzpm.so first would pull in the
+# system runtime and leave torch without a usable device.
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 
 c_i32, c_i64, c_u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
@@ -70,6 +75,24 @@ zpm_mul_ex = _sig("zpm_mul_ex", ctypes.c_int,
 zpm_sync = _sig("zpm_sync", ctypes.c_int, [c_vp, c_vp])
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("a", c_vp), ("da", c_i64), ("Na", c_i32), ("b", c_vp), ("db", c_i64),
+                ("Nb", c_i32), ("c", c_vp), ("wc", c_i32)]
+
+
+ZPM_BATCH_GRAPH = 1
+zpm_mul_batch = _sig("zpm_mul_batch", ctypes.c_int, [c_vp, ctypes.POINTER(Job), c_i64, c_i32, c_vp])
+zpm_mul_batch_ex = _sig("zpm_mul_batch_ex", ctypes.c_int,
+                        [c_vp, ctypes.POINTER(Job), c_i64, c_i32, c_i32, c_vp])
+ZPM_BATCH_PERSISTENT = 2
+zpm_batch_schedule = _sig("zpm_batch_schedule", ctypes.c_int,
+                          [ctypes.POINTER(Job), c_i64, c_i32, ctypes.POINTER(c_i64),
+                           ctypes.POINTER(c_i64), c_i64])
+zpm_device_limits = _sig("zpm_device_limits", ctypes.c_int,
+                         [ctypes.c_int, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64),
+                          ctypes.POINTER(c_i64)])
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", c_i64), ("total_ms", ctypes.c_double)]
 
@@ -80,7 +103,8 @@ zpm_profile_end = _sig("zpm_profile_end", ctypes.c_int,
 
 EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
            "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync",
-           "zpm_profile_begin", "zpm_profile_end"]
+           "zpm_profile_begin", "zpm_profile_end", "zpm_mul_batch", "zpm_mul_batch_ex",
+           "zpm_device_limits", "zpm_batch_schedule"]
 
 
 class ZpmError(RuntimeError):

@@ -26,6 +26,13 @@ def plan(da: int, Na: int, db: int, Nb: int, K: int = 0, np: int = 0) -> dict:
     return info.as_dict()
 
 
+def device_limits(device: int = 0) -> dict:
+    ncu, lb, lc = nat.c_i32(), nat.c_i64(), nat.c_i64()
+    nat.check(nat.zpm_device_limits(device, ctypes.byref(ncu), ctypes.byref(lb), ctypes.byref(lc)),
+              "zpm_device_limits")
+    return {"cus": ncu.value, "lds_per_block": lb.value, "lds_per_cu": lc.value}
+
+
 def prime(k: int) -> tuple[int, int]:
     p, r = nat.c_u32(), nat.c_u32()
     nat.check(nat.zpm_prime(k, ctypes.byref(p), ctypes.byref(r)), "zpm_prime")
@@ -109,6 +116,39 @@ class Context:
         L = 1 << info["log2_L"]
         w = ws.to(torch.int64) & 0xFFFFFFFF
         return w.view(info["np"], 2 * info["K"], L), info
+
+    def mul_batch(self, items, graph: bool = False, K: int = 0, stream=None, outs=None):
+        """Products of many (a, Na, b, Nb) in one persistent launch.
+
+        items: list of (a, Na, b, Nb) with a, b int64 CUDA tensors as for mul.
+        Returns the list of output tensors (allocated unless ``outs`` is given).
+        The Job array is kept on the context so that a graph replay sees the same bytes.
+        """
+        n = len(items)
+        jobs = (nat.Job * max(n, 1))()
+        res = []
+        for i, (a, Na, b, Nb) in enumerate(items):
+            da = _check_operand(a, Na, "a")
+            db = _check_operand(b, Nb, "b")
+            nout = da + db - 1 if (da and db) else 0
+            wc = out_words(da, Na, db, Nb) if nout else 1
+            o = outs[i] if outs is not None else torch.empty((nout, wc), dtype=torch.int64,
+                                                            device=a.device)
+            if outs is not None:
+                wc = o.shape[1] if o.dim() == 2 else wc
+            res.append(o)
+            jobs[i].a, jobs[i].da, jobs[i].Na = a.data_ptr(), da, Na
+            jobs[i].b, jobs[i].db, jobs[i].Nb = b.data_ptr(), db, Nb
+            jobs[i].c, jobs[i].wc = (o.data_ptr() if nout else None), wc
+        self._jobs = jobs
+        flags = nat.ZPM_BATCH_GRAPH if graph else 0
+        st = _stream_handle(stream)
+        if K:
+            rc = nat.zpm_mul_batch_ex(self._h, jobs, n, flags, K, st)
+        else:
+            rc = nat.zpm_mul_batch(self._h, jobs, n, flags, st)
+        nat.check(rc, "zpm_mul_batch")
+        return res
 
     def profile_begin(self) -> None:
         nat.check(nat.zpm_profile_begin(self._h), "zpm_profile_begin")

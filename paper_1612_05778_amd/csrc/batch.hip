@@ -1,0 +1,173 @@
+// Batched products as grouped launches.
+//
+// Every stage of every product is cut into the same tiles the per-stage kernels use.
+// A batch runs level by level (level s = the s-th stage of each product); within a
+// level, tiles of the same stage kind and the same compiled variant (prime count or
+// limb count) go into one launch, where block b finds its product and tile from a
+// list of segments.  Launch order on the stream carries the dependencies between
+// levels, so no workgroup ever waits for another.
+#include <hip/hip_runtime.h>
+
+#include "batch.hpp"
+#include "stages.hpp"
+
+namespace zpm {
+
+__device__ __forceinline__ int find_seg(const GroupSeg *__restrict__ segs, int32_t nseg, int64_t b) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].start <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int NP>
+__global__ __launch_bounds__(BLOCK) void kg_convert(const JobDev *__restrict__ jobs,
+                                                    const GroupSeg *__restrict__ segs, int32_t nseg,
+                                                    const PrimeDev *__restrict__ primes) {
+  extern __shared__ uint32_t s[];
+  const GroupSeg g = segs[find_seg(segs, nseg, blockIdx.x)];
+  const JobDev &jb = jobs[g.job];
+  const int64_t tile = (int64_t)blockIdx.x - g.start;
+  const bool ob = tile >= jb.tiles_a;      // tiles of a first, then tiles of b
+  const int32_t N = ob ? jb.Nb : jb.Na;
+  body_convert_in<NP>(s, ob ? tile - jb.tiles_a : tile, ob ? jb.b : jb.a, ob ? jb.db : jb.da, N,
+                      (N + 63) / 64, jb.K, jb.M, NP, jb.X, jb.L, ob ? jb.K : 0, jb.log_ti_in,
+                      primes, jb.plan);
+}
+
+template <int NP>
+__global__ __launch_bounds__(BLOCK) void kg_recover(const JobDev *__restrict__ jobs,
+                                                    const GroupSeg *__restrict__ segs, int32_t nseg,
+                                                    const PrimeDev *__restrict__ primes) {
+  extern __shared__ uint64_t S[];
+  const GroupSeg g = segs[find_seg(segs, nseg, blockIdx.x)];
+  const JobDev &jb = jobs[g.job];
+  body_recover<NP>(S, (int64_t)blockIdx.x - g.start, jb.X, jb.L, jb.K, jb.M, jb.nout, jb.nw32,
+                   jb.wc, jb.log_ti_out, primes, jb.plan, jb.c);
+}
+
+__global__ __launch_bounds__(BLOCK) void kg_col(const JobDev *__restrict__ jobs,
+                                                const GroupSeg *__restrict__ segs, int32_t nseg,
+                                                int32_t inverse, const PrimeDev *__restrict__ primes) {
+  extern __shared__ uint32_t s[];
+  const GroupSeg g = segs[find_seg(segs, nseg, blockIdx.x)];
+  const JobDev &jb = jobs[g.job];
+  const int c = g.pass;
+  const bool outer = c == 0;
+  const int64_t L = jb.L;
+  body_col_pass(s, (int64_t)blockIdx.x - g.start, jb.X, L, 2 * jb.K, jb.col_logn[c], jb.col_S[c],
+                jb.col_logT[c], (outer && !inverse) ? jb.da : L, (outer && !inverse) ? jb.db : L,
+                jb.K, (outer && inverse) ? jb.nout : L, inverse, primes);
+}
+
+template <int LOGK>
+__global__ __launch_bounds__(BLOCK) void kg_convolve_reg(const JobDev *__restrict__ jobs,
+                                                         const GroupSeg *__restrict__ segs,
+                                                         int32_t nseg,
+                                                         const PrimeDev *__restrict__ primes) {
+  extern __shared__ uint32_t s[];
+  const GroupSeg g = segs[find_seg(segs, nseg, blockIdx.x)];
+  const JobDev &jb = jobs[g.job];
+  const int64_t L = jb.L;
+  const bool direct = jb.ncol == 0;
+  body_convolve_reg<LOGK>(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.logL1, direct ? jb.da : L,
+                          direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan);
+}
+
+__global__ __launch_bounds__(BLOCK) void kg_convolve(const JobDev *__restrict__ jobs,
+                                                     const GroupSeg *__restrict__ segs, int32_t nseg,
+                                                     const PrimeDev *__restrict__ primes) {
+  extern __shared__ uint32_t s[];
+  const GroupSeg g = segs[find_seg(segs, nseg, blockIdx.x)];
+  const JobDev &jb = jobs[g.job];
+  const int64_t L = jb.L;
+  const bool direct = jb.ncol == 0;
+  int logK = 0;
+  while ((1 << logK) < jb.K) ++logK;
+  body_convolve(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.K, logK, jb.logL1,
+                direct ? jb.da : L, direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan);
+}
+
+hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *segs,
+                        const PrimeDev *primes, hipStream_t st) {
+  if (gr.blocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)gr.blocks), blk(BLOCK);
+  const GroupSeg *sg = segs + gr.seg0;
+  const int32_t ns = gr.nseg;
+  switch (gr.kind) {
+    case SK_CONVERT:
+      switch (gr.variant) {
+#define ZPM_G(NP_) \
+  case NP_: hipLaunchKernelGGL(kg_convert<NP_>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+        ZPM_G(1) ZPM_G(2) ZPM_G(3) ZPM_G(4) ZPM_G(5) ZPM_G(6) ZPM_G(7) ZPM_G(8)
+        ZPM_G(9) ZPM_G(10) ZPM_G(11) ZPM_G(12) ZPM_G(13) ZPM_G(14) ZPM_G(15) ZPM_G(16)
+#undef ZPM_G
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    case SK_RECOVER:
+      switch (gr.variant) {
+#define ZPM_G(NP_) \
+  case NP_: hipLaunchKernelGGL(kg_recover<NP_>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+        ZPM_G(1) ZPM_G(2) ZPM_G(3) ZPM_G(4) ZPM_G(5) ZPM_G(6) ZPM_G(7) ZPM_G(8)
+        ZPM_G(9) ZPM_G(10) ZPM_G(11) ZPM_G(12) ZPM_G(13) ZPM_G(14) ZPM_G(15) ZPM_G(16)
+#undef ZPM_G
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    case SK_COL_FWD:
+    case SK_COL_INV:
+      hipLaunchKernelGGL(kg_col, grid, blk, gr.lds, st, jobs, sg, ns, gr.kind == SK_COL_INV ? 1 : 0,
+                         primes);
+      break;
+    case SK_CONVOLVE:
+      switch (gr.variant) {
+        case 1: hipLaunchKernelGGL(kg_convolve_reg<1>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+        case 2: hipLaunchKernelGGL(kg_convolve_reg<2>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+        case 3: hipLaunchKernelGGL(kg_convolve_reg<3>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+        case 4: hipLaunchKernelGGL(kg_convolve_reg<4>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+        case 0: hipLaunchKernelGGL(kg_convolve, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t stage_lds(const Plan &pl, int kind, int pass) {
+  switch (kind) {
+    case SK_CONVERT: {
+      const int w = (std::max(pl.Na, pl.Nb) + 63) / 64;
+      const int nchunks = (pl.M + 31) >> 5;
+      return sizeof(uint32_t) * (((((size_t)1 << pl.log_ti_in) * (2 * w + 1)) + 1) & ~(size_t)1) +
+             sizeof(uint2) * (size_t)nchunks * pl.np;
+    }
+    case SK_COL_FWD:
+    case SK_COL_INV:
+      return sizeof(uint32_t) * ((size_t)pl.col_tile[pass] << pl.col[pass].logn);
+    case SK_CONVOLVE:
+      return pl.conv_reg ? sizeof(uint32_t) * (size_t)(2 * pl.K) * (((size_t)1 << pl.logL1) + 1)
+                         : sizeof(uint32_t) * (size_t)4 * pl.K << pl.logL1;
+    case SK_RECOVER: {
+      const int nw32 = 2 * ((pl.nout_bits + 63) / 64);
+      return sizeof(uint64_t) * ((size_t)nw32 << pl.log_ti_out) +
+             sizeof(uint32_t) * ((size_t)((pl.np + 1) & ~1) * pl.np + pl.np + ((3 * pl.np + 1) & ~1)) +
+             sizeof(double) * pl.np;
+    }
+    default:
+      return 0;
+  }
+}
+
+bool batch_supports(const Plan &pl) {
+  if (pl.np < 1 || pl.np > 16) return false;
+  if (pl.conv_reg && pl.K > 16) return false;
+  return true;
+}
+
+}  // namespace zpm

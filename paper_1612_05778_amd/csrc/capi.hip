@@ -138,8 +138,12 @@ int Ctx::prepare(const Plan &pl, DevState *ds) {
 }
 
 Ctx::~Ctx() {
+  if (!primes) return;   // a host-only context (planning) owns no device resources
   (void)hipSetDevice(device);
   (void)hipDeviceSynchronize();
+  batch_eager.release();
+  batch_graph.release();
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
   if (ws) (void)hipFree(ws);
   if (heaps) (void)hipFree(heaps);
   if (primes) (void)hipFree(primes);
@@ -186,6 +190,22 @@ int zpm_prime(int32_t k, uint32_t *p, uint32_t *root) {
   if (k >= (int)T.size()) return ZPM_EINVAL;
   *p = T[k].p;
   *root = T[k].root;
+  return ZPM_OK;
+}
+
+int zpm_device_limits(int device, int32_t *ncu, int64_t *lds_per_block, int64_t *lds_per_cu) {
+  if (!ncu || !lds_per_block || !lds_per_cu) return ZPM_EINVAL;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return ZPM_EDEVICE;
+  *ncu = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+    return ZPM_EDEVICE;
+  *lds_per_block = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) !=
+      hipSuccess)
+    return ZPM_EDEVICE;
+  *lds_per_cu = v;
   return ZPM_OK;
 }
 

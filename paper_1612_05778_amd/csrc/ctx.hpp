@@ -5,11 +5,43 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
+#include "../../include/zpm.h"
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "zpm_internal.hpp"
 
 namespace zpm {
+
+// Host-side schedule of a batch (see Ctx::schedule_batch).
+struct BatchHost {
+  std::vector<Plan> plans;       // per job of the call (only live jobs are planned)
+  std::vector<JobDev> jobs;      // live jobs; X = workspace offset in words
+  std::vector<int32_t> job_plan; // live job -> index into plans
+  std::vector<GroupSeg> segs;    // segments of all launches, launch after launch
+  std::vector<Group> groups;     // launches in order
+  int64_t ws_words = 0, H = 2, TP = 64;
+  int npmax = 1;
+};
+
+// Device and pinned host buffers of one batch, plus its captured graph.
+struct BatchState {
+  BatchHost host;
+  uint32_t *ws = nullptr;
+  int64_t ws_cap = 0;
+  JobDev *jobs_h = nullptr, *jobs_d = nullptr;
+  int64_t jobs_hcap = 0, jobs_dcap = 0;
+  GroupSeg *segs_h = nullptr, *segs_d = nullptr;
+  int64_t segs_hcap = 0, segs_dcap = 0;
+  int32_t nseg = 0;
+  int64_t nlive = 0;
+  hipEvent_t upload_done = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t key = 0;
+  static uint64_t hash(const zpm_job *jobs, int64_t n, int32_t K_force);
+  void release();
+};
 
 struct Ctx {
   int device = 0;
@@ -24,12 +56,20 @@ struct Ctx {
   int64_t ws_words = 0;
   std::mutex mu;
   Profiler prof;
+  std::map<int32_t, int32_t> tuned;            // size class -> K chosen by zpm_tune
+  BatchState batch_eager, batch_graph;
+  hipStream_t capture_stream = nullptr;        // graph capture only (default priority)
 
   int ensure_tables(int np, int64_t H, int64_t TP);
   int plan_consts(const Plan &pl, PlanDev **out);
   int ensure_ws(int64_t words);
   int get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np, Plan *out);
   int prepare(const Plan &pl, DevState *ds);
+  int get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, Plan *out);
+  int schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHost &bh);
+  int build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState &bs);
+  int enqueue_batch(BatchState &bs, hipStream_t st);
+  int mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_force, hipStream_t st);
   ~Ctx();
 };
 

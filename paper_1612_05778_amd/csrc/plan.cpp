@@ -51,10 +51,10 @@ static int64_t col_tile_max() {
   return v;
 }
 
-static bool split_y(Plan &pl) {
+static bool split_y(Plan &pl, int reg_k_max) {
   const int logK = ceil_log2(pl.K);
   int logcap = 0;
-  pl.conv_reg = pl.K <= 32 ? 1 : 0;
+  pl.conv_reg = pl.K <= reg_k_max ? 1 : 0;
   if (pl.conv_reg) {
     // 2K rows of L1 + 1 words (x-transforms in registers)
     while (2ll * pl.K * ((1ll << (logcap + 1)) + 1) <= LDS_WORDS) ++logcap;
@@ -129,8 +129,15 @@ static double model_cost(const Plan &pl) {
   return t_alu + t_mem + 4e-6 * (4 + 3 * pl.ncol);
 }
 
+int32_t size_class(int64_t da, int32_t Na, int64_t db, int32_t Nb) {
+  const int32_t N = std::max(std::max(Na, Nb), 2);
+  return (ceil_log2(da + db - 1) << 8) | ceil_log2((N + 31) / 32);
+}
+
 bool make_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, int32_t np_force,
-               Plan &out, const char **why) {
+               Plan &out, const char **why, const PlanLimits *lim) {
+  static const PlanLimits deflim;
+  if (!lim) lim = &deflim;
   static const char *dummy;
   if (!why) why = &dummy;
   *why = nullptr;
@@ -145,6 +152,7 @@ bool make_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, 
   for (int logK = 1; logK <= 20; ++logK) {
     const int32_t K = 1 << logK;
     if (K_force && K != K_force) continue;
+    if (K > lim->k_max) break;
     if (!K_force && K > 2 * (int64_t)N) break;     // limbs of 2 bits or less: no point going further
     if (logK + 1 > LOG2_ROOT_ORDER) break;
     Plan pl;
@@ -163,13 +171,14 @@ bool make_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, 
         continue;
       np = np_force;
     } else {
-      for (int t = 1; t <= MAXNP; ++t)
+      for (int t = 1; t <= lim->np_max; ++t)
         if (primes_cover(t, d, K, pl.M)) { np = t; break; }
       if (!np) continue;
       np = np_compiled(np);
+      if (np > lim->np_max) continue;
     }
     pl.np = np;
-    if (!split_y(pl) || !finish(pl)) continue;
+    if (!split_y(pl, lim->reg_k_max) || !finish(pl)) continue;
     pl.cost = model_cost(pl);
     if (!found || pl.cost < best.cost) { best = pl; found = true; }
   }

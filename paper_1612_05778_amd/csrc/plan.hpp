@@ -6,8 +6,16 @@
 namespace zpm {
 
 int32_t out_bits(int64_t da, int32_t Na, int64_t db, int32_t Nb);
+struct PlanLimits {
+  int32_t np_max = MAXNP;    // largest prime count
+  int32_t k_max = 1 << 20;   // largest K
+  int32_t reg_k_max = 32;    // largest K for the register x-transform kernel
+};
+
 // K_force / np_force: 0 = choose; otherwise the plan must use that value.
 bool make_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, int32_t np_force,
-               Plan &out, const char **why);
+               Plan &out, const char **why, const PlanLimits *lim = nullptr);
+// Class of a product for tuning: (ceil log2 of da + db - 1, ceil log2 of ceil(max N / 32)).
+int32_t size_class(int64_t da, int32_t Na, int64_t db, int32_t Nb);
 
 }  // namespace zpm

@@ -1,0 +1,693 @@
+// Device bodies of the pipeline stages, shared by the per-stage kernels and by the
+// persistent batch kernel.  Each body processes one tile (one workgroup's share) and
+// takes its LDS buffer and tile index as arguments.  See kernels.hip for the layout
+// of the workspace and the order of the stages.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "zpm_internal.hpp"
+
+namespace zpm {
+
+// ------------------------------------------------------------------------------------
+// modular arithmetic on 32-bit words, p < 2^31
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t p) {
+  uint32_t s = a + b;
+  return min(s, s - p);
+}
+__device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t p) {
+  uint32_t d = a - b;
+  return min(d, d + p);
+}
+// x * w mod p for a constant w with Shoup companion ws = floor(w 2^32 / p); any x < 2^32.
+__device__ __forceinline__ uint32_t mul_shoup(uint32_t x, uint2 w, uint32_t p) {
+  uint32_t q = __umulhi(x, w.y);
+  uint32_t r = x * w.x - q * p;   // in [0, 2p)
+  return min(r, r - p);
+}
+// a * b * 2^-32 mod p (Montgomery), a, b < p.
+__device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
+  uint32_t lo = a * b, hi = __umulhi(a, b);
+  uint32_t m = lo * pinv;
+  uint32_t mp = __umulhi(m, p);
+  uint32_t r = hi - mp;
+  return hi < mp ? r + p : r;
+}
+// w_m^e from a heap table (tab[m/2 + e] = w_m^e for e < m/2), any e in [0, m).
+__device__ __forceinline__ uint2 heap_root(const uint2 *__restrict__ tab, int64_t m, int64_t e, uint32_t p) {
+  const int64_t half = m >> 1;
+  if (e < half) return tab[half + e];
+  uint2 w = tab[e];            // w_m^(e - m/2) = -w_m^e
+  return make_uint2(p - w.x, ~w.y);
+}
+
+// ------------------------------------------------------------------------------------
+// radix-2^R butterfly groups on transforms held in LDS.
+// Transform t (t < ntr = 2^logntr, times nops operand copies) has element e at
+// s[(t & (ntr-1)) * ts + (t >> logntr) * off2 + e * es].
+// ------------------------------------------------------------------------------------
+struct LdsShape {
+  int logntr, logn, ts, es, off2, logops;
+};
+
+__device__ __forceinline__ int lds_base(const LdsShape &sh, int t) {
+  return (t & ((1 << sh.logntr) - 1)) * sh.ts + (t >> sh.logntr) * sh.off2;
+}
+
+// DIF (Gentleman-Sande) stages with half-sizes h0, h0/2, ..., h0/2^(R-1); output of the
+// whole transform is in bit-reversed order.
+template <int R>
+__device__ void dif_group(uint32_t *s, const LdsShape &sh, int logh0, const uint2 *__restrict__ tw,
+                          uint32_t p) {
+  constexpr int NR = 1 << R;
+  const int loghl = logh0 - (R - 1);
+  const int hl = 1 << loghl;
+  const int lgpt = sh.logn - R;                       // groups per transform (log)
+  const int total = 1 << (sh.logntr + sh.logops + lgpt);
+  // lanes run over transforms when those are adjacent in LDS, or when the element
+  // stride inside the group is small (which would put a wave on few banks)
+  const bool tfast = sh.ts < sh.es || ((sh.ts & 1) && hl * sh.es < 16 && sh.logntr + sh.logops >= 4);
+  for (int g = threadIdx.x; g < total; g += BLOCK) {
+    int t, q;
+    if (tfast) {
+      t = g & ((1 << (sh.logntr + sh.logops)) - 1);
+      q = g >> (sh.logntr + sh.logops);
+    } else {
+      q = g & ((1 << lgpt) - 1);
+      t = g >> lgpt;
+    }
+    const int j = q & (hl - 1);
+    const int blk = q >> loghl;
+    const int base = lds_base(sh, t) + ((blk << (logh0 + 1)) + j) * sh.es;
+    const int step = hl * sh.es;
+    uint32_t x[NR];
+#pragma unroll
+    for (int m = 0; m < NR; ++m) x[m] = s[base + m * step];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int half = NR >> (i + 1);
+      const int hsz = 1 << (logh0 - i);
+#pragma unroll
+      for (int m = 0; m < NR; ++m) {
+        if (m & half) continue;
+        const uint2 w = tw[hsz + j + (m & (half - 1)) * hl];
+        const uint32_t u = x[m], v = x[m + half];
+        x[m] = add_mod(u, v, p);
+        x[m + half] = mul_shoup(u - v + p, w, p);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < NR; ++m) s[base + m * step] = x[m];
+  }
+}
+
+// DIT (Cooley-Tukey) stages with half-sizes h0, 2 h0, ..., h0 2^(R-1); input in
+// bit-reversed order, output natural.
+template <int R>
+__device__ void dit_group(uint32_t *s, const LdsShape &sh, int logh0, const uint2 *__restrict__ tw,
+                          uint32_t p) {
+  constexpr int NR = 1 << R;
+  const int h0 = 1 << logh0;
+  const int loghr = logh0 + R - 1;
+  const int lgpt = sh.logn - R;
+  const int total = 1 << (sh.logntr + sh.logops + lgpt);
+  const bool tfast = sh.ts < sh.es || ((sh.ts & 1) && h0 * sh.es < 16 && sh.logntr + sh.logops >= 4);
+  for (int g = threadIdx.x; g < total; g += BLOCK) {
+    int t, q;
+    if (tfast) {
+      t = g & ((1 << (sh.logntr + sh.logops)) - 1);
+      q = g >> (sh.logntr + sh.logops);
+    } else {
+      q = g & ((1 << lgpt) - 1);
+      t = g >> lgpt;
+    }
+    const int j = q & (h0 - 1);
+    const int blk = q >> logh0;
+    const int base = lds_base(sh, t) + ((blk << (loghr + 1)) + j) * sh.es;
+    const int step = h0 * sh.es;
+    uint32_t x[NR];
+#pragma unroll
+    for (int m = 0; m < NR; ++m) x[m] = s[base + m * step];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int half = 1 << i;
+      const int hsz = h0 << i;
+#pragma unroll
+      for (int m = 0; m < NR; ++m) {
+        if (m & half) continue;
+        const uint2 w = tw[hsz + j + (m & (half - 1)) * h0];
+        const uint32_t u = x[m];
+        const uint32_t v = mul_shoup(x[m + half], w, p);
+        x[m] = add_mod(u, v, p);
+        x[m + half] = sub_mod(u, v, p);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < NR; ++m) s[base + m * step] = x[m];
+  }
+}
+
+// Full forward transform (all logn stages); caller synchronises before and after.
+__device__ void lds_dif(uint32_t *s, const LdsShape &sh, const uint2 *__restrict__ tw, uint32_t p) {
+  int st = sh.logn;
+  while (st > 0) {
+    const int r = st >= 3 ? 3 : st;
+    if (r == 3) dif_group<3>(s, sh, st - 1, tw, p);
+    else if (r == 2) dif_group<2>(s, sh, st - 1, tw, p);
+    else dif_group<1>(s, sh, st - 1, tw, p);
+    st -= r;
+    __syncthreads();
+  }
+}
+
+__device__ void lds_dit(uint32_t *s, const LdsShape &sh, const uint2 *__restrict__ tw, uint32_t p) {
+  int done = 0;
+  while (done < sh.logn) {
+    const int left = sh.logn - done;
+    const int r = left >= 3 ? 3 : left;
+    if (r == 3) dit_group<3>(s, sh, done, tw, p);
+    else if (r == 2) dit_group<2>(s, sh, done, tw, p);
+    else dit_group<1>(s, sh, done, tw, p);
+    done += r;
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int bitrev(int x, int logn) {
+  return logn ? (int)(__brev((unsigned)x) >> (32 - logn)) : 0;
+}
+
+// Element-wise staging between global memory and LDS: for idx = threadIdx.x, +BLOCK, ...
+// below `total`, put(idx, load(idx)).  U loads are issued before their results are
+// used, so a thread keeps U global reads in flight instead of one.
+template <int U, typename T, typename LD, typename ST>
+__device__ __forceinline__ void staged(int total, LD load, ST put) {
+  for (int i0 = threadIdx.x; i0 < total; i0 += U * BLOCK) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = i0 + u * BLOCK;
+      v[u] = idx < total ? load(idx) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = i0 + u * BLOCK;
+      if (idx < total) put(idx, v[u]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// BivariateRepresentation: coefficient i of a (N-bit two's complement, w words) is
+// split into K limbs of M bits, a_i = sum_j a_{i,j} 2^(M j) (Section 2).  Lower limbs
+// are unsigned M-bit fields; the top limb is the signed top field, so that the split
+// needs no carries.  Each limb is reduced mod every prime.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t get32(const uint32_t *row, int nw, uint32_t sgn, int64_t pos) {
+  const int64_t q = pos >> 5;
+  const int sh = (int)(pos & 31);
+  const uint32_t lo = q < nw ? row[q] : sgn;
+  if (!sh) return lo;
+  const uint32_t hi = q + 1 < nw ? row[q + 1] : sgn;
+  return (lo >> sh) | (hi << (32 - sh));
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run
+// of tiles so that neighbouring tiles share that XCD's L2.  The grid has 8 * chunk
+// blocks; tiles >= ntiles are idle.
+__device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
+  const int64_t chunk = (ntiles + 7) >> 3;
+  return (int64_t)(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+}
+
+// NP = np exactly: per-prime accumulators stay in registers, loops fully unrolled.
+template <int NP>
+__device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__restrict__ src,
+                                int64_t d, int32_t N, int32_t w, int32_t K, int32_t M, int32_t np,
+                                uint32_t *__restrict__ X, int64_t L, int32_t col_off, int32_t logTI,
+                                const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd) {
+  const int TI = 1 << logTI;
+  const int64_t i0 = tile_id << logTI;
+  if (i0 >= d) return;
+  const int ti = (int)min<int64_t>(TI, d - i0);
+  const int nw = 2 * w;
+  const int stride = nw + 1;
+  // stage the tile's words (one contiguous block of ti * w words)
+  const uint64_t *tile = src + i0 * w;
+  staged<8, uint64_t>(ti * w, [&](int idx) { return tile[idx]; }, [&](int idx, uint64_t v) {
+    const int il = idx / w, u = idx - il * w;
+    s[il * stride + 2 * u] = (uint32_t)v;
+    s[il * stride + 2 * u + 1] = (uint32_t)(v >> 32);
+  });
+  __syncthreads();
+  // sign-extend from bit N-1: bits >= N are not part of the value
+  const int tq = (N - 1) >> 5, tb = (N - 1) & 31;
+  for (int il = threadIdx.x; il < ti; il += BLOCK) {
+    uint32_t *row = s + il * stride;
+    const uint32_t top = row[tq];
+    const uint32_t sgn = ((top >> tb) & 1u) ? 0xFFFFFFFFu : 0u;
+    if (tb < 31) {
+      const uint32_t keep = (2u << tb) - 1u;
+      row[tq] = (top & keep) | (sgn & ~keep);
+    }
+    for (int q = tq + 1; q < nw; ++q) row[q] = sgn;
+  }
+  __syncthreads();
+  const int nchunks = (M + 31) >> 5;
+  const uint32_t lastmask = (M & 31) ? ((1u << (M & 31)) - 1u) : 0xFFFFFFFFu;
+  const int64_t twoK = 2 * (int64_t)K;
+  // 2^(32 t) mod p_k with Shoup companions, [t][k], after the staged tile
+  uint2 *pw = reinterpret_cast<uint2 *>(s + (((ti * stride) + 1) & ~1));
+  for (int idx = threadIdx.x; idx < nchunks * np; idx += BLOCK) {
+    const int t = idx / np, k = idx - t * np;
+    pw[idx] = primes[k].pow32[t];
+  }
+  __syncthreads();
+  uint32_t pk[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) pk[k] = primes[k].p;
+  for (int idx = threadIdx.x; idx < (K << logTI); idx += BLOCK) {
+    const int il = idx & (TI - 1);
+    const int j = idx >> logTI;
+    if (il >= ti) continue;
+    const uint32_t *row = s + il * stride;
+    const uint32_t sgn = (uint32_t)((int32_t)row[nw - 1] >> 31);
+    const int64_t b = (int64_t)M * j;
+    // unsigned value of bits [b, b + M): sum_t chunk_t 2^(32 t), reduced lazily per prime
+    uint64_t acc[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = 0;
+    for (int t = 0; t < nchunks; ++t) {
+      uint32_t c = get32(row, nw, sgn, b + 32 * (int64_t)t);
+      if (t == nchunks - 1) c &= lastmask;
+      const uint2 *pwt = pw + t * NP;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const uint2 w2 = pwt[k];
+        const uint32_t q = __umulhi(c, w2.y);
+        acc[k] += (uint32_t)(c * w2.x - q * pk[k]);   // in [0, 2p)
+      }
+    }
+    // the top limb is signed: subtract 2^M when its top bit (bit M K - 1) is set
+    const bool neg_top = (j == K - 1) && ((get32(row, nw, sgn, b + M - 1) & 1u) != 0);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const uint32_t p = pk[k];
+      const uint2 one = make_uint2(1u, primes[k].ones);
+      const uint2 c32 = make_uint2(primes[k].c32, primes[k].c32s);
+      uint32_t r = add_mod(mul_shoup((uint32_t)acc[k], one, p),
+                           mul_shoup((uint32_t)(acc[k] >> 32), c32, p), p);
+      if (neg_top) r = sub_mod(r, pd->pow2M[k], p);
+      X[((int64_t)k * twoK + col_off + j) * L + i0 + il] = r;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Strided column passes of the y-transform (outer factors of a four-step split).
+// Index i = inner + S (e + n outer); the pass transforms along e and leaves the
+// frequencies in natural order.  Forward: DIF, then multiply frequency k by
+// w_{nS}^(inner k).  Inverse: multiply by w_{nS}^(-inner k), then DIT.  Each thread
+// meets the frequencies k = e0, e0 + de, ... of one column, so its twiddles form a
+// geometric progression kept in Montgomery form (no table gathers).
+// ------------------------------------------------------------------------------------
+__device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
+                              int32_t twoK, int32_t logn, int64_t S, int32_t logT, int64_t nz_a,
+                              int64_t nz_b, int32_t K, int64_t nlimit, int32_t inverse,
+                              const PrimeDev *__restrict__ primes) {
+  const int n = 1 << logn, T = 1 << logT;
+  const int64_t inner_tiles = S >> logT;
+  const int64_t outers = L / ((int64_t)n * S);
+  const int64_t tiles = inner_tiles * outers;
+  const int64_t col = bid / tiles;
+  const int64_t tile = bid - col * tiles;
+  const int64_t outer = tile / inner_tiles;
+  const int64_t inner0 = (tile - outer * inner_tiles) << logT;
+  const int k = (int)(col / twoK);
+  const int jc = (int)(col - (int64_t)k * twoK);
+  const PrimeDev pr = primes[k];
+  const uint32_t p = pr.p;
+  const int64_t first = inner0 + S * (int64_t)n * outer;   // y index of (t = 0, e = 0)
+  uint32_t *base = X + col * L + first;
+  const int64_t nz = inverse ? L : (jc < K ? nz_a : nz_b);
+  const int64_t m = (int64_t)n * S;
+  const int t = threadIdx.x & (T - 1);
+  const int e0 = threadIdx.x >> logT, de = BLOCK >> logT;
+  const int64_t inner = inner0 + t;
+  const uint2 *tab = inverse ? pr.hi : pr.hf;
+  const uint32_t R = pr.c32;   // 2^32 mod p
+  uint32_t cur = mul_shoup(R, heap_root(tab, m, (inner * e0) & (m - 1), p), p);
+  const uint32_t step = mul_shoup(R, heap_root(tab, m, (inner * de) & (m - 1), p), p);
+  if (!inverse) {
+    staged<8, uint32_t>(n << logT, [&](int idx) {
+      const int tt = idx & (T - 1), e = idx >> logT;
+      const int64_t off = tt + S * (int64_t)e;
+      return (first + off < nz) ? base[off] : 0u;
+    }, [&](int idx, uint32_t v) { s[idx] = v; });
+    __syncthreads();
+    lds_dif(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hf, p);
+    for (int e = e0; e < n; e += de) {
+      const uint32_t v = mont_mul(s[(bitrev(e, logn) << logT) + t], cur, p, pr.pinv);
+      cur = mont_mul(cur, step, p, pr.pinv);
+      base[t + S * (int64_t)e] = v;
+    }
+  } else {
+    // eight independent loads in flight per thread, then the twiddle progression
+    for (int e = e0; e < n; e += 8 * de) {
+      uint32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ee = e + u * de;
+        v[u] = ee < n ? base[t + S * (int64_t)ee] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ee = e + u * de;
+        if (ee < n) {
+          s[(bitrev(ee, logn) << logT) + t] = mont_mul(v[u], cur, p, pr.pinv);
+          cur = mont_mul(cur, step, p, pr.pinv);
+        }
+      }
+    }
+    __syncthreads();
+    lds_dit(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hi, p);
+    staged<8, uint32_t>(n << logT, [&](int idx) { return s[idx]; }, [&](int idx, uint32_t v) {
+      const int tt = idx & (T - 1), e = idx >> logT;
+      const int64_t off = tt + S * (int64_t)e;
+      if (first + off < nlimit) base[off] = v;
+    });
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// The two convolutions along x for one prime and one block of L1 consecutive y
+// positions.  Per y-frequency the limbs a_{.,j} (j < K) are zero-padded to 2K and
+// transformed with DIF of length 2K: the first stage multiplies row j by theta^j
+// (theta a primitive 2K-th root, the twist of NegacyclicConvolution) and the two
+// halves then hold the cyclic (mod x^K - 1) and twisted (mod x^K + 1) spectra.
+// After the pointwise product the DIT inverse of length 2K undoes both transforms;
+// its last stage applies theta^-j (untwist) and forms c- + c+ and c- - c+, which
+// after the 1/(2K) in the scale constant are c_{i,j} and c_{i,j+K} (Section 2,
+// C+ and C- through Relation (recoveringC)).
+// ------------------------------------------------------------------------------------
+__device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
+                              int32_t K, int32_t logK, int32_t logL1, int64_t nz_a, int64_t nz_b,
+                              int64_t nlimit, const PrimeDev *__restrict__ primes,
+                              const PlanDev *__restrict__ pd) {
+  const int L1 = 1 << logL1;
+  const int64_t nrb = L >> logL1;
+  const int k = (int)(bid / nrb);
+  const int64_t rb = bid - (int64_t)k * nrb;
+  const PrimeDev pr = primes[k];
+  const uint32_t p = pr.p;
+  const int twoK = 2 * K;
+  uint32_t *A = s;                      // 2K rows x L1
+  uint32_t *B = s + twoK * L1;          // 2K rows x L1
+  uint32_t *base = X + (int64_t)k * twoK * L + rb * L1;
+  const int64_t y0 = rb * L1;
+  staged<8, uint32_t>(K << logL1, [&](int idx) {
+    const int j = idx >> logL1, e = idx & (L1 - 1);
+    return (y0 + e < nz_a) ? base[(int64_t)j * L + e] : 0u;
+  }, [&](int idx, uint32_t v) { A[idx] = v; A[(K << logL1) + idx] = 0u; });
+  staged<8, uint32_t>(K << logL1, [&](int idx) {
+    const int j = idx >> logL1, e = idx & (L1 - 1);
+    return (y0 + e < nz_b) ? base[(int64_t)(K + j) * L + e] : 0u;
+  }, [&](int idx, uint32_t v) { B[idx] = v; B[(K << logL1) + idx] = 0u; });
+  __syncthreads();
+  // innermost y factor on the K limb rows of both operands
+  lds_dif(s, LdsShape{logK, logL1, L1, 1, twoK * L1, 1}, pr.hf, p);
+  // x: 2K-point transforms down the L1 columns of both operands
+  lds_dif(s, LdsShape{logL1, logK + 1, 1, L1, twoK * L1, 1}, pr.hf, p);
+  const uint2 sc = pd->scale[k];
+  for (int idx = threadIdx.x; idx < (twoK << logL1); idx += BLOCK)
+    A[idx] = mul_shoup(mont_mul(A[idx], B[idx], p, pr.pinv), sc, p);
+  __syncthreads();
+  lds_dit(s, LdsShape{logL1, logK + 1, 1, L1, 0, 0}, pr.hi, p);
+  lds_dit(s, LdsShape{logK + 1, logL1, L1, 1, 0, 0}, pr.hi, p);
+  staged<8, uint32_t>(twoK << logL1, [&](int idx) { return A[idx]; }, [&](int idx, uint32_t v) {
+    const int j = idx >> logL1, e = idx & (L1 - 1);
+    if (y0 + e < nlimit) base[(int64_t)j * L + e] = v;
+  });
+}
+
+// ------------------------------------------------------------------------------------
+// Same convolutions with each 2K-point x-transform held in one thread's registers
+// (K <= 32): the column's K limbs of a and of b are transformed, multiplied and
+// transformed back without touching LDS.  Twiddle offsets are compile-time.
+// ------------------------------------------------------------------------------------
+template <int LOGK>
+__device__ __forceinline__ void reg_dif(uint32_t (&x)[2 << LOGK], const uint2 *__restrict__ tw,
+                                        uint32_t p) {
+  constexpr int N2 = 2 << LOGK;
+  // first stage: the upper half is zero, so x[j + K] = x[j] theta^j (the twist)
+#pragma unroll
+  for (int j = 0; j < N2 / 2; ++j) x[j + N2 / 2] = j ? mul_shoup(x[j], tw[N2 / 2 + j], p) : x[j];
+#pragma unroll
+  for (int h = N2 / 4; h >= 1; h >>= 1) {
+#pragma unroll
+    for (int blk = 0; blk < N2; blk += 2 * h) {
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        const uint32_t u = x[blk + j], v = x[blk + j + h];
+        x[blk + j] = add_mod(u, v, p);
+        x[blk + j + h] = j ? mul_shoup(u - v + p, tw[h + j], p) : sub_mod(u, v, p);
+      }
+    }
+  }
+}
+
+template <int LOGK>
+__device__ __forceinline__ void reg_dit(uint32_t (&x)[2 << LOGK], const uint2 *__restrict__ tw,
+                                        uint32_t p) {
+  constexpr int N2 = 2 << LOGK;
+#pragma unroll
+  for (int h = 1; h < N2; h <<= 1) {
+#pragma unroll
+    for (int blk = 0; blk < N2; blk += 2 * h) {
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        const uint32_t u = x[blk + j];
+        const uint32_t v = j ? mul_shoup(x[blk + j + h], tw[h + j], p) : x[blk + j + h];
+        x[blk + j] = add_mod(u, v, p);
+        x[blk + j + h] = sub_mod(u, v, p);
+      }
+    }
+  }
+}
+
+template <int LOGK>
+__device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
+                                  int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
+                                  const PrimeDev *__restrict__ primes,
+                                  const PlanDev *__restrict__ pd) {
+  constexpr int K = 1 << LOGK, K2 = 2 * K;
+  const int L1 = 1 << logL1, RS = L1 + 1;      // odd row stride: rows fall on distinct banks
+  const int64_t nrb = L >> logL1;
+  const int k = (int)(bid / nrb);
+  const int64_t rb = bid - (int64_t)k * nrb;
+  const PrimeDev pr = primes[k];
+  const uint32_t p = pr.p;
+  uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
+  const int64_t y0 = rb * L1;
+  // rows 0..K-1: limbs of a; rows K..2K-1: limbs of b
+  staged<8, uint32_t>(K2 << logL1, [&](int idx) {
+    const int j = idx >> logL1, e = idx & (L1 - 1);
+    const int64_t nz = j < K ? nz_a : nz_b;
+    return (y0 + e < nz) ? base[(int64_t)j * L + e] : 0u;
+  }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
+  __syncthreads();
+  lds_dif(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
+  const uint2 sc = pd->scale[k];
+  for (int e = threadIdx.x; e < L1; e += BLOCK) {
+    // the column of a is transformed and parked back in LDS (this thread owns column e)
+    // before b is transformed, so that at most 3K values are live in registers
+    uint32_t b[K2];
+#pragma unroll
+    for (int j = 0; j < K; ++j) b[j] = s[(K + j) * RS + e];
+    {
+      uint32_t a[K2];
+#pragma unroll
+      for (int j = 0; j < K; ++j) a[j] = s[j * RS + e];
+      reg_dif<LOGK>(a, pr.hf, p);
+#pragma unroll
+      for (int j = 0; j < K2; ++j) s[j * RS + e] = a[j];
+    }
+    reg_dif<LOGK>(b, pr.hf, p);
+#pragma unroll
+    for (int j = 0; j < K2; ++j) b[j] = mul_shoup(mont_mul(s[j * RS + e], b[j], p, pr.pinv), sc, p);
+    reg_dit<LOGK>(b, pr.hi, p);
+#pragma unroll
+    for (int j = 0; j < K2; ++j) s[j * RS + e] = b[j];
+  }
+  __syncthreads();
+  lds_dit(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hi, p);
+  staged<8, uint32_t>(K2 << logL1, [&](int idx) {
+    return s[(idx >> logL1) * RS + (idx & (L1 - 1))];
+  }, [&](int idx, uint32_t v) {
+    const int j = idx >> logL1, e = idx & (L1 - 1);
+    if (y0 + e < nlimit) base[(int64_t)j * L + e] = v;
+  });
+}
+
+// ------------------------------------------------------------------------------------
+// RecoveringProduct.  For each output coefficient i and each j < 2K-1:
+//   c_{i,j} from its np residues by CRT into (-P/2, P/2) (exact because
+//   |c_{i,j}| < d K 2^(2M) < P/4), as W-word two's complement;
+// then c_i = sum_j c_{i,j} 2^(M j) (evaluation at beta = 2^M) by per-word sums of
+// shifted windows and a wave-wide carry scan.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int fapply(int code, int y) { return ((code >> (2 * (y + 1))) & 3) - 1; }
+__device__ __forceinline__ int fcompose(int g, int f) {   // g after f
+  int r = 0;
+#pragma unroll
+  for (int y = -1; y <= 1; ++y) r |= (fapply(g, fapply(f, y)) + 1) << (2 * (y + 1));
+  return r;
+}
+
+// NP = np exactly and W = NP words per CRT value (32 NP >= log2 P + 1 since every
+// prime is below 2^31).  Per workgroup: TI consecutive coefficients; S holds their
+// output words as 64-bit partial sums.
+template <int NP>
+__device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__restrict__ X,
+                             int64_t L, int32_t K, int32_t M, int64_t nout, int32_t nw32,
+                             int32_t wc, int32_t logTI, const PrimeDev *__restrict__ primes,
+                             const PlanDev *__restrict__ pd, uint64_t *__restrict__ out) {
+  // S: TI x nw32 partial sums, then the CRT constants
+  constexpr int W = NP;
+  constexpr int NPE = (NP + 1) & ~1;  // primes padded to a pair
+  const int TI = 1 << logTI;
+  const int J = 2 * K - 1;            // c_{i,2K-1} = 0
+  const int64_t twoK = 2 * (int64_t)K;
+  const int64_t i0 = tile_id << logTI;
+  if (i0 >= nout) return;
+  const int ti = (int)min<int64_t>(TI, nout - i0);
+  // CRT constants, read by every lane: P/p_k as [u][k] (W x NPE words), P (W words),
+  // per prime (c_k Shoup pair, p_k), and 1/p_k
+  uint32_t *cq = reinterpret_cast<uint32_t *>(S + ((int64_t)nw32 << logTI));
+  uint32_t *cp = cq + NPE * W;
+  uint32_t *ci = cp + W;
+  double *cr = reinterpret_cast<double *>(ci + ((3 * NP + 1) & ~1));
+  for (int idx = threadIdx.x; idx < NPE * W; idx += BLOCK) {
+    const int u = idx / NPE, kk = idx - u * NPE;
+    cq[idx] = kk < NP ? pd->crt_q[kk][u] : 0u;
+  }
+  for (int idx = threadIdx.x; idx < W; idx += BLOCK) cp[idx] = pd->crt_p[idx];
+  for (int idx = threadIdx.x; idx < NP; idx += BLOCK) {
+    ci[3 * idx] = pd->crt_inv[idx].x;
+    ci[3 * idx + 1] = pd->crt_inv[idx].y;
+    ci[3 * idx + 2] = primes[idx].p;
+    cr[idx] = pd->crt_rcp[idx];
+  }
+  for (int idx = threadIdx.x; idx < ti * nw32; idx += BLOCK) S[idx] = 0;
+  __syncthreads();
+  // ---- CRT of each c_{i,j}, then add c_{i,j} 2^(M j) into the output words ----
+  for (int idx = threadIdx.x; idx < (J << logTI); idx += BLOCK) {
+    const int il = idx & (TI - 1), j = idx >> logTI;
+    if (il >= ti) continue;
+    const int64_t i = i0 + il;
+    uint32_t cc[NPE];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) cc[k] = X[((int64_t)k * twoK + j) * L + i];
+    if (NPE > NP) cc[NPE - 1] = 0;
+    double f = 0.0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      cc[k] = mul_shoup(cc[k], make_uint2(ci[3 * k], ci[3 * k + 1]), ci[3 * k + 2]);
+      f += (double)cc[k] * cr[k];
+    }
+    // c_{i,j} = sum_k c_k (P/p_k) - t P, where sum_k c_k P/p_k = c + t P with |c| < P/4,
+    // so t = round(sum_k c_k / p_k).  The value is produced one 32-bit word u at a time
+    // (column sums of the products, primes taken in pairs so that each pair's sum stays
+    // below 2^64, a signed carry between words) and its shifted digits are added into
+    // the output words at once.
+    const uint32_t tq = (uint32_t)__double2int_rn(f);
+    const int64_t bit = (int64_t)M * j;
+    const int64_t q0 = bit >> 5;
+    const int sh = (int)(bit & 31);
+    uint64_t *Si = S + (int64_t)il * nw32;
+    int64_t carry = 0;
+    uint32_t prev = 0;
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      uint64_t lo = 0;
+      uint32_t hi = 0;
+#pragma unroll
+      for (int k = 0; k < NPE; k += 2) {
+        const uint2 qq = *reinterpret_cast<const uint2 *>(cq + u * NPE + k);
+        uint64_t pr2 = (uint64_t)cc[k + 1] * qq.y;
+        pr2 += (uint64_t)cc[k] * qq.x;
+        lo += pr2;
+        hi += lo < pr2 ? 1u : 0u;
+      }
+      const uint64_t tp = (uint64_t)tq * cp[u];
+      const uint64_t D = lo - tp;
+      int64_t H = (int64_t)hi - (lo < tp ? 1 : 0);
+      const uint64_t D2 = D + (uint64_t)carry;
+      H += (D2 < D ? 1 : 0) - (carry < 0 ? 1 : 0);
+      const uint32_t wd = (uint32_t)D2;                 // word u of c_{i,j}, two's complement
+      carry = (int64_t)((uint64_t)H << 32) + (int64_t)(D2 >> 32);
+      const uint32_t dgt = sh ? ((wd << sh) | (prev >> (32 - sh))) : wd;
+      prev = wd;
+      if (q0 + u < nw32 && dgt) atomicAdd((unsigned long long *)&Si[q0 + u], (unsigned long long)dgt);
+    }
+    const int64_t top = sh ? (int64_t)((int32_t)prev >> (32 - sh)) : -(int64_t)(prev >> 31);
+    if (q0 + W < nw32 && top) atomicAdd((unsigned long long *)&Si[q0 + W], (unsigned long long)top);
+  }
+  __syncthreads();
+  // ---- carries, one wave per coefficient ----
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int per = (nw32 + 63) >> 6;
+  const int w_lo = min(lane * per, nw32), w_hi = min(w_lo + per, nw32);
+  for (int il = wave; il < ti; il += BLOCK / 64) {
+    uint64_t *Si = S + (int64_t)il * nw32;
+    int64_t carry = 0;
+    for (int w = w_lo; w < w_hi; ++w) {
+      const int64_t tsum = (int64_t)Si[w] + carry;
+      Si[w] = (uint32_t)tsum;
+      carry = tsum >> 32;
+    }
+    // pass the local carry to the next lane and normalise
+    int64_t cin = __shfl_up(carry, 1, 64);
+    if (lane == 0) cin = 0;
+    int64_t x = cin;
+    bool allz = true, allo = true;
+    for (int w = w_lo; w < w_hi; ++w) {
+      const int64_t tsum = (int64_t)Si[w] + x;
+      Si[w] = (uint32_t)tsum;
+      x = tsum >> 32;
+      allz = allz && (uint32_t)tsum == 0u;
+      allo = allo && (uint32_t)tsum == 0xFFFFFFFFu;
+    }
+    int code;
+    if (w_lo >= w_hi) {
+      code = (0) | (1 << 2) | (2 << 4);                 // identity
+    } else {
+      const int g = (int)x;                             // in {-1, 0, 1}
+      const int fm = g + (allz ? -1 : 0), f0 = g, fp = g + (allo ? 1 : 0);
+      code = (fm + 1) | ((f0 + 1) << 2) | ((fp + 1) << 4);
+    }
+    // inclusive scan of carry-transfer functions across the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int other = __shfl_up(code, off, 64);
+      if (lane >= off) code = fcompose(code, other);
+    }
+    const int prevc = __shfl_up(code, 1, 64);
+    int y = lane == 0 ? 0 : fapply(prevc, 0);
+    for (int w = w_lo; w < w_hi && y != 0; ++w) {
+      const int64_t tsum = (int64_t)Si[w] + y;
+      Si[w] = (uint32_t)tsum;
+      y = (int)(tsum >> 32);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint64_t fill = ((int32_t)(uint32_t)Si[nw32 - 1] < 0) ? ~0ull : 0ull;
+    uint64_t *o = out + (i0 + il) * (int64_t)wc;
+    for (int u = lane; u < wc; u += 64)
+      o[u] = (2 * u + 1 < nw32) ? ((Si[2 * u] & 0xFFFFFFFFull) | (Si[2 * u + 1] << 32)) : fill;
+  }
+}
+
+}  // namespace zpm
