@@ -15,6 +15,7 @@ the number of coefficient pairs; it is a reported baseline only.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -77,6 +78,62 @@ def cpu_baseline(prod, target_s: float) -> dict:
     }
 
 
+def batch_leg(ctx, reps: int) -> dict:
+    """The 4096-product batch (degree log-uniform in [63, 8191], magnitude bits
+    log-uniform in [32, 2048], seed 4): one product at a time through zpm_mul against
+    zpm_mul_batch (tuned per size class, graph replay); outputs must be identical."""
+    import torch
+    from paper_1612_05778_amd import _native as nat
+    from paper_1612_05778_amd import synth
+    from paper_1612_05778_amd.batchio import PackedBatch
+    print("[bench] batch leg: generating 4096 products", file=sys.stderr, flush=True)
+    pb = PackedBatch(synth.batch(4, 4096))
+    st = torch.cuda.current_stream()
+    h = st.cuda_stream
+    bits = pb.bits()
+    t0 = time.perf_counter()
+    nat.check(nat.zpm_tune(ctx.handle, pb.jobs, pb.n, None, h), "zpm_tune")
+    tune_s = time.perf_counter() - t0
+    print(f"[bench] batch leg: tuned in {tune_s:.1f} s; timing plain path", file=sys.stderr, flush=True)
+
+    def plain():
+        for i in range(pb.n):
+            j = pb.jobs[i]
+            nat.check(nat.zpm_mul(ctx.handle, j.a, j.da, j.Na, j.b, j.db, j.Nb, j.c, j.wc, h), "zpm_mul")
+
+    def timed(fn, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(k):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    plain()
+    torch.cuda.synchronize()
+    ref = pb.outputs.clone()
+    plain_ms = timed(plain, 2)
+    print("[bench] batch leg: timing batched path", file=sys.stderr, flush=True)
+    pb.outputs.zero_()
+
+    def batched():
+        nat.check(nat.zpm_mul_batch(ctx.handle, pb.jobs, pb.n, nat.ZPM_BATCH_GRAPH, h), "zpm_mul_batch")
+
+    batched()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(pb.outputs, ref))
+    batch_ms = timed(batched, reps)
+    nl = nat.c_i64()
+    nat.zpm_batch_schedule(pb.jobs, pb.n, 0, ctypes.byref(nl), None, 0)
+    return {"workload": "batch4096", "products": pb.n, "out_bits": bits,
+            "value": bits / (batch_ms / 1e3), "ms": batch_ms, "launches": nl.value,
+            "plain_value": bits / (plain_ms / 1e3), "plain_ms": plain_ms,
+            "speedup": plain_ms / batch_ms, "identical_to_plain": same,
+            "tune_s": tune_s, "tuned_classes": len(ctx.tune_table())}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +142,8 @@ def main() -> int:
     ap.add_argument("--workload", default="bits4096_64k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -171,6 +230,8 @@ def main() -> int:
         "roofline": roof,
         "kernels": kinfo,
     }
+    if not args.no_batch:
+        line["batched"] = batch_leg(ctx, args.batch_reps)
     if not args.no_cpu:
         print("[bench] cpu_baseline: timing the oracle on a sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(prod, args.cpu_seconds)

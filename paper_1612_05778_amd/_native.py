@@ -88,6 +88,10 @@ ZPM_BATCH_PERSISTENT = 2
 zpm_batch_schedule = _sig("zpm_batch_schedule", ctypes.c_int,
                           [ctypes.POINTER(Job), c_i64, c_i32, ctypes.POINTER(c_i64),
                            ctypes.POINTER(c_i64), c_i64])
+zpm_tune = _sig("zpm_tune", ctypes.c_int, [c_vp, ctypes.POINTER(Job), c_i64, ctypes.c_char_p, c_vp])
+zpm_tune_load = _sig("zpm_tune_load", ctypes.c_int, [c_vp, ctypes.c_char_p])
+zpm_tune_get = _sig("zpm_tune_get", ctypes.c_int,
+                    [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), c_i32, ctypes.POINTER(c_i32)])
 zpm_device_limits = _sig("zpm_device_limits", ctypes.c_int,
                          [ctypes.c_int, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64),
                           ctypes.POINTER(c_i64)])
@@ -104,7 +108,8 @@ zpm_profile_end = _sig("zpm_profile_end", ctypes.c_int,
 EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
            "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync",
            "zpm_profile_begin", "zpm_profile_end", "zpm_mul_batch", "zpm_mul_batch_ex",
-           "zpm_device_limits", "zpm_batch_schedule"]
+           "zpm_device_limits", "zpm_batch_schedule", "zpm_tune", "zpm_tune_load",
+           "zpm_tune_get"]
 
 
 class ZpmError(RuntimeError):

@@ -150,6 +150,41 @@ class Context:
         nat.check(rc, "zpm_mul_batch")
         return res
 
+    def _jobs(self, items, outs=None):
+        n = len(items)
+        jobs = (nat.Job * max(n, 1))()
+        res = []
+        for i, (a, Na, b, Nb) in enumerate(items):
+            da = _check_operand(a, Na, "a")
+            db = _check_operand(b, Nb, "b")
+            nout = da + db - 1 if (da and db) else 0
+            wc = out_words(da, Na, db, Nb) if nout else 1
+            o = outs[i] if outs is not None else None
+            res.append(o)
+            jobs[i].a, jobs[i].da, jobs[i].Na = a.data_ptr(), da, Na
+            jobs[i].b, jobs[i].db, jobs[i].Nb = b.data_ptr(), db, Nb
+            jobs[i].c, jobs[i].wc = (o.data_ptr() if (o is not None and nout) else None), \
+                (o.shape[1] if o is not None and o.dim() == 2 else wc)
+        return jobs, res
+
+    def tune(self, items, cache_path: str | None = None, stream=None) -> dict:
+        """Autotune K per size class on a sample of (a, Na, b, Nb); returns {class: K}."""
+        jobs, _ = self._jobs(items)
+        path = cache_path.encode() if cache_path else None
+        nat.check(nat.zpm_tune(self._h, jobs, len(items), path, _stream_handle(stream)), "zpm_tune")
+        return self.tune_table()
+
+    def tune_load(self, cache_path: str) -> None:
+        nat.check(nat.zpm_tune_load(self._h, cache_path.encode()), "zpm_tune_load")
+
+    def tune_table(self) -> dict:
+        n = nat.c_i32()
+        nat.check(nat.zpm_tune_get(self._h, None, None, 0, ctypes.byref(n)), "zpm_tune_get")
+        cl = (nat.c_i32 * max(n.value, 1))()
+        ks = (nat.c_i32 * max(n.value, 1))()
+        nat.check(nat.zpm_tune_get(self._h, cl, ks, n.value, ctypes.byref(n)), "zpm_tune_get")
+        return {cl[i]: ks[i] for i in range(n.value)}
+
     def profile_begin(self) -> None:
         nat.check(nat.zpm_profile_begin(self._h), "zpm_profile_begin")
 

@@ -70,6 +70,7 @@ struct Ctx {
   int build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState &bs);
   int enqueue_batch(BatchState &bs, hipStream_t st);
   int mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_force, hipStream_t st);
+  int tune(const zpm_job *sample, int64_t n, hipStream_t st, std::map<int32_t, int32_t> &out);
   ~Ctx();
 };
 
