@@ -11,6 +11,12 @@ seed 2.  Prints one JSON line.
 The cpu_baseline leg times the oracle (plain schoolbook, all host threads) on a
 bounded sample of output coefficients of the same workload and extrapolates by
 the number of coefficient pairs; it is a reported baseline only.
+
+Two more legs follow the main line's timing: ``batched`` (4096 products of uneven
+size, one at a time through zpm_mul against tuned zpm_mul_batch with graph replay)
+and ``served`` (an open-loop Poisson stream through the continuous-batching server
+at a stated fraction of its saturated throughput, with p50/p99 latency, and the
+same stream through the single-product baseline).
 """
 from __future__ import annotations
 
@@ -134,6 +140,148 @@ def batch_leg(ctx, reps: int) -> dict:
             "tune_s": tune_s, "tuned_classes": len(ctx.tune_table())}
 
 
+def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: int,
+               n_single: int, large_bits: float = 0.0) -> dict:
+    """Open-loop Poisson stream of the served distribution (degree log-uniform in
+    [15, 65535], magnitude bits log-uniform in [16, 8192], seed 5) through the
+    continuous-batching server.  The offered load is ``load`` times the server's
+    saturated throughput on the same request pool, measured first.  Latency runs
+    from each request's scheduled arrival to its completion.  The same stream (its
+    first ``n_single`` requests) also runs through a single-product server, the
+    unbatched baseline.  Every output must equal the product computed alone."""
+    import torch
+    from paper_1612_05778_amd import _native as nat
+    from paper_1612_05778_amd import api, synth
+    from paper_1612_05778_amd.batchio import PackedBatch
+    from paper_1612_05778_amd.workmodel import product_bits
+
+    n_pool = 1024
+    print(f"[bench] served leg: generating a pool of {n_pool} requests", file=sys.stderr, flush=True)
+    pool = synth.served_pool(5, n_pool)
+    pb = PackedBatch(pool)
+    bits = [product_bits(p.da, p.Na, p.db, p.Nb) for p in pool]
+    mean_bits = float(np.mean(bits))
+    h = torch.cuda.current_stream().cuda_stream
+    t0 = time.perf_counter()
+    for i in range(pb.n):
+        j = pb.jobs[i]
+        nat.check(nat.zpm_mul(ctx.handle, j.a, j.da, j.Na, j.b, j.db, j.Nb, j.c, j.wc, h), "zpm_mul")
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    ref = pb.outputs.clone()
+
+    cap_t = (nat.c_u64 * 8192)()
+    cap_s = (nat.c_i32 * 8192)()
+    cap_l = (ctypes.c_double * 8192)()
+    cap_n = nat.c_i64()
+
+    def saturated(srv):
+        pb.outputs.zero_()
+        torch.cuda.synchronize()
+        t = nat.c_u64()
+        w0 = time.perf_counter()
+        for i in range(pb.n):
+            nat.check(nat.zpm_server_submit(srv._h, ctypes.byref(pb.jobs[i]), ctypes.byref(t)), "submit")
+        left = pb.n
+        while left:
+            nat.check(nat.zpm_server_completions(srv._h, cap_t, cap_s, cap_l, 8192, ctypes.byref(cap_n)),
+                      "completions")
+            for k in range(cap_n.value):
+                if cap_s[k] != 0:
+                    raise RuntimeError(f"served request failed with {cap_s[k]}")
+            left -= cap_n.value
+        return sum(bits) / (time.perf_counter() - w0)
+
+    def stream(srv, n_total, warm, rate):
+        arr = synth.served_arrivals(5, n_total) / rate
+        owner = {}                     # ticket -> request index
+        busy = [0] * n_pool            # ticket in flight per pool entry
+        lag = np.zeros(n_total)
+        lat = np.full(n_total, np.nan)
+        guard_waits = 0
+        t = nat.c_u64()
+
+        def drain():
+            nat.check(nat.zpm_server_completions(srv._h, cap_t, cap_s, cap_l, 8192, ctypes.byref(cap_n)),
+                      "completions")
+            for k in range(cap_n.value):
+                r = owner.pop(cap_t[k])
+                if cap_s[k] != 0:
+                    raise RuntimeError(f"served request {r} failed with {cap_s[k]}")
+                lat[r] = lag[r] + cap_l[k]
+                if busy[r % n_pool] == cap_t[k]:
+                    busy[r % n_pool] = 0
+
+        t_start = time.perf_counter()
+        for k in range(n_total):
+            if k == warm:
+                srv.reset_stats()
+                t_meas = time.perf_counter()
+            due = t_start + arr[k]
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                if due - now > 50e-6:
+                    drain()
+            e = k % n_pool
+            while busy[e]:             # the entry's previous request still writes its output
+                guard_waits += 1
+                drain()
+            lag[k] = time.perf_counter() - due
+            nat.check(nat.zpm_server_submit(srv._h, ctypes.byref(pb.jobs[e]), ctypes.byref(t)), "submit")
+            owner[t.value] = k
+            busy[e] = t.value
+        while owner:
+            drain()
+        span = time.perf_counter() - t_meas
+        st = srv.stats()
+        m = lat[warm:]
+        done_bits = sum(bits[k % n_pool] for k in range(warm, n_total))
+        return {"requests": n_total - warm, "warmup_requests": warm,
+                "offered_req_per_s": rate, "offered_bits_per_s": rate * mean_bits,
+                "throughput_bits_per_s": done_bits / span,
+                "p50_ms": float(np.percentile(m, 50)) * 1e3, "p99_ms": float(np.percentile(m, 99)) * 1e3,
+                "max_ms": float(np.max(m)) * 1e3, "mean_ms": float(np.mean(m)) * 1e3,
+                "server_p50_ms": st["p50_s"] * 1e3, "server_p99_ms": st["p99_s"] * 1e3,
+                "max_submit_lag_ms": float(np.max(lag[warm:])) * 1e3,
+                "batches": st["batches"], "mean_batch": st["mean_batch"],
+                "admission_waits": st["admission_waits"], "hbm_peak_bytes": st["hbm_peak"],
+                "inflight_peak": st["inflight_peak"], "pool_reuse_waits": guard_waits}
+
+    srv = api.Server(ctx, hbm_budget=budget, n_streams=streams, large_bits=large_bits)
+    print("[bench] served leg: saturated throughput", file=sys.stderr, flush=True)
+    saturated(srv)
+    cap = saturated(srv)
+    torch.cuda.synchronize()
+    same_sat = bool(torch.equal(pb.outputs, ref))
+    rate = load * cap / mean_bits
+    print(f"[bench] served leg: capacity {cap:.3g} bits/s; offered {rate:.0f} req/s for "
+          f"{n_warm}+{n_req} requests", file=sys.stderr, flush=True)
+    pb.outputs.zero_()
+    torch.cuda.synchronize()
+    res = stream(srv, n_warm + n_req, n_warm, rate)
+    srv.close()
+    torch.cuda.synchronize()
+    res["identical_to_alone"] = same_sat and bool(torch.equal(pb.outputs, ref))
+    out = {"workload": "served", "pool_requests": n_pool, "pool_mean_out_bits": mean_bits,
+           "hbm_budget_bytes": budget, "streams": streams, "load": load,
+           "large_bits": large_bits or float(1 << 26),
+           "saturated_bits_per_s": cap, "plain_sequential_bits_per_s": sum(bits) / plain_s,
+           **res}
+    if n_single:
+        print(f"[bench] served leg: single-product baseline, {n_single} requests", file=sys.stderr,
+              flush=True)
+        srv = api.Server(ctx, hbm_budget=budget, n_streams=streams, large_bits=large_bits,
+                         single_product=True)
+        w = max(1, n_single // 10)
+        base = stream(srv, n_single + w, w, rate)
+        srv.close()
+        out["single_product"] = {k: base[k] for k in (
+            "requests", "throughput_bits_per_s", "p50_ms", "p99_ms", "max_ms", "mean_ms")}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +292,17 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson) leg")
+    ap.add_argument("--served-requests", type=int, default=20000)
+    ap.add_argument("--served-warmup", type=int, default=2000)
+    ap.add_argument("--served-load", type=float, default=0.7,
+                    help="offered load as a fraction of the server's saturated throughput")
+    ap.add_argument("--served-budget-gib", type=float, default=16.0)
+    ap.add_argument("--served-streams", type=int, default=4)
+    ap.add_argument("--served-large-bits", type=float, default=0.0,
+                    help="output bits from which a request runs alone (0 = library default)")
+    ap.add_argument("--served-single", type=int, default=3000,
+                    help="requests of the single-product baseline (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -232,6 +391,10 @@ def main() -> int:
     }
     if not args.no_batch:
         line["batched"] = batch_leg(ctx, args.batch_reps)
+    if not args.no_served:
+        line["served"] = served_leg(ctx, args.served_requests, args.served_warmup, args.served_load,
+                                    int(args.served_budget_gib * (1 << 30)), args.served_streams,
+                                    args.served_single, args.served_large_bits)
     if not args.no_cpu:
         print("[bench] cpu_baseline: timing the oracle on a sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(prod, args.cpu_seconds)

@@ -170,6 +170,82 @@ typedef struct zpm_kernel_time {
 int zpm_profile_begin(zpm_ctx *ctx);
 int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t *n_out);
 
+/* Serving by continuous batching.  A server runs a worker thread with n_streams
+ * streams on the context's device and a workspace pool of hbm_budget bytes of device
+ * memory, allocated once at creation.  zpm_server_submit queues one product (a job as
+ * for zpm_mul_batch) and returns at once with a ticket.  Whenever a stream is free the
+ * worker takes the next work from the queue, admitting requests in arrival order while
+ * their workspace (the np * 2K * L residues of their plan) fits in the free part of
+ * the pool.  Requests with fewer than large_bits output bits
+ * ((da + db - 1) * zpm_out_bits) are batched: as many as fit run together as
+ * zpm_mul_batch's grouped launches on that stream.  A larger request keeps the device
+ * busy by itself and runs alone, with the zpm_mul plan, on at most n_streams - 1
+ * streams at once, so that small requests never wait behind it.  Work on different
+ * streams overlaps on the device, and requests that arrive while others run join the
+ * next batch.  Twiddle tables and per-plan constants stay resident in the context; the
+ * limb counts tuned into the context before creation are used.
+ *
+ * Ownership: the caller keeps a, b and c allocated, and leaves c alone, until the
+ * request's ticket is reported finished.  The server is internally synchronized and
+ * may be called from any thread; it must be destroyed before its context.  Other
+ * calls on the context remain allowed meanwhile and are serialized with the worker.
+ *
+ * Results: status 1 = queued or running, 0 = done, < 0 = the error that ended the
+ * request (ZPM_EDEVICE after a device error, after which every queued request fails
+ * and submissions return ZPM_EDEVICE).  A finished ticket is reported once: the
+ * first of zpm_server_poll, zpm_server_wait or zpm_server_completions that returns
+ * it consumes it, and later queries return ZPM_ENOTFOUND.  latency_s runs from
+ * submission to the moment the worker saw the batch complete. */
+typedef struct zpm_server zpm_server;
+typedef struct zpm_server_config {
+  size_t hbm_budget;   /* workspace pool bytes; 0 = half of the free device memory */
+  int32_t n_streams;   /* batches in flight at once, 1..16; 0 = 4 */
+  int32_t max_batch;   /* products per batch, 1..4096; 0 = 4096 */
+  double large_bits;   /* output bits from which a request is large; 0 = 2^26 */
+  int32_t single_product; /* 1: no batching, every request runs alone through the
+                             zpm_mul path (a baseline for the batched server) */
+  int32_t reserved;    /* 0 */
+} zpm_server_config;
+int zpm_server_create(zpm_ctx *ctx, size_t hbm_budget, int32_t n_streams, zpm_server **out);
+int zpm_server_create_ex(zpm_ctx *ctx, const zpm_server_config *cfg, zpm_server **out);
+/* A server whose device is simulated, for tests of the admission and batching policy
+ * on a host without a GPU: nothing is computed and c is never written.  A batch runs
+ * for overhead_s + (its output bits) / bits_per_s seconds of wall-clock time; with
+ * fail_after >= 0 the batches launched after the first fail_after report ZPM_EDEVICE.
+ * cfg->hbm_budget must be given (no device memory is allocated). */
+int zpm_server_create_simulated(const zpm_server_config *cfg, double bits_per_s,
+                                double overhead_s, int32_t fail_after, zpm_server **out);
+/* Validates and queues a product.  ZPM_EINVAL for a bad job (as zpm_mul),
+ * ZPM_ENOMEM if its workspace alone exceeds the pool (counted as rejected),
+ * ZPM_EUNSUPPORTED if no plan covers it, ZPM_EBUSY while the server is being
+ * destroyed.  Empty products (da or db == 0) finish at once. */
+int zpm_server_submit(zpm_server *srv, const zpm_job *job, uint64_t *ticket);
+int zpm_server_poll(zpm_server *srv, uint64_t ticket, int32_t *status, double *latency_s);
+/* Blocks until the ticket finishes or timeout_s passes (< 0: no limit); ZPM_EBUSY
+ * with *status = 1 on time-out. */
+int zpm_server_wait(zpm_server *srv, uint64_t ticket, double timeout_s, int32_t *status,
+                    double *latency_s);
+/* Up to cap finished tickets in the order they finished; *n gets the count. */
+int zpm_server_completions(zpm_server *srv, uint64_t *tickets, int32_t *status, double *latency_s,
+                           int64_t cap, int64_t *n);
+/* Counters and latency since creation or the last zpm_server_reset_stats.
+ * Percentiles are over the first 2^22 completions of that period. */
+typedef struct zpm_server_report {
+  uint64_t submitted, completed, failed, rejected;
+  uint64_t batches;           /* batches launched */
+  uint64_t admission_waits;   /* times a lane's head waited for pool memory */
+  double p50_s, p99_s, max_s, mean_s;
+  double out_bits;            /* output bits of the completed requests */
+  double bits_per_s;          /* out_bits / (last completion - first submission) */
+  double mean_batch;          /* requests per batch */
+  int64_t hbm_budget, hbm_peak, hbm_in_use;   /* pool bytes */
+  int64_t inflight, inflight_peak, queued;    /* requests */
+} zpm_server_report;
+int zpm_server_stats(zpm_server *srv, zpm_server_report *out);
+int zpm_server_reset_stats(zpm_server *srv);
+/* Finishes every submitted request, stops the worker and frees the pool. */
+void zpm_server_destroy(zpm_server *srv);
+
 /* Wait for the stream and report any device error raised by earlier calls. */
 int zpm_sync(zpm_ctx *ctx, void *stream);
 

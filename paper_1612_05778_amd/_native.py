@@ -105,11 +105,57 @@ zpm_profile_begin = _sig("zpm_profile_begin", ctypes.c_int, [c_vp])
 zpm_profile_end = _sig("zpm_profile_end", ctypes.c_int,
                        [c_vp, ctypes.POINTER(KernelTime), c_i32, ctypes.POINTER(c_i32)])
 
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("n_streams", c_i32), ("max_batch", c_i32),
+                ("large_bits", ctypes.c_double), ("single_product", c_i32), ("reserved", c_i32)]
+
+
+class ServerReport(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("admission_waits", ctypes.c_uint64),
+                ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
+                ("max_s", ctypes.c_double), ("mean_s", ctypes.c_double),
+                ("out_bits", ctypes.c_double), ("bits_per_s", ctypes.c_double),
+                ("mean_batch", ctypes.c_double),
+                ("hbm_budget", c_i64), ("hbm_peak", c_i64), ("hbm_in_use", c_i64),
+                ("inflight", c_i64), ("inflight_peak", c_i64), ("queued", c_i64)]
+
+    def as_dict(self) -> dict:
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+c_u64 = ctypes.c_uint64
+zpm_server_create = _sig("zpm_server_create", ctypes.c_int,
+                         [c_vp, ctypes.c_size_t, c_i32, ctypes.POINTER(c_vp)])
+zpm_server_create_ex = _sig("zpm_server_create_ex", ctypes.c_int,
+                            [c_vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_vp)])
+zpm_server_create_simulated = _sig("zpm_server_create_simulated", ctypes.c_int,
+                                   [ctypes.POINTER(ServerConfig), ctypes.c_double, ctypes.c_double,
+                                    c_i32, ctypes.POINTER(c_vp)])
+zpm_server_submit = _sig("zpm_server_submit", ctypes.c_int,
+                         [c_vp, ctypes.POINTER(Job), ctypes.POINTER(c_u64)])
+zpm_server_poll = _sig("zpm_server_poll", ctypes.c_int,
+                       [c_vp, c_u64, ctypes.POINTER(c_i32), ctypes.POINTER(ctypes.c_double)])
+zpm_server_wait = _sig("zpm_server_wait", ctypes.c_int,
+                       [c_vp, c_u64, ctypes.c_double, ctypes.POINTER(c_i32),
+                        ctypes.POINTER(ctypes.c_double)])
+zpm_server_completions = _sig("zpm_server_completions", ctypes.c_int,
+                              [c_vp, ctypes.POINTER(c_u64), ctypes.POINTER(c_i32),
+                               ctypes.POINTER(ctypes.c_double), c_i64, ctypes.POINTER(c_i64)])
+zpm_server_stats = _sig("zpm_server_stats", ctypes.c_int, [c_vp, ctypes.POINTER(ServerReport)])
+zpm_server_reset_stats = _sig("zpm_server_reset_stats", ctypes.c_int, [c_vp])
+zpm_server_destroy = _sig("zpm_server_destroy", None, [c_vp])
+
 EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
            "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync",
            "zpm_profile_begin", "zpm_profile_end", "zpm_mul_batch", "zpm_mul_batch_ex",
            "zpm_device_limits", "zpm_batch_schedule", "zpm_tune", "zpm_tune_load",
-           "zpm_tune_get"]
+           "zpm_tune_get", "zpm_server_create", "zpm_server_create_ex",
+           "zpm_server_create_simulated", "zpm_server_submit", "zpm_server_poll",
+           "zpm_server_wait", "zpm_server_completions", "zpm_server_stats",
+           "zpm_server_reset_stats", "zpm_server_destroy"]
 
 
 class ZpmError(RuntimeError):

@@ -118,7 +118,7 @@ class Context:
         return w.view(info["np"], 2 * info["K"], L), info
 
     def mul_batch(self, items, graph: bool = False, K: int = 0, stream=None, outs=None):
-        """Products of many (a, Na, b, Nb) in one persistent launch.
+        """Products of many (a, Na, b, Nb) in one call (grouped launches per level).
 
         items: list of (a, Na, b, Nb) with a, b int64 CUDA tensors as for mul.
         Returns the list of output tensors (allocated unless ``outs`` is given).
@@ -197,3 +197,104 @@ class Context:
 
     def sync(self, stream=None) -> None:
         nat.check(nat.zpm_sync(self._h, _stream_handle(stream)), "zpm_sync")
+
+
+class Server:
+    """Continuous-batching server over a context (see zpm_server_* in include/zpm.h).
+
+    ``submit`` takes CUDA tensors as ``Context.mul`` does and keeps references to them
+    until the request is reported finished, so the caller need not.  Results arrive
+    in the output tensor given to (or returned by) ``submit``.
+    """
+
+    def __init__(self, ctx: Context | None, hbm_budget: int = 0, n_streams: int = 0,
+                 max_batch: int = 0, large_bits: float = 0.0, single_product: bool = False,
+                 simulate: dict | None = None):
+        cfg = nat.ServerConfig(hbm_budget, n_streams, max_batch, large_bits, int(single_product), 0)
+        h = nat.c_vp()
+        if simulate is not None:
+            rc = nat.zpm_server_create_simulated(ctypes.byref(cfg), simulate["bits_per_s"],
+                                                 simulate.get("overhead_s", 0.0),
+                                                 simulate.get("fail_after", -1), ctypes.byref(h))
+        else:
+            rc = nat.zpm_server_create_ex(ctx.handle, ctypes.byref(cfg), ctypes.byref(h))
+        nat.check(rc, "zpm_server_create")
+        self._h = h
+        self._ctx = ctx
+        self._keep: dict[int, tuple] = {}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            nat.zpm_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit_job(self, job: nat.Job, keep=()) -> int:
+        t = nat.c_u64()
+        nat.check(nat.zpm_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)),
+                  "zpm_server_submit")
+        if keep:
+            self._keep[t.value] = tuple(keep)
+        return t.value
+
+    def submit(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int,
+               out: torch.Tensor | None = None) -> tuple[int, torch.Tensor]:
+        """Queue a * b; returns (ticket, output tensor)."""
+        da = _check_operand(a, Na, "a")
+        db = _check_operand(b, Nb, "b")
+        n = da + db - 1 if (da and db) else 0
+        wc = out_words(da, Na, db, Nb) if n else 1
+        if out is None:
+            out = torch.empty((n, wc), dtype=torch.int64, device=a.device)
+        elif out.dim() != 2 or out.shape[0] != n or out.dtype != torch.int64 or not out.is_contiguous():
+            raise ValueError("out has the wrong shape or dtype")
+        job = nat.Job()
+        job.a, job.da, job.Na = a.data_ptr(), da, Na
+        job.b, job.db, job.Nb = b.data_ptr(), db, Nb
+        job.c, job.wc = (out.data_ptr() if n else None), out.shape[1] if n else wc
+        return self.submit_job(job, keep=(a, b, out)), out
+
+    def poll(self, ticket: int):
+        """None while queued or running, else (status, latency_s)."""
+        st, lat = nat.c_i32(), ctypes.c_double()
+        nat.check(nat.zpm_server_poll(self._h, ticket, ctypes.byref(st), ctypes.byref(lat)),
+                  "zpm_server_poll")
+        if st.value == 1:
+            return None
+        self._keep.pop(ticket, None)
+        return st.value, lat.value
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """(status, latency_s) once the ticket finishes; ZpmError(EBUSY) on time-out."""
+        st, lat = nat.c_i32(), ctypes.c_double()
+        nat.check(nat.zpm_server_wait(self._h, ticket, timeout, ctypes.byref(st), ctypes.byref(lat)),
+                  "zpm_server_wait")
+        self._keep.pop(ticket, None)
+        return st.value, lat.value
+
+    def completions(self, cap: int = 4096) -> list[tuple[int, int, float]]:
+        """Finished (ticket, status, latency_s) in completion order, consumed."""
+        t = (nat.c_u64 * cap)()
+        st = (nat.c_i32 * cap)()
+        lat = (ctypes.c_double * cap)()
+        n = nat.c_i64()
+        nat.check(nat.zpm_server_completions(self._h, t, st, lat, cap, ctypes.byref(n)),
+                  "zpm_server_completions")
+        res = [(t[i], st[i], lat[i]) for i in range(n.value)]
+        for tk, _, _ in res:
+            self._keep.pop(tk, None)
+        return res
+
+    def stats(self) -> dict:
+        r = nat.ServerReport()
+        nat.check(nat.zpm_server_stats(self._h, ctypes.byref(r)), "zpm_server_stats")
+        return r.as_dict()
+
+    def reset_stats(self) -> None:
+        nat.check(nat.zpm_server_reset_stats(self._h), "zpm_server_reset_stats")

@@ -1,4 +1,5 @@
-// Many independent products in one persistent launch.
+// Many independent products per launch: every stage of every product of a batch is a
+// segment of one grouped launch per pipeline level, stage kind and compiled variant.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

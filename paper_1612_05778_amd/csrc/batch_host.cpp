@@ -15,11 +15,27 @@ namespace zpm {
 
 static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-int Ctx::get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force,
-                        Plan *out) {
+int plan_for_batch(const std::map<int32_t, int32_t> &tuned, int64_t da, int32_t Na, int64_t db,
+                   int32_t Nb, int32_t K_force, Plan *out) {
   PlanLimits lim;
   lim.np_max = 16;
   lim.reg_k_max = 16;
+  int32_t K = K_force;
+  if (!K) {
+    auto it = tuned.find(size_class(da, Na, db, Nb));
+    if (it != tuned.end()) K = it->second;
+  }
+  Plan pl;
+  const char *why = nullptr;
+  bool ok = make_plan(da, Na, db, Nb, K, 0, pl, &why, &lim);
+  if (!ok && K && !K_force) ok = make_plan(da, Na, db, Nb, 0, 0, pl, &why, &lim);   // tuned K infeasible
+  if (!ok || !batch_supports(pl)) return ZPM_EUNSUPPORTED;
+  *out = pl;
+  return ZPM_OK;
+}
+
+int Ctx::get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force,
+                        Plan *out) {
   int32_t K = K_force;
   if (!K) {
     auto it = tuned.find(size_class(da, Na, db, Nb));
@@ -29,10 +45,8 @@ int Ctx::get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t 
   auto it = plans.find(key);
   if (it != plans.end()) { *out = it->second; return ZPM_OK; }
   Plan pl;
-  const char *why = nullptr;
-  bool ok = make_plan(da, Na, db, Nb, K, 0, pl, &why, &lim);
-  if (!ok && K && !K_force) ok = make_plan(da, Na, db, Nb, 0, 0, pl, &why, &lim);   // tuned K infeasible
-  if (!ok || !batch_supports(pl)) return ZPM_EUNSUPPORTED;
+  const int rc = plan_for_batch(tuned, da, Na, db, Nb, K_force, &pl);
+  if (rc != ZPM_OK) return rc;
   if (plans.size() > 65536) plans.clear();
   plans[key] = pl;
   *out = pl;
@@ -129,7 +143,8 @@ static int stage_variant(const Plan &pl, int kind) {
 
 // Host part of a batch: plans, job descriptors (X holds the workspace offset in words
 // until the buffer exists), grouped launches in level order.  No device work.
-int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHost &bh) {
+int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHost &bh,
+                        const Plan *given) {
   int rc;
   bh = BatchHost();
   std::vector<Plan> &pls = bh.plans;
@@ -141,7 +156,12 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
     if (j.da < 0 || j.db < 0 || j.Na < 1 || j.Nb < 1) return ZPM_EINVAL;
     if (j.da == 0 || j.db == 0) continue;
     if (j.wc < (out_bits(j.da, j.Na, j.db, j.Nb) + 63) / 64) return ZPM_EINVAL;
-    if ((rc = get_plan_batch(j.da, j.Na, j.db, j.Nb, K_force, &pls[i])) != ZPM_OK) return rc;
+    if (given) {
+      if (!batch_supports(given[i])) return ZPM_EUNSUPPORTED;
+      pls[i] = given[i];
+    } else if ((rc = get_plan_batch(j.da, j.Na, j.db, j.Nb, K_force, &pls[i])) != ZPM_OK) {
+      return rc;
+    }
     live[i] = 1;
     const Plan &pl = pls[i];
     bh.npmax = std::max(bh.npmax, pl.np);
@@ -218,7 +238,8 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
   return ZPM_OK;
 }
 
-int Ctx::build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState &bs) {
+int Ctx::build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState &bs,
+                     const Plan *given, uint32_t *ws_ext, int64_t ws_ext_words) {
   int rc;
   // the previous upload from the pinned buffers must be done before they are rewritten
   if (bs.upload_done) (void)hipEventSynchronize(bs.upload_done);
@@ -226,17 +247,23 @@ int Ctx::build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState
     if (jobs[i].da > 0 && jobs[i].db > 0 && (!jobs[i].a || !jobs[i].b || !jobs[i].c))
       return ZPM_EINVAL;
   BatchHost &bh = bs.host;
-  if ((rc = schedule_batch(jobs, n, K_force, bh)) != ZPM_OK) return rc;
+  if ((rc = schedule_batch(jobs, n, K_force, bh, given)) != ZPM_OK) return rc;
   const int64_t nlive = (int64_t)bh.jobs.size();
   if ((rc = ensure_tables(bh.npmax, bh.H, bh.TP)) != ZPM_OK) return rc;
-  if ((rc = grow_dev(&bs.ws, &bs.ws_cap, std::max<int64_t>(bh.ws_words, 1))) != ZPM_OK) return rc;
+  uint32_t *base = ws_ext;
+  if (ws_ext) {
+    if (bh.ws_words > ws_ext_words) return ZPM_EINVAL;
+  } else {
+    if ((rc = grow_dev(&bs.ws, &bs.ws_cap, std::max<int64_t>(bh.ws_words, 1))) != ZPM_OK) return rc;
+    base = bs.ws;
+  }
   if ((rc = grow_host(&bs.jobs_h, &bs.jobs_hcap, std::max<int64_t>(nlive, 1))) != ZPM_OK) return rc;
   for (int64_t s = 0; s < nlive; ++s) {
     JobDev jd = bh.jobs[s];
     PlanDev *pd = nullptr;
     if ((rc = plan_consts(bh.plans[bh.job_plan[s]], &pd)) != ZPM_OK) return rc;
     jd.plan = pd;
-    jd.X = bs.ws + (int64_t)reinterpret_cast<uintptr_t>(jd.X);
+    jd.X = base + (int64_t)reinterpret_cast<uintptr_t>(jd.X);
     bs.jobs_h[s] = jd;
   }
   const int64_t nseg = (int64_t)bh.segs.size();
@@ -318,6 +345,14 @@ int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_forc
     return ZPM_EDEVICE;
   (void)hipEventRecord(bs.upload_done, st);
   return ZPM_OK;
+}
+
+int Ctx::reserve_batch(BatchState &bs, int64_t jobs, int64_t segs) {
+  int rc;
+  if ((rc = grow_host(&bs.jobs_h, &bs.jobs_hcap, jobs)) != ZPM_OK) return rc;
+  if ((rc = grow_host(&bs.segs_h, &bs.segs_hcap, segs)) != ZPM_OK) return rc;
+  if ((rc = grow_dev(&bs.jobs_d, &bs.jobs_dcap, jobs)) != ZPM_OK) return rc;
+  return grow_dev(&bs.segs_d, &bs.segs_dcap, segs);
 }
 
 void BatchState::release() {

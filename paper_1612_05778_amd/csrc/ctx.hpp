@@ -43,6 +43,12 @@ struct BatchState {
   void release();
 };
 
+// Plan of a product for the batch kernels: the tuned limb count of its size class when
+// `tuned` has one (and it is feasible), else the planner's choice, limited to what the
+// batch kernels support.  K_force != 0 forces K.
+int plan_for_batch(const std::map<int32_t, int32_t> &tuned, int64_t da, int32_t Na, int64_t db,
+                   int32_t Nb, int32_t K_force, Plan *out);
+
 struct Ctx {
   int device = 0;
   PrimeDev *primes = nullptr;   // MAXNP entries
@@ -66,8 +72,15 @@ struct Ctx {
   int get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np, Plan *out);
   int prepare(const Plan &pl, DevState *ds);
   int get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, Plan *out);
-  int schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHost &bh);
-  int build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState &bs);
+  // given: plans per job (from plan_for_batch) instead of the context's choice
+  int schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHost &bh,
+                     const Plan *given = nullptr);
+  // ws_ext: workspace of ws_ext_words words to use instead of the state's own buffer
+  int build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState &bs,
+                  const Plan *given = nullptr, uint32_t *ws_ext = nullptr, int64_t ws_ext_words = 0);
+  // sizes the descriptor buffers of bs for batches of up to `jobs` products and `segs`
+  // segments, so that later batches within those bounds allocate nothing
+  int reserve_batch(BatchState &bs, int64_t jobs, int64_t segs);
   int enqueue_batch(BatchState &bs, hipStream_t st);
   int mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_force, hipStream_t st);
   int tune(const zpm_job *sample, int64_t n, hipStream_t st, std::map<int32_t, int32_t> &out);

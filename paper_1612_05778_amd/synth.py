@@ -18,7 +18,8 @@ Workloads (sizes of the named configurations):
 * ``batch4096``  4096 products, degree log-uniform in [63, 8191], magnitude bits
   log-uniform in [32, 2048], seed 4.
 * ``served``     Poisson arrivals, degree log-uniform in [15, 65535], bits
-  log-uniform in [16, 8192], seed 5.
+  log-uniform in [16, 8192], seed 5: a pool of distinct requests
+  (``served_pool``) and arrival times (``served_arrivals``) that cycle through it.
 """
 from __future__ import annotations
 
@@ -181,3 +182,27 @@ def served_sizes(seed: int = 5, n: int = 1000, deg=(15, 65535), bits=(16, 8192))
     r = rng_for(seed)
     r.exponential(1.0, size=n)
     return _log_uniform_int(r, deg[0], deg[1], n), _log_uniform_int(r, bits[0], bits[1], n)
+
+
+def served_pool(seed: int = 5, n_pool: int = 1024, deg=(15, 65535),
+                bits=(16, 8192)) -> list[Product]:
+    """``n_pool`` distinct requests of the served distribution (degree and magnitude
+    bits log-uniform as stated; a then b drawn per request).  Generator stream
+    ``PCG64([seed, 1])``: all degrees, then all bit sizes, then the operands."""
+    r = np.random.Generator(np.random.PCG64([seed, 1]))
+    degs = _log_uniform_int(r, deg[0], deg[1], n_pool)
+    nbits = _log_uniform_int(r, bits[0], bits[1], n_pool)
+    out = []
+    for t in range(n_pool):
+        a, Na = signed_words(r, int(degs[t]) + 1, int(nbits[t]))
+        b, Nb = signed_words(r, int(degs[t]) + 1, int(nbits[t]))
+        out.append(Product(a, Na, b, Nb))
+    return out
+
+
+def served_arrivals(seed: int = 5, n: int = 22000) -> np.ndarray:
+    """Arrival times of an open-loop Poisson stream at rate 1 (divide by the rate in
+    requests/s): cumulative sums of unit exponential gaps, stream ``PCG64([seed, 2])``.
+    Request k carries pool entry ``k % n_pool``."""
+    r = np.random.Generator(np.random.PCG64([seed, 2]))
+    return np.cumsum(r.exponential(1.0, size=n))
