@@ -179,8 +179,8 @@ int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t
  * the pool.  Requests with fewer than large_bits output bits
  * ((da + db - 1) * zpm_out_bits) are batched: as many as fit run together as
  * zpm_mul_batch's grouped launches on that stream.  A larger request keeps the device
- * busy by itself and runs alone, with the zpm_mul plan, on at most n_streams - 1
- * streams at once, so that small requests never wait behind it.  Work on different
+ * busy by itself and runs alone, with the zpm_mul plan; large requests hold at most
+ * large_streams streams at once, so that small requests do not wait behind them.  Work on different
  * streams overlaps on the device, and requests that arrive while others run join the
  * next batch.  Twiddle tables and per-plan constants stay resident in the context; the
  * limb counts tuned into the context before creation are used.
@@ -199,12 +199,13 @@ int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t
 typedef struct zpm_server zpm_server;
 typedef struct zpm_server_config {
   size_t hbm_budget;   /* workspace pool bytes; 0 = half of the free device memory */
-  int32_t n_streams;   /* batches in flight at once, 1..16; 0 = 4 */
+  int32_t n_streams;   /* batches in flight at once, 1..16; 0 = 8 */
   int32_t max_batch;   /* products per batch, 1..4096; 0 = 4096 */
   double large_bits;   /* output bits from which a request is large; 0 = 2^26 */
   int32_t single_product; /* 1: no batching, every request runs alone through the
                              zpm_mul path (a baseline for the batched server) */
-  int32_t reserved;    /* 0 */
+  int32_t large_streams;  /* streams large requests may hold at once, 1..n_streams;
+                             0 = max(1, n_streams / 4) */
 } zpm_server_config;
 int zpm_server_create(zpm_ctx *ctx, size_t hbm_budget, int32_t n_streams, zpm_server **out);
 int zpm_server_create_ex(zpm_ctx *ctx, const zpm_server_config *cfg, zpm_server **out);

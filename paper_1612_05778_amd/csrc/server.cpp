@@ -10,8 +10,10 @@
 // the batch kernels do not cover and every request in single-product mode (the
 // unbatched baseline).  Work on different streams overlaps on the device, and
 // requests that arrive meanwhile wait for the next free stream.  Large requests may
-// occupy at most n_streams - 1 streams, so a small request never waits behind a
-// large one.  Twiddle tables and plan constants stay resident in the context.
+// occupy at most large_streams streams (a quarter of them by default): while large
+// kernels fill the device, small kernels wait for free compute units, so the fewer
+// large requests run at once, the shorter small requests' tail latency, at some cost
+// in throughput.  Twiddle tables and plan constants stay resident in the context.
 //
 // The executor is an interface so that the admission and batching policy can also run
 // against a simulated device (no computation, a modelled duration per batch).
@@ -365,7 +367,7 @@ bool Server::take(int ln, Flight &f) {
 // Picks the lane whose head arrived first among those allowed a stream (under m).
 bool Server::form(Flight &f, int busy_large) {
   const int S = cfg.n_streams;
-  const bool large_ok = !lane[1].empty() && (S == 1 || busy_large < S - 1);
+  const bool large_ok = !lane[1].empty() && busy_large < cfg.large_streams;
   const bool small_ok = !lane[0].empty();
   int order[2] = {0, 1};
   if (large_ok && small_ok && lane[1].front().t0 < lane[0].front().t0) std::swap(order[0], order[1]);
@@ -497,11 +499,13 @@ static int fill_config(const zpm_server_config *in, zpm_server_config *out) {
   zpm_server_config c;
   std::memset(&c, 0, sizeof(c));
   if (in) c = *in;
-  if (c.n_streams == 0) c.n_streams = 4;
+  if (c.n_streams == 0) c.n_streams = 8;
   if (c.max_batch == 0) c.max_batch = kMaxBatch;
   if (c.large_bits == 0) c.large_bits = 67108864.0;
+  if (c.large_streams == 0 && c.n_streams >= 1) c.large_streams = std::max(1, c.n_streams / 4);
   if (c.n_streams < 1 || c.n_streams > kMaxStreams || c.max_batch < 1 || c.max_batch > kMaxBatch ||
-      !(c.large_bits > 0) || (c.single_product != 0 && c.single_product != 1) || c.reserved != 0)
+      !(c.large_bits > 0) || (c.single_product != 0 && c.single_product != 1) ||
+      c.large_streams < 1 || c.large_streams > c.n_streams)
     return ZPM_EINVAL;
   *out = c;
   return ZPM_OK;

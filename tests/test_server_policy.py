@@ -105,6 +105,20 @@ def test_small_requests_pass_large_ones():
     s.close()
 
 
+def test_large_stream_limit():
+    # four long large requests, two of them at a time at most; small ones keep flowing
+    s = api.Server(None, hbm_budget=8 << 30, n_streams=3, large_bits=1e8, large_streams=2,
+                   simulate={"bits_per_s": 1e10, "overhead_s": 1e-5})
+    big = [s.submit_job(job(30000, 8000)) for _ in range(4)]
+    time.sleep(0.02)
+    st = s.stats()
+    assert st["inflight"] == 2 and st["queued"] == 2
+    small = [s.submit_job(job(20, 64)) for _ in range(10)]
+    got = drain(s, big + small, timeout=30)
+    assert max(got[t][2] for t in small) < min(got[t][2] for t in big)
+    s.close()
+
+
 def test_one_stream_serves_a_lane_in_order():
     s = sim(1 << 30, streams=1, rate=1e9, max_batch=4)
     ts = [s.submit_job(job(50 + (i % 7) * 10, 100)) for i in range(40)]
@@ -206,9 +220,11 @@ def test_concurrent_submitters():
 
 
 def test_config_rejected():
-    for cfg in ({"n_streams": 17}, {"max_batch": 5000}, {"large_bits": -1.0}, {"single": 2}):
+    for cfg in ({"n_streams": 17}, {"max_batch": 5000}, {"large_bits": -1.0}, {"single": 2},
+                {"n_streams": 2, "large_streams": 3}, {"large_streams": -1}):
         c = nat.ServerConfig(1 << 20, cfg.get("n_streams", 0), cfg.get("max_batch", 0),
-                             cfg.get("large_bits", 0.0), cfg.get("single", 0), 0)
+                             cfg.get("large_bits", 0.0), cfg.get("single", 0),
+                             cfg.get("large_streams", 0))
         h = nat.c_vp()
         assert nat.zpm_server_create_simulated(ctypes.byref(c), 1e9, 0.0, -1, ctypes.byref(h)) \
             == nat.ZPM_EINVAL
