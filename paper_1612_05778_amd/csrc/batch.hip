@@ -49,16 +49,21 @@ __global__ __launch_bounds__(BLOCK) void kg_recover(const JobDev *__restrict__ j
                    jb.wc, jb.log_ti_out, primes, jb.plan, jb.c);
 }
 
+// Blocks are remapped with xcd_tile (as in the single-product column pass) so that
+// neighbouring tiles, which share 128-byte lines, run on one XCD.
 __global__ __launch_bounds__(BLOCK) void kg_col(const JobDev *__restrict__ jobs,
                                                 const GroupSeg *__restrict__ segs, int32_t nseg,
-                                                int32_t inverse, const PrimeDev *__restrict__ primes) {
+                                                int32_t inverse, const PrimeDev *__restrict__ primes,
+                                                int64_t nblocks) {
   extern __shared__ uint32_t s[];
-  const GroupSeg g = segs[find_seg(segs, nseg, blockIdx.x)];
+  const int64_t b = xcd_tile(nblocks);
+  if (b >= nblocks) return;
+  const GroupSeg g = segs[find_seg(segs, nseg, b)];
   const JobDev &jb = jobs[g.job];
   const int c = g.pass;
   const bool outer = c == 0;
   const int64_t L = jb.L;
-  body_col_pass(s, (int64_t)blockIdx.x - g.start, jb.X, L, 2 * jb.K, jb.col_logn[c], jb.col_S[c],
+  body_col_pass(s, b - g.start, jb.X, L, 2 * jb.K, jb.col_logn[c], jb.col_S[c],
                 jb.col_logT[c], (outer && !inverse) ? jb.da : L, (outer && !inverse) ? jb.db : L,
                 jb.K, (outer && inverse) ? jb.nout : L, inverse, primes);
 }
@@ -120,8 +125,8 @@ hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *seg
       break;
     case SK_COL_FWD:
     case SK_COL_INV:
-      hipLaunchKernelGGL(kg_col, grid, blk, gr.lds, st, jobs, sg, ns, gr.kind == SK_COL_INV ? 1 : 0,
-                         primes);
+      hipLaunchKernelGGL(kg_col, dim3((unsigned)(8 * ((gr.blocks + 7) / 8))), blk, gr.lds, st, jobs,
+                         sg, ns, gr.kind == SK_COL_INV ? 1 : 0, primes, gr.blocks);
       break;
     case SK_CONVOLVE:
       switch (gr.variant) {

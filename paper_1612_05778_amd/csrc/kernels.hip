@@ -37,12 +37,17 @@ __global__ __launch_bounds__(BLOCK) void k_bivariate_representation(
                       col_off, logTI, primes, pd);
 }
 
+// Neighbouring tiles of a column read the two halves of the same 128-byte lines when
+// a tile is 16 columns wide: they are placed on one XCD, next to each other in its
+// dispatch order, so that the second read hits that XCD's L2.
 __global__ __launch_bounds__(BLOCK) void k_col_pass(
     uint32_t *__restrict__ X, int64_t L, int32_t twoK, int32_t logn, int64_t S, int32_t logT,
     int64_t nz_a, int64_t nz_b, int32_t K, int64_t nlimit, int32_t inverse,
-    const PrimeDev *__restrict__ primes) {
+    const PrimeDev *__restrict__ primes, int64_t nblocks) {
   extern __shared__ uint32_t s[];
-  body_col_pass(s, blockIdx.x, X, L, twoK, logn, S, logT, nz_a, nz_b, K, nlimit, inverse, primes);
+  const int64_t bid = xcd_tile(nblocks);
+  if (bid >= nblocks) return;
+  body_col_pass(s, bid, X, L, twoK, logn, S, logT, nz_a, nz_b, K, nlimit, inverse, primes);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_convolve_rows(
@@ -119,8 +124,9 @@ hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, h
   const int64_t nz_a = (c == 0 && !inverse) ? pl.da : L;
   const int64_t nz_b = (c == 0 && !inverse) ? pl.db : L;
   const int64_t nlimit = (c == 0 && inverse) ? pl.nout : L;
-  hipLaunchKernelGGL(k_col_pass, dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, L, 2 * pl.K,
-                     logn, S, logT, nz_a, nz_b, pl.K, nlimit, inverse ? 1 : 0, ds.primes);
+  const int64_t grid = 8 * ((blocks + 7) / 8);   // xcd_tile's shape
+  hipLaunchKernelGGL(k_col_pass, dim3((unsigned)grid), dim3(BLOCK), lds, st, ds.X, L, 2 * pl.K,
+                     logn, S, logT, nz_a, nz_b, pl.K, nlimit, inverse ? 1 : 0, ds.primes, blocks);
   return hipGetLastError();
 }
 
