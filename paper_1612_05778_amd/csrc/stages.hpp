@@ -1,5 +1,5 @@
 // Device bodies of the pipeline stages, shared by the per-stage kernels and by the
-// persistent batch kernel.  Each body processes one tile (one workgroup's share) and
+// grouped batch kernels.  Each body processes one tile (one workgroup's share) and
 // takes its LDS buffer and tile index as arguments.  See kernels.hip for the layout
 // of the workspace and the order of the stages.
 #pragma once

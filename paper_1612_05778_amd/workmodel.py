@@ -1,9 +1,12 @@
 """Algorithmic work per kernel launch, for roofline reporting.
 
 Counts are what the method itself must do for a plan (Section 3.3: K
-transforms of length L along y for each operand, and 2L length-K cyclic and
-negacyclic convolutions along x, here as one 2K-point transform per
-y-frequency), not what a particular kernel happens to execute:
+transforms of length L along y for each operand and 2K inverse ones; along x,
+per y-frequency, a cyclic and a negacyclic convolution of length K, i.e. three
+K-point transforms each, plus the twist by theta^j before the negacyclic
+forward transforms and the untwist after its inverse), not what a particular
+kernel happens to execute (the kernels run the x part as 2K-point transforms
+whose first stage is the twist):
 
 * one radix-2 butterfly = 11 int32 VALU operations (Shoup product: 2 mul_lo,
   1 mul_hi, 1 sub, 2 for the final reduction; modular add 3; modular sub 2);
@@ -33,10 +36,13 @@ def kernel_work(plan: dict, name: str) -> dict:
     nout = da + db - 1
     logx = int(math.log2(2 * K))
     if name == "convolve_rows":
-        bfly = np_ * L * K * (2 * logL1 + 3 * logx)
+        logK = logx - 1
+        bfly = np_ * L * K * (2 * logL1 + 3 * logK)
+        twists = np_ * L * 3 * K               # theta^j on both operands, theta^-j after
         pw = np_ * 2 * K * L
         words_in = np_ * 2 * K * L
-        return {"ops": bfly * OPS_BFLY + pw * OPS_POINTWISE, "bytes": 4 * 2 * words_in}
+        return {"ops": bfly * OPS_BFLY + twists * OPS_TWIDDLE + pw * OPS_POINTWISE,
+                "bytes": 4 * 2 * words_in}
     if name in ("col_pass_fwd", "col_pass_inv"):
         # per launch = one pass; use the mean pass length
         cols = plan["col_log2n"]

@@ -9,8 +9,16 @@ The oracle cannot redo a whole 2^16 x 4096-bit product in test time, so:
   y = 1 and y = -1 (a wrong coefficient passes one modular check with
   probability about (da + db) / q);
 * every coefficient satisfies |c_i| <= min(da, db) 2^(Na+Nb-2) and its words
-  above Nout bits are pure sign extension.
+  above Nout bits are pure sign extension;
+* where tests/golden/digests.json holds the SHA-256 of the oracle's complete output
+  for the workload (written by tests/golden/make_digests.py from the generators and
+  the oracle alone), the whole device output must have that digest: every
+  coefficient bit for bit.
 """
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -33,6 +41,22 @@ def eval_mod(vals, r, q):
     for x in reversed(vals):
         acc = (acc * r + x) % q
     return acc
+
+
+DIGESTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")
+
+
+def check_digest(name, got):
+    if not os.path.exists(DIGESTS):
+        return False
+    ref = json.load(open(DIGESTS)).get(name)
+    if ref is None:
+        return False
+    assert got.shape[1] == ref["wc"], "output width differs from the digested one"
+    assert hashlib.sha256(got.tobytes()).hexdigest() == ref["sha256"], \
+        f"{name}: device output differs from the oracle's full output"
+    print(f"[fullsize] {name}: every coefficient matches the oracle digest", flush=True)
+    return True
 
 
 def full_checks(prod, got, nsample, seed):
@@ -76,6 +100,7 @@ def test_bits4096_64k(ctx):
     torch.cuda.synchronize()
     got = host(out)
     del out
+    check_digest("bits4096_64k", got)
     full_checks(prod, got, 40, 7)
 
 
