@@ -147,15 +147,19 @@ int zpm_batch_schedule(const zpm_job *jobs, int64_t n, int32_t K, int64_t *nlaun
 /* Autotuner.  Products are grouped into size classes, (ceil log2(da + db - 1),
  * ceil log2(ceil(max(Na, Nb) / 32))).  For every class present in `sample` the
  * median product is replicated into a batch and timed with each feasible limb count
- * K; the fastest K is kept in the context and used by later zpm_mul_batch calls for
- * that class.  Runs on `stream` and waits for it.  With a non-NULL cache_path the
- * table is also written there as JSON (device, library version, class -> K);
- * zpm_tune_load reads such a file back (ZPM_EINVAL if it was written by another
- * library version).  zpm_tune_get copies the table (up to cap entries) and sets *n
- * to its size. */
+ * K <= 64 (which fixes M and the prime count, Section 3.1) and column-tile width T
+ * of the y passes (8, 16 or 32 inner indices per workgroup); the fastest (K, T) is
+ * kept in the context and used by later zpm_mul_batch calls, and by servers created
+ * afterwards, for that class.  Runs on `stream` and waits for it.  With a non-NULL
+ * cache_path the table is also written there as JSON (device, library version,
+ * class -> [K, T]); zpm_tune_load reads such a file back (ZPM_EINVAL if it was
+ * written by another library version or is malformed; the table is then unchanged).
+ * zpm_tune_get copies the table (up to cap entries; tiles may be NULL) and sets *n to
+ * its size. */
 int zpm_tune(zpm_ctx *ctx, const zpm_job *sample, int64_t n, const char *cache_path, void *stream);
 int zpm_tune_load(zpm_ctx *ctx, const char *cache_path);
-int zpm_tune_get(zpm_ctx *ctx, int32_t *classes, int32_t *ks, int32_t cap, int32_t *n);
+int zpm_tune_get(zpm_ctx *ctx, int32_t *classes, int32_t *ks, int32_t *tiles, int32_t cap,
+                 int32_t *n);
 
 /* Per-kernel timing.  Between zpm_profile_begin and zpm_profile_end every kernel
  * the context launches is bracketed by HIP events recorded on its stream.

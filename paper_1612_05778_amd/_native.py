@@ -91,7 +91,8 @@ zpm_batch_schedule = _sig("zpm_batch_schedule", ctypes.c_int,
 zpm_tune = _sig("zpm_tune", ctypes.c_int, [c_vp, ctypes.POINTER(Job), c_i64, ctypes.c_char_p, c_vp])
 zpm_tune_load = _sig("zpm_tune_load", ctypes.c_int, [c_vp, ctypes.c_char_p])
 zpm_tune_get = _sig("zpm_tune_get", ctypes.c_int,
-                    [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), c_i32, ctypes.POINTER(c_i32)])
+                    [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), c_i32,
+                     ctypes.POINTER(c_i32)])
 zpm_device_limits = _sig("zpm_device_limits", ctypes.c_int,
                          [ctypes.c_int, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64),
                           ctypes.POINTER(c_i64)])

@@ -168,7 +168,8 @@ class Context:
         return jobs, res
 
     def tune(self, items, cache_path: str | None = None, stream=None) -> dict:
-        """Autotune K per size class on a sample of (a, Na, b, Nb); returns {class: K}."""
+        """Autotune (K, column tile) per size class on a sample of (a, Na, b, Nb);
+        returns {class: (K, T)}."""
         jobs, _ = self._jobs(items)
         path = cache_path.encode() if cache_path else None
         nat.check(nat.zpm_tune(self._h, jobs, len(items), path, _stream_handle(stream)), "zpm_tune")
@@ -178,12 +179,14 @@ class Context:
         nat.check(nat.zpm_tune_load(self._h, cache_path.encode()), "zpm_tune_load")
 
     def tune_table(self) -> dict:
+        """{size class: (K, column tile)} chosen by tune or loaded by tune_load."""
         n = nat.c_i32()
-        nat.check(nat.zpm_tune_get(self._h, None, None, 0, ctypes.byref(n)), "zpm_tune_get")
+        nat.check(nat.zpm_tune_get(self._h, None, None, None, 0, ctypes.byref(n)), "zpm_tune_get")
         cl = (nat.c_i32 * max(n.value, 1))()
         ks = (nat.c_i32 * max(n.value, 1))()
-        nat.check(nat.zpm_tune_get(self._h, cl, ks, n.value, ctypes.byref(n)), "zpm_tune_get")
-        return {cl[i]: ks[i] for i in range(n.value)}
+        ts = (nat.c_i32 * max(n.value, 1))()
+        nat.check(nat.zpm_tune_get(self._h, cl, ks, ts, n.value, ctypes.byref(n)), "zpm_tune_get")
+        return {cl[i]: (ks[i], ts[i]) for i in range(n.value)}
 
     def profile_begin(self) -> None:
         nat.check(nat.zpm_profile_begin(self._h), "zpm_profile_begin")

@@ -15,37 +15,47 @@ namespace zpm {
 
 static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-int plan_for_batch(const std::map<int32_t, int32_t> &tuned, int64_t da, int32_t Na, int64_t db,
-                   int32_t Nb, int32_t K_force, Plan *out) {
+int plan_for_batch(const TuneTable &tuned, int64_t da, int32_t Na, int64_t db, int32_t Nb,
+                   int32_t K_force, int32_t T_force, Plan *out) {
   PlanLimits lim;
   lim.np_max = 16;
   lim.reg_k_max = 16;
-  int32_t K = K_force;
-  if (!K) {
+  int32_t K = K_force, T = T_force;
+  if (!K && !T) {
     auto it = tuned.find(size_class(da, Na, db, Nb));
-    if (it != tuned.end()) K = it->second;
+    if (it != tuned.end()) {
+      K = it->second.K;
+      T = it->second.T;
+    }
   }
+  lim.col_tile = T;
   Plan pl;
   const char *why = nullptr;
   bool ok = make_plan(da, Na, db, Nb, K, 0, pl, &why, &lim);
-  if (!ok && K && !K_force) ok = make_plan(da, Na, db, Nb, 0, 0, pl, &why, &lim);   // tuned K infeasible
+  if (!ok && K && !K_force) {      // tuned choice infeasible for this member of the class
+    lim.col_tile = T_force;
+    ok = make_plan(da, Na, db, Nb, 0, 0, pl, &why, &lim);
+  }
   if (!ok || !batch_supports(pl)) return ZPM_EUNSUPPORTED;
   *out = pl;
   return ZPM_OK;
 }
 
 int Ctx::get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force,
-                        Plan *out) {
-  int32_t K = K_force;
-  if (!K) {
+                        int32_t T_force, Plan *out) {
+  int32_t K = K_force, T = T_force;
+  if (!K && !T) {
     auto it = tuned.find(size_class(da, Na, db, Nb));
-    if (it != tuned.end()) K = it->second;
+    if (it != tuned.end()) {
+      K = it->second.K;
+      T = it->second.T;
+    }
   }
-  auto key = std::make_tuple(da, Na, db, Nb, K, (int32_t)-1);
+  auto key = std::make_tuple(da, Na, db, Nb, K, T, (int32_t)-1);
   auto it = plans.find(key);
   if (it != plans.end()) { *out = it->second; return ZPM_OK; }
   Plan pl;
-  const int rc = plan_for_batch(tuned, da, Na, db, Nb, K_force, &pl);
+  const int rc = plan_for_batch(tuned, da, Na, db, Nb, K_force, T_force, &pl);
   if (rc != ZPM_OK) return rc;
   if (plans.size() > 65536) plans.clear();
   plans[key] = pl;
@@ -80,8 +90,9 @@ static int grow_host(T **p, int64_t *cap, int64_t n) {
   return ZPM_OK;
 }
 
-uint64_t BatchState::hash(const zpm_job *jobs, int64_t n, int32_t K_force) {
-  uint64_t h = 1469598103934665603ull ^ (uint64_t)n ^ ((uint64_t)K_force << 40);
+uint64_t BatchState::hash(const zpm_job *jobs, int64_t n, int32_t K_force, int32_t T_force) {
+  uint64_t h = 1469598103934665603ull ^ (uint64_t)n ^ ((uint64_t)K_force << 40) ^
+               ((uint64_t)T_force << 52);
   const unsigned char *p = reinterpret_cast<const unsigned char *>(jobs);
   for (size_t i = 0; i < sizeof(zpm_job) * (size_t)n; ++i) h = (h ^ p[i]) * 1099511628211ull;
   return h;
@@ -144,7 +155,7 @@ static int stage_variant(const Plan &pl, int kind) {
 // Host part of a batch: plans, job descriptors (X holds the workspace offset in words
 // until the buffer exists), grouped launches in level order.  No device work.
 int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHost &bh,
-                        const Plan *given) {
+                        const Plan *given, int32_t T_force) {
   int rc;
   bh = BatchHost();
   std::vector<Plan> &pls = bh.plans;
@@ -159,7 +170,7 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
     if (given) {
       if (!batch_supports(given[i])) return ZPM_EUNSUPPORTED;
       pls[i] = given[i];
-    } else if ((rc = get_plan_batch(j.da, j.Na, j.db, j.Nb, K_force, &pls[i])) != ZPM_OK) {
+    } else if ((rc = get_plan_batch(j.da, j.Na, j.db, j.Nb, K_force, T_force, &pls[i])) != ZPM_OK) {
       return rc;
     }
     live[i] = 1;
@@ -239,7 +250,7 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
 }
 
 int Ctx::build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState &bs,
-                     const Plan *given, uint32_t *ws_ext, int64_t ws_ext_words) {
+                     const Plan *given, uint32_t *ws_ext, int64_t ws_ext_words, int32_t T_force) {
   int rc;
   // the previous upload from the pinned buffers must be done before they are rewritten
   if (bs.upload_done) (void)hipEventSynchronize(bs.upload_done);
@@ -247,7 +258,7 @@ int Ctx::build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState
     if (jobs[i].da > 0 && jobs[i].db > 0 && (!jobs[i].a || !jobs[i].b || !jobs[i].c))
       return ZPM_EINVAL;
   BatchHost &bh = bs.host;
-  if ((rc = schedule_batch(jobs, n, K_force, bh, given)) != ZPM_OK) return rc;
+  if ((rc = schedule_batch(jobs, n, K_force, bh, given, T_force)) != ZPM_OK) return rc;
   const int64_t nlive = (int64_t)bh.jobs.size();
   if ((rc = ensure_tables(bh.npmax, bh.H, bh.TP)) != ZPM_OK) return rc;
   uint32_t *base = ws_ext;
@@ -295,12 +306,13 @@ int Ctx::enqueue_batch(BatchState &bs, hipStream_t st) {
   return ZPM_OK;
 }
 
-int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_force, hipStream_t st) {
+int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_force, hipStream_t st,
+                   int32_t T_force) {
   int rc;
   const bool graph = (flags & ZPM_BATCH_GRAPH) != 0;
   BatchState &bs = graph ? batch_graph : batch_eager;
   if (graph) {
-    const uint64_t h = BatchState::hash(jobs, n, K_force);
+    const uint64_t h = BatchState::hash(jobs, n, K_force, T_force);
     if (bs.exec && bs.key == h) {
       prof.begin(KK_BATCH, st);
       const hipError_t e = hipGraphLaunch(bs.exec, st);
@@ -308,7 +320,7 @@ int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_forc
       return e == hipSuccess ? ZPM_OK : ZPM_EDEVICE;
     }
     if (bs.exec) { (void)hipGraphExecDestroy(bs.exec); bs.exec = nullptr; }
-    if ((rc = build_batch(jobs, n, K_force, bs)) != ZPM_OK) return rc;
+    if ((rc = build_batch(jobs, n, K_force, bs, nullptr, nullptr, 0, T_force)) != ZPM_OK) return rc;
     if (bs.host.groups.empty()) return ZPM_OK;
     // capture on a stream of our own (the caller's may be the legacy default stream,
     // which cannot be captured); the graph is then launched on the caller's stream
@@ -339,7 +351,7 @@ int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_forc
     prof.end(st);
     return e == hipSuccess ? ZPM_OK : ZPM_EDEVICE;
   }
-  if ((rc = build_batch(jobs, n, K_force, bs)) != ZPM_OK) return rc;
+  if ((rc = build_batch(jobs, n, K_force, bs, nullptr, nullptr, 0, T_force)) != ZPM_OK) return rc;
   if ((rc = enqueue_batch(bs, st)) != ZPM_OK) return rc;
   if (!bs.upload_done && hipEventCreateWithFlags(&bs.upload_done, hipEventDisableTiming) != hipSuccess)
     return ZPM_EDEVICE;

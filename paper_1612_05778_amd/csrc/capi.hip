@@ -112,7 +112,7 @@ int Ctx::ensure_ws(int64_t words) {
 
 int Ctx::get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np,
                   Plan *out) {
-  auto key = std::make_tuple(da, Na, db, Nb, K, np);
+  auto key = std::make_tuple(da, Na, db, Nb, K, np, (int32_t)-2);   // -2: single-product plans
   auto it = plans.find(key);
   if (it != plans.end()) { *out = it->second; return ZPM_OK; }
   Plan pl;

@@ -39,15 +39,21 @@ struct BatchState {
   hipEvent_t upload_done = nullptr;
   hipGraphExec_t exec = nullptr;
   uint64_t key = 0;
-  static uint64_t hash(const zpm_job *jobs, int64_t n, int32_t K_force);
+  static uint64_t hash(const zpm_job *jobs, int64_t n, int32_t K_force, int32_t T_force);
   void release();
 };
 
-// Plan of a product for the batch kernels: the tuned limb count of its size class when
-// `tuned` has one (and it is feasible), else the planner's choice, limited to what the
-// batch kernels support.  K_force != 0 forces K.
-int plan_for_batch(const std::map<int32_t, int32_t> &tuned, int64_t da, int32_t Na, int64_t db,
-                   int32_t Nb, int32_t K_force, Plan *out);
+// Autotuned choice for a size class: limb count K and column-tile width T.
+struct TuneChoice {
+  int32_t K = 0, T = 0;
+};
+using TuneTable = std::map<int32_t, TuneChoice>;
+
+// Plan of a product for the batch kernels: the tuned K and column tile of its size
+// class when `tuned` has them (and they are feasible), else the planner's choice,
+// limited to what the batch kernels support.  K_force / T_force != 0 force K / T.
+int plan_for_batch(const TuneTable &tuned, int64_t da, int32_t Na, int64_t db, int32_t Nb,
+                   int32_t K_force, int32_t T_force, Plan *out);
 
 struct Ctx {
   int device = 0;
@@ -57,12 +63,12 @@ struct Ctx {
   int64_t H_built = 0;
   int64_t TP_built = 0;         // entries of each prime's 2^(32 t) table
   std::map<std::tuple<int, int, int, int>, PlanDev *> consts;
-  std::map<std::tuple<int64_t, int32_t, int64_t, int32_t, int32_t, int32_t>, Plan> plans;
+  std::map<std::tuple<int64_t, int32_t, int64_t, int32_t, int32_t, int32_t, int32_t>, Plan> plans;
   uint32_t *ws = nullptr;
   int64_t ws_words = 0;
   std::mutex mu;
   Profiler prof;
-  std::map<int32_t, int32_t> tuned;            // size class -> K chosen by zpm_tune
+  TuneTable tuned;                             // size class -> choice of zpm_tune
   BatchState batch_eager, batch_graph;
   hipStream_t capture_stream = nullptr;        // graph capture only (default priority)
 
@@ -71,19 +77,22 @@ struct Ctx {
   int ensure_ws(int64_t words);
   int get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np, Plan *out);
   int prepare(const Plan &pl, DevState *ds);
-  int get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, Plan *out);
+  int get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force,
+                     int32_t T_force, Plan *out);
   // given: plans per job (from plan_for_batch) instead of the context's choice
   int schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHost &bh,
-                     const Plan *given = nullptr);
+                     const Plan *given = nullptr, int32_t T_force = 0);
   // ws_ext: workspace of ws_ext_words words to use instead of the state's own buffer
   int build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState &bs,
-                  const Plan *given = nullptr, uint32_t *ws_ext = nullptr, int64_t ws_ext_words = 0);
+                  const Plan *given = nullptr, uint32_t *ws_ext = nullptr, int64_t ws_ext_words = 0,
+                  int32_t T_force = 0);
   // sizes the descriptor buffers of bs for batches of up to `jobs` products and `segs`
   // segments, so that later batches within those bounds allocate nothing
   int reserve_batch(BatchState &bs, int64_t jobs, int64_t segs);
   int enqueue_batch(BatchState &bs, hipStream_t st);
-  int mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_force, hipStream_t st);
-  int tune(const zpm_job *sample, int64_t n, hipStream_t st, std::map<int32_t, int32_t> &out);
+  int mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_force, hipStream_t st,
+                int32_t T_force = 0);
+  int tune(const zpm_job *sample, int64_t n, hipStream_t st);
   ~Ctx();
 };
 

@@ -51,7 +51,7 @@ static int64_t col_tile_max() {
   return v;
 }
 
-static bool split_y(Plan &pl, int reg_k_max) {
+static bool split_y(Plan &pl, int reg_k_max, int col_tile) {
   const int logK = ceil_log2(pl.K);
   int logcap = 0;
   pl.conv_reg = pl.K <= reg_k_max ? 1 : 0;
@@ -76,7 +76,8 @@ static bool split_y(Plan &pl, int reg_k_max) {
     S >>= take;
     pl.col[c].S = S;
     // inner indices per workgroup: T * n <= LDS_WORDS, T <= S, T <= 64
-    int64_t T = std::min<int64_t>(S, std::min<int64_t>(col_tile_max(), LDS_WORDS >> take));
+    const int64_t want = col_tile > 0 ? col_tile : col_tile_max();
+    int64_t T = std::min<int64_t>(S, std::min<int64_t>(want, LDS_WORDS >> take));
     pl.col_tile[c] = (int32_t)std::max<int64_t>(T, 1);
   }
   return true;
@@ -178,7 +179,7 @@ bool make_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, 
       if (np > lim->np_max) continue;
     }
     pl.np = np;
-    if (!split_y(pl, lim->reg_k_max) || !finish(pl)) continue;
+    if (!split_y(pl, lim->reg_k_max, lim->col_tile) || !finish(pl)) continue;
     pl.cost = model_cost(pl);
     if (!found || pl.cost < best.cost) { best = pl; found = true; }
   }

@@ -10,6 +10,7 @@ struct PlanLimits {
   int32_t np_max = MAXNP;    // largest prime count
   int32_t k_max = 1 << 20;   // largest K
   int32_t reg_k_max = 32;    // largest K for the register x-transform kernel
+  int32_t col_tile = 0;      // widest column tile (power of two); 0 = the default
 };
 
 // K_force / np_force: 0 = choose; otherwise the plan must use that value.

@@ -252,7 +252,7 @@ struct Server {
 
   Ctx *cx = nullptr;                  // null for a simulated server
   std::unique_ptr<Exec> ex;
-  std::map<int32_t, int32_t> tuned;   // the context's tuned limb counts at creation
+  TuneTable tuned;                    // the context's tuned choices at creation
   zpm_server_config cfg;
   uint8_t *pool = nullptr;
   int64_t pool_bytes = 0;
@@ -306,7 +306,7 @@ int Server::plan_req(SReq &r) {
       // and products beyond the batch kernels run alone with the single-product plan
       Plan pl;
       bool batch = !cfg.single_product && !r.large &&
-                   plan_for_batch(tuned, j.da, j.Na, j.db, j.Nb, 0, &pl) == ZPM_OK;
+                   plan_for_batch(tuned, j.da, j.Na, j.db, j.Nb, 0, 0, &pl) == ZPM_OK;
       if (!batch) {
         const char *why = nullptr;
         if (!make_plan(j.da, j.Na, j.db, j.Nb, 0, 0, pl, &why, nullptr)) return ZPM_EUNSUPPORTED;
