@@ -41,12 +41,14 @@ int32_t out_bits(int64_t da, int32_t Na, int64_t db, int32_t Nb) {
 // Split of the y-transform: innermost factor L1 inside the fused kernel, the rest
 // into strided column passes of length <= 2^10 each.
 // Widest column tile of a strided pass (inner indices per workgroup); ZPM_COL_TILE
-// overrides the default of 16 (64-byte runs; more workgroups per CU beat longer runs).
+// overrides the default of 8.  Tiles sharing 128-byte lines run next to each other on
+// one XCD, so narrow tiles cost no extra HBM traffic, and more workgroups per CU beat
+// longer runs.
 static int64_t col_tile_max() {
   static const int64_t v = [] {
     const char *e = std::getenv("ZPM_COL_TILE");
     const long x = e ? std::atol(e) : 0;
-    return (int64_t)(x >= 1 && x <= 64 && !(x & (x - 1)) ? x : 16);
+    return (int64_t)(x >= 1 && x <= 64 && !(x & (x - 1)) ? x : 8);
   }();
   return v;
 }
@@ -124,9 +126,9 @@ static double model_cost(const Plan &pl) {
   bytes += 8.0 * (pl.da * ((pl.Na + 63) / 64) + pl.db * ((pl.Nb + 63) / 64) +
                   pl.nout * ((pl.nout_bits + 63) / 64));
   double t_alu = alu / 39.3e12, t_mem = bytes / 5.0e12;
-  // coalescing penalty for strided passes with narrow tiles
+  // strided passes with tiles narrower than 32 bytes waste part of each request
   for (int c = 0; c < pl.ncol; ++c)
-    if (pl.col_tile[c] < 16) t_mem *= 16.0 / pl.col_tile[c];
+    if (pl.col_tile[c] < 8) t_mem *= 8.0 / pl.col_tile[c];
   return t_alu + t_mem + 4e-6 * (4 + 3 * pl.ncol);
 }
 

@@ -69,12 +69,12 @@ int Ctx::tune(const zpm_job *sample, int64_t n, hipStream_t st) {
     TuneChoice best;
     for (int32_t K = 2; K <= 64 && rc == ZPM_OK; K *= 2) {
       int32_t last_tiles[MAX_COL_PASSES] = {-1, -1, -1, -1};
-      for (int32_t T : {16, 8, 32}) {
+      for (int32_t T : {8, 16, 32}) {
         Plan pl;
         if (get_plan_batch(rep.da, rep.Na, rep.db, rep.Nb, K, T, &pl) != ZPM_OK) continue;
         // a tile wider than a pass allows gives the plan of a narrower one: skip repeats
-        if (T != 16 && std::equal(pl.col_tile, pl.col_tile + MAX_COL_PASSES, last_tiles)) continue;
-        if (T == 16) std::copy(pl.col_tile, pl.col_tile + MAX_COL_PASSES, last_tiles);
+        if (std::equal(pl.col_tile, pl.col_tile + MAX_COL_PASSES, last_tiles)) continue;
+        std::copy(pl.col_tile, pl.col_tile + MAX_COL_PASSES, last_tiles);
         // first call captures the graph (and sizes tables and buffers); replays are timed
         if (mul_batch(reps.data(), R, ZPM_BATCH_GRAPH, K, st, T) != ZPM_OK) continue;
         float ms = 1e30f;
