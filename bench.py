@@ -84,6 +84,37 @@ def cpu_baseline(prod, target_s: float) -> dict:
     }
 
 
+KERNEL_SOURCES = ("stages.hpp", "kernels.hip", "kernels.hpp", "zpm_internal.hpp")
+
+
+def kernel_sources_sha256() -> str:
+    """Digest of the device sources of the single-product kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1612_05778_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(base, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<workload>_traffic.json: FETCH_SIZE x its copy-calibrated factor plus
+    WRITE_SIZE x its factor), or None when there is none or the kernel sources have
+    changed since the counters were taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    k = doc.get("kernels", {}).get(kernel)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
 def batch_leg(ctx, reps: int) -> dict:
     """The 4096-product batch (degree log-uniform in [63, 8191], magnitude bits
     log-uniform in [32, 2048], seed 4): one product at a time through zpm_mul against
@@ -386,12 +417,15 @@ def main() -> int:
     if d["ops"]:
         achieved = d["ops"] / (d["avg_ms"] / 1e3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_PEAK / 1e12,
-                "unit": "Tops/s (int32 VALU)", "frac": achieved / INT32_PEAK, "traffic": None,
+                "unit": "Tops/s (int32 VALU)", "frac": achieved / INT32_PEAK,
+                "traffic": measured_traffic(args.workload, dom), "traffic_unit": "bytes/launch",
+                "algorithmic_bytes": d["bytes"],
                 "kernel": dom}
     else:
         achieved = d["bytes"] / (d["avg_ms"] / 1e3)
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": None, "kernel": dom}
+                "frac": achieved / HBM_PEAK, "traffic": measured_traffic(args.workload, dom),
+                "traffic_unit": "bytes/launch", "algorithmic_bytes": d["bytes"], "kernel": dom}
     for v in kinfo.values():
         if v["ops"]:
             v["int32_Tops"] = v["ops"] / (v["avg_ms"] / 1e3) / 1e12

@@ -95,7 +95,11 @@ int zpm_create(zpm_ctx **out, int device);
 void zpm_destroy(zpm_ctx *ctx);
 
 /* c = a * b (the algorithm of Section 2.3).  `stream` is a hipStream_t (NULL =
- * default stream).  da or db == 0 gives an empty product (nothing written). */
+ * default stream).  da or db == 0 gives an empty product (nothing written).
+ * Passing one operand twice (b == a, db == da, Nb == Na) computes the square a^2
+ * with a single conversion and forward transform of a, whose spectra serve as both
+ * factors of the pointwise products (Section 2.1); the same holds for jobs of
+ * zpm_mul_batch and requests of a server. */
 int zpm_mul(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
             int64_t db, int32_t Nb, uint64_t *c, int32_t wc, void *stream);
 

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(BLOCK) void kg_convert(const JobDev *__restrict__ j
   const GroupSeg g = segs[find_seg(segs, nseg, blockIdx.x)];
   const JobDev &jb = jobs[g.job];
   const int64_t tile = (int64_t)blockIdx.x - g.start;
-  const bool ob = tile >= jb.tiles_a;      // tiles of a first, then tiles of b
+  const bool ob = tile >= jb.tiles_a;      // tiles of a first, then tiles of b (none for a square)
   const int32_t N = ob ? jb.Nb : jb.Na;
   body_convert_in<NP>(s, ob ? tile - jb.tiles_a : tile, ob ? jb.b : jb.a, ob ? jb.db : jb.da, N,
                       (N + 63) / 64, jb.K, jb.M, NP, jb.X, jb.L, ob ? jb.K : 0, jb.log_ti_in,
@@ -65,7 +65,8 @@ __global__ __launch_bounds__(BLOCK) void kg_col(const JobDev *__restrict__ jobs,
   const int64_t L = jb.L;
   body_col_pass(s, b - g.start, jb.X, L, 2 * jb.K, jb.col_logn[c], jb.col_S[c],
                 jb.col_logT[c], (outer && !inverse) ? jb.da : L, (outer && !inverse) ? jb.db : L,
-                jb.K, (outer && inverse) ? jb.nout : L, inverse, primes);
+                jb.K, (outer && inverse) ? jb.nout : L, inverse, primes,
+                (jb.square && !inverse) ? jb.K : 2 * jb.K);
 }
 
 template <int LOGK>
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(BLOCK) void kg_convolve_reg(const JobDev *__restric
   const int64_t L = jb.L;
   const bool direct = jb.ncol == 0;
   body_convolve_reg<LOGK>(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.logL1, direct ? jb.da : L,
-                          direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan);
+                          direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan, jb.square);
 }
 
 __global__ __launch_bounds__(BLOCK) void kg_convolve(const JobDev *__restrict__ jobs,
@@ -93,7 +94,8 @@ __global__ __launch_bounds__(BLOCK) void kg_convolve(const JobDev *__restrict__ 
   int logK = 0;
   while ((1 << logK) < jb.K) ++logK;
   body_convolve(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.K, logK, jb.logL1,
-                direct ? jb.da : L, direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan);
+                direct ? jb.da : L, direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan,
+                jb.square);
 }
 
 hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *segs,

@@ -27,7 +27,7 @@ struct JobDev {
   int64_t col_S[MAX_COL_PASSES];
   int32_t col_logn[MAX_COL_PASSES];
   int32_t col_logT[MAX_COL_PASSES];
-  int32_t Na, Nb, wc, K, M, np, logL, logL1, ncol, conv_reg, log_ti_in, log_ti_out, nw32, pad;
+  int32_t Na, Nb, wc, K, M, np, logL, logL1, ncol, conv_reg, log_ti_in, log_ti_out, nw32, square;
 };
 
 // A run of consecutive blocks of one grouped launch: all tiles of one stage of one

@@ -125,13 +125,14 @@ static int64_t stage_tiles(const Plan &pl, int kind, int pass) {
   switch (kind) {
     case SK_CONVERT: {
       const int64_t ti = (int64_t)1 << pl.log_ti_in;
-      return (pl.da + ti - 1) / ti + (pl.db + ti - 1) / ti;
+      return (pl.da + ti - 1) / ti + (pl.square ? 0 : (pl.db + ti - 1) / ti);
     }
     case SK_COL_FWD:
     case SK_COL_INV: {
       const int64_t S = pl.col[pass].S;
       const int64_t nn = (int64_t)1 << pl.col[pass].logn;
-      return (S / pl.col_tile[pass]) * (L / (nn * S)) * pl.np * 2 * pl.K;
+      const int64_t cols = (pl.square && kind == SK_COL_FWD) ? pl.K : 2 * pl.K;
+      return (S / pl.col_tile[pass]) * (L / (nn * S)) * pl.np * cols;
     }
     case SK_CONVOLVE:
       return (int64_t)pl.np * (L >> pl.logL1);
@@ -173,6 +174,8 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
     } else if ((rc = get_plan_batch(j.da, j.Na, j.db, j.Nb, K_force, T_force, &pls[i])) != ZPM_OK) {
       return rc;
     }
+    // one operand passed twice is transformed once
+    pls[i].square = (j.a && j.a == j.b && j.da == j.db && j.Na == j.Nb) ? 1 : 0;
     live[i] = 1;
     const Plan &pl = pls[i];
     bh.npmax = std::max(bh.npmax, pl.np);
@@ -191,7 +194,7 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
     jd.X = reinterpret_cast<uint32_t *>((uintptr_t)off);
     off += align_up(pl.ws_words, 64);
     jd.da = pl.da; jd.db = pl.db; jd.nout = pl.nout; jd.L = (int64_t)1 << pl.logL;
-    jd.tiles_a = (pl.da + (1 << pl.log_ti_in) - 1) >> pl.log_ti_in;
+    jd.tiles_a = (pl.da + (1 << pl.log_ti_in) - 1) >> pl.log_ti_in;   // b's tiles follow
     for (int c = 0; c < pl.ncol; ++c) {
       jd.col_S[c] = pl.col[c].S;
       jd.col_logn[c] = pl.col[c].logn;
@@ -203,6 +206,7 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
     jd.logL = pl.logL; jd.logL1 = pl.logL1; jd.ncol = pl.ncol; jd.conv_reg = pl.conv_reg;
     jd.log_ti_in = pl.log_ti_in; jd.log_ti_out = pl.log_ti_out;
     jd.nw32 = 2 * ((pl.nout_bits + 63) / 64);
+    jd.square = pl.square;
     slot[i] = (int32_t)bh.jobs.size();
     bh.jobs.push_back(jd);
     bh.job_plan.push_back((int32_t)i);

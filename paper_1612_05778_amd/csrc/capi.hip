@@ -255,6 +255,9 @@ int zpm_mul_ex(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const ui
   if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
   Plan pl;
   if ((rc = cx->get_plan(da, Na, db, Nb, K, np, &pl)) != ZPM_OK) return rc;
+  // c = a^2 when one operand is passed twice: it is converted and transformed once
+  // (stage dumps keep the documented layout with both operands' rows)
+  pl.square = (a == b && da == db && Na == Nb && !stop_after) ? 1 : 0;
   DevState ds;
   if ((rc = cx->prepare(pl, &ds)) != ZPM_OK) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);

@@ -43,27 +43,27 @@ __global__ __launch_bounds__(BLOCK) void k_bivariate_representation(
 __global__ __launch_bounds__(BLOCK) void k_col_pass(
     uint32_t *__restrict__ X, int64_t L, int32_t twoK, int32_t logn, int64_t S, int32_t logT,
     int64_t nz_a, int64_t nz_b, int32_t K, int64_t nlimit, int32_t inverse,
-    const PrimeDev *__restrict__ primes, int64_t nblocks) {
+    const PrimeDev *__restrict__ primes, int64_t nblocks, int32_t cols) {
   extern __shared__ uint32_t s[];
   const int64_t bid = xcd_tile(nblocks);
   if (bid >= nblocks) return;
-  body_col_pass(s, bid, X, L, twoK, logn, S, logT, nz_a, nz_b, K, nlimit, inverse, primes);
+  body_col_pass(s, bid, X, L, twoK, logn, S, logT, nz_a, nz_b, K, nlimit, inverse, primes, cols);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_convolve_rows(
     uint32_t *__restrict__ X, int64_t L, int32_t K, int32_t logK, int32_t logL1, int64_t nz_a,
     int64_t nz_b, int64_t nlimit, const PrimeDev *__restrict__ primes,
-    const PlanDev *__restrict__ pd) {
+    const PlanDev *__restrict__ pd, int32_t square) {
   extern __shared__ uint32_t s[];
-  body_convolve(s, blockIdx.x, X, L, K, logK, logL1, nz_a, nz_b, nlimit, primes, pd);
+  body_convolve(s, blockIdx.x, X, L, K, logK, logL1, nz_a, nz_b, nlimit, primes, pd, square);
 }
 
 template <int LOGK>
 __global__ __launch_bounds__(BLOCK) void k_convolve_rows_reg(
     uint32_t *__restrict__ X, int64_t L, int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
-    const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd) {
+    const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd, int32_t square) {
   extern __shared__ uint32_t s[];
-  body_convolve_reg<LOGK>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd);
+  body_convolve_reg<LOGK>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd, square);
 }
 
 template <int NP>
@@ -119,14 +119,16 @@ hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, h
   const int T = pl.col_tile[c];
   const int logT = ilog2(T);
   const int64_t tiles = (S >> logT) * (L / (((int64_t)1 << logn) * S));
-  const int64_t blocks = tiles * pl.np * 2 * pl.K;
+  const int32_t cols = (pl.square && !inverse) ? pl.K : 2 * pl.K;   // a square: a's limbs only
+  const int64_t blocks = tiles * pl.np * cols;
   const size_t lds = sizeof(uint32_t) * ((size_t)T << logn);
   const int64_t nz_a = (c == 0 && !inverse) ? pl.da : L;
   const int64_t nz_b = (c == 0 && !inverse) ? pl.db : L;
   const int64_t nlimit = (c == 0 && inverse) ? pl.nout : L;
   const int64_t grid = 8 * ((blocks + 7) / 8);   // xcd_tile's shape
   hipLaunchKernelGGL(k_col_pass, dim3((unsigned)grid), dim3(BLOCK), lds, st, ds.X, L, 2 * pl.K,
-                     logn, S, logT, nz_a, nz_b, pl.K, nlimit, inverse ? 1 : 0, ds.primes, blocks);
+                     logn, S, logT, nz_a, nz_b, pl.K, nlimit, inverse ? 1 : 0, ds.primes, blocks,
+                     cols);
   return hipGetLastError();
 }
 
@@ -139,7 +141,7 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st) {
     const size_t lds = sizeof(uint32_t) * (size_t)(2 * pl.K) * (((size_t)1 << pl.logL1) + 1);
 #define ZPM_CONV(LK_)                                                                           \
   hipLaunchKernelGGL(k_convolve_rows_reg<LK_>, dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, \
-                     L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan)
+                     L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, pl.square)
     switch (ilog2(pl.K)) {
       case 1: ZPM_CONV(1); break;
       case 2: ZPM_CONV(2); break;
@@ -152,7 +154,7 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st) {
   }
   const size_t lds = sizeof(uint32_t) * (size_t)4 * pl.K << pl.logL1;
   hipLaunchKernelGGL(k_convolve_rows, dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, L, pl.K,
-                     ilog2(pl.K), pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan);
+                     ilog2(pl.K), pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, pl.square);
   return hipGetLastError();
 }
 
@@ -187,10 +189,12 @@ hipError_t launch_mul(const Plan &pl, const DevState &ds, const uint64_t *a, con
   e = launch_convert_in(pl, ds, a, pl.da, pl.Na, 0, st);
   pr.end(st);
   if (e != hipSuccess) return e;
-  pr.begin(KK_CONVERT_IN, st);
-  e = launch_convert_in(pl, ds, b, pl.db, pl.Nb, pl.K, st);
-  pr.end(st);
-  if (e != hipSuccess) return e;
+  if (!pl.square) {    // a square transforms its one operand once
+    pr.begin(KK_CONVERT_IN, st);
+    e = launch_convert_in(pl, ds, b, pl.db, pl.Nb, pl.K, st);
+    pr.end(st);
+    if (e != hipSuccess) return e;
+  }
   if (stop_after == 1) return hipSuccess;
   for (int cidx = 0; cidx < pl.ncol; ++cidx) {
     pr.begin(KK_COL_FWD, st);

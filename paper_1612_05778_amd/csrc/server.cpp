@@ -317,6 +317,7 @@ int Server::plan_req(SReq &r) {
       r.batch = batch;
     }
   }
+  r.plan.square = (j.a == j.b && j.da == j.db && j.Na == j.Nb) ? 1 : 0;
   r.bytes = align_up(r.plan.ws_words, 64) * 4;
   return ZPM_OK;
 }

@@ -312,20 +312,23 @@ __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__
 // meets the frequencies k = e0, e0 + de, ... of one column, so its twiddles form a
 // geometric progression kept in Montgomery form (no table gathers).
 // ------------------------------------------------------------------------------------
+// cols: columns transformed per prime, the first `cols` of each prime's 2K (K when
+// only a's limbs need a forward transform, for a square).
 __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
                               int32_t twoK, int32_t logn, int64_t S, int32_t logT, int64_t nz_a,
                               int64_t nz_b, int32_t K, int64_t nlimit, int32_t inverse,
-                              const PrimeDev *__restrict__ primes) {
+                              const PrimeDev *__restrict__ primes, int32_t cols) {
   const int n = 1 << logn, T = 1 << logT;
   const int64_t inner_tiles = S >> logT;
   const int64_t outers = L / ((int64_t)n * S);
   const int64_t tiles = inner_tiles * outers;
-  const int64_t col = bid / tiles;
-  const int64_t tile = bid - col * tiles;
+  const int64_t cidx = bid / tiles;
+  const int64_t tile = bid - cidx * tiles;
   const int64_t outer = tile / inner_tiles;
   const int64_t inner0 = (tile - outer * inner_tiles) << logT;
-  const int k = (int)(col / twoK);
-  const int jc = (int)(col - (int64_t)k * twoK);
+  const int k = (int)(cidx / cols);
+  const int jc = (int)(cidx - (int64_t)k * cols);
+  const int64_t col = (int64_t)k * twoK + jc;
   const PrimeDev pr = primes[k];
   const uint32_t p = pr.p;
   const int64_t first = inner0 + S * (int64_t)n * outer;   // y index of (t = 0, e = 0)
@@ -394,7 +397,7 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
 __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
                               int32_t K, int32_t logK, int32_t logL1, int64_t nz_a, int64_t nz_b,
                               int64_t nlimit, const PrimeDev *__restrict__ primes,
-                              const PlanDev *__restrict__ pd) {
+                              const PlanDev *__restrict__ pd, int32_t square) {
   const int L1 = 1 << logL1;
   const int64_t nrb = L >> logL1;
   const int k = (int)(bid / nrb);
@@ -410,18 +413,22 @@ __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     const int j = idx >> logL1, e = idx & (L1 - 1);
     return (y0 + e < nz_a) ? base[(int64_t)j * L + e] : 0u;
   }, [&](int idx, uint32_t v) { A[idx] = v; A[(K << logL1) + idx] = 0u; });
-  staged<8, uint32_t>(K << logL1, [&](int idx) {
-    const int j = idx >> logL1, e = idx & (L1 - 1);
-    return (y0 + e < nz_b) ? base[(int64_t)(K + j) * L + e] : 0u;
-  }, [&](int idx, uint32_t v) { B[idx] = v; B[(K << logL1) + idx] = 0u; });
+  if (!square) {
+    staged<8, uint32_t>(K << logL1, [&](int idx) {
+      const int j = idx >> logL1, e = idx & (L1 - 1);
+      return (y0 + e < nz_b) ? base[(int64_t)(K + j) * L + e] : 0u;
+    }, [&](int idx, uint32_t v) { B[idx] = v; B[(K << logL1) + idx] = 0u; });
+  }
   __syncthreads();
-  // innermost y factor on the K limb rows of both operands
-  lds_dif(s, LdsShape{logK, logL1, L1, 1, twoK * L1, 1}, pr.hf, p);
+  // innermost y factor on the K limb rows of both operands (of a alone for a square)
+  const int ops = square ? 0 : 1;
+  lds_dif(s, LdsShape{logK, logL1, L1, 1, twoK * L1, ops}, pr.hf, p);
   // x: 2K-point transforms down the L1 columns of both operands
-  lds_dif(s, LdsShape{logL1, logK + 1, 1, L1, twoK * L1, 1}, pr.hf, p);
+  lds_dif(s, LdsShape{logL1, logK + 1, 1, L1, twoK * L1, ops}, pr.hf, p);
   const uint2 sc = pd->scale[k];
+  const uint32_t *F = square ? A : B;
   for (int idx = threadIdx.x; idx < (twoK << logL1); idx += BLOCK)
-    A[idx] = mul_shoup(mont_mul(A[idx], B[idx], p, pr.pinv), sc, p);
+    A[idx] = mul_shoup(mont_mul(A[idx], F[idx], p, pr.pinv), sc, p);
   __syncthreads();
   lds_dit(s, LdsShape{logL1, logK + 1, 1, L1, 0, 0}, pr.hi, p);
   lds_dit(s, LdsShape{logK + 1, logL1, L1, 1, 0, 0}, pr.hi, p);
@@ -480,7 +487,7 @@ template <int LOGK>
 __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
                                   int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
                                   const PrimeDev *__restrict__ primes,
-                                  const PlanDev *__restrict__ pd) {
+                                  const PlanDev *__restrict__ pd, int32_t square) {
   constexpr int K = 1 << LOGK, K2 = 2 * K;
   const int L1 = 1 << logL1, RS = L1 + 1;      // odd row stride: rows fall on distinct banks
   const int64_t nrb = L >> logL1;
@@ -490,16 +497,31 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
   const uint32_t p = pr.p;
   uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
   const int64_t y0 = rb * L1;
-  // rows 0..K-1: limbs of a; rows K..2K-1: limbs of b
-  staged<8, uint32_t>(K2 << logL1, [&](int idx) {
+  // rows 0..K-1: limbs of a; rows K..2K-1: limbs of b (absent for a square)
+  const int rows = square ? K : K2;
+  staged<8, uint32_t>(rows << logL1, [&](int idx) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
     const int64_t nz = j < K ? nz_a : nz_b;
     return (y0 + e < nz) ? base[(int64_t)j * L + e] : 0u;
   }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
   __syncthreads();
-  lds_dif(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
+  lds_dif(s, LdsShape{square ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
   const uint2 sc = pd->scale[k];
-  for (int e = threadIdx.x; e < L1; e += BLOCK) {
+  if (square) {
+    // one transform per column, multiplied by itself
+    for (int e = threadIdx.x; e < L1; e += BLOCK) {
+      uint32_t a[K2];
+#pragma unroll
+      for (int j = 0; j < K; ++j) a[j] = s[j * RS + e];
+      reg_dif<LOGK>(a, pr.hf, p);
+#pragma unroll
+      for (int j = 0; j < K2; ++j) a[j] = mul_shoup(mont_mul(a[j], a[j], p, pr.pinv), sc, p);
+      reg_dit<LOGK>(a, pr.hi, p);
+#pragma unroll
+      for (int j = 0; j < K2; ++j) s[j * RS + e] = a[j];
+    }
+  }
+  for (int e = threadIdx.x; !square && e < L1; e += BLOCK) {
     // the column of a is transformed and parked back in LDS (this thread owns column e)
     // before b is transformed, so that at most 3K values are live in registers
     uint32_t b[K2];

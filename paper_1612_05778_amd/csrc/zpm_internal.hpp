@@ -65,6 +65,7 @@ struct Plan {
   int32_t logL;        // L = 2^logL >= da + db - 1, the cyclic length along y
   int32_t logL1;       // innermost y factor handled inside the fused convolution kernel
   int32_t conv_reg;    // 1: x-transforms in registers (K <= 32), 0: in LDS
+  int32_t square;      // 1: a and b are one operand, transformed once (c = a^2)
   int32_t ncol;        // number of strided column passes (outermost first)
   ColPass col[MAX_COL_PASSES];
   int32_t col_tile[MAX_COL_PASSES];  // inner indices per workgroup of each column pass
