@@ -442,6 +442,30 @@ def main() -> int:
         "roofline": roof,
         "kernels": kinfo,
     }
+    # the same workload squared (a passed twice): one conversion and forward transform
+    sq = ctx.mul(a, prod.Na, a, prod.Na)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.mul(a, prod.Na, a, prod.Na, out=sq)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sq_ms = e0.elapsed_time(e1) / args.steps
+    line["square"] = {"ms": sq_ms, "value": bits / (sq_ms / 1e3), "vs_product": ms / sq_ms}
+    del sq
+    # b transformed once (resident operand), then products with a
+    from paper_1612_05778_amd.api import Operand
+    op = Operand(ctx, b, prod.Nb, prod.da, prod.Na)
+    op.mul(a, prod.Na, out=out)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        op.mul(a, prod.Na, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    op_ms = e0.elapsed_time(e1) / args.steps
+    line["resident_operand"] = {"ms": op_ms, "value": bits / (op_ms / 1e3), "vs_product": ms / op_ms}
+    op.close()
     if not args.no_batch:
         line["batched"] = batch_leg(ctx, args.batch_reps)
     if not args.no_served:

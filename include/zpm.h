@@ -255,6 +255,26 @@ int zpm_server_reset_stats(zpm_server *srv);
 /* Finishes every submitted request, stops the worker and frees the pool. */
 void zpm_server_destroy(zpm_server *srv);
 
+/* Resident operand (one factor transformed once, for many products).
+ * zpm_operand_create converts b and runs its forward transforms (Section 2.1:
+ * BivariateRepresentation, then the y and x transforms of CyclicConvolution and
+ * NegacyclicConvolution) under the plan for (da_max, Na_max, db, Nb), and keeps its
+ * np * 2K * L spectra in device memory owned by the operand (K = 0 lets the planner
+ * choose).  zpm_mul_operand then computes c = a * b for any a with da <= da_max and
+ * Na <= Na_max with a's conversion and transforms only (ZPM_EINVAL beyond the
+ * bounds); c, wc and the stream rules are as for zpm_mul.  b must stay allocated and
+ * unchanged while the operand exists (its words are not read again, but c may not
+ * overlap them).  The operand belongs to the context that created it; it must be
+ * destroyed after the products that use it have completed and before the context.
+ * zpm_operand_info reports its plan. */
+typedef struct zpm_operand zpm_operand;
+int zpm_operand_create(zpm_ctx *ctx, const uint64_t *b, int64_t db, int32_t Nb, int64_t da_max,
+                       int32_t Na_max, int32_t K, zpm_operand **out, void *stream);
+int zpm_mul_operand(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const zpm_operand *op,
+                    uint64_t *c, int32_t wc, void *stream);
+int zpm_operand_info(const zpm_operand *op, zpm_plan_info *out);
+void zpm_operand_destroy(zpm_operand *op);
+
 /* Wait for the stream and report any device error raised by earlier calls. */
 int zpm_sync(zpm_ctx *ctx, void *stream);
 

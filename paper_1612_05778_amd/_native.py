@@ -149,6 +149,13 @@ zpm_server_stats = _sig("zpm_server_stats", ctypes.c_int, [c_vp, ctypes.POINTER(
 zpm_server_reset_stats = _sig("zpm_server_reset_stats", ctypes.c_int, [c_vp])
 zpm_server_destroy = _sig("zpm_server_destroy", None, [c_vp])
 
+zpm_operand_create = _sig("zpm_operand_create", ctypes.c_int,
+                          [c_vp, c_vp, c_i64, c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(c_vp), c_vp])
+zpm_mul_operand = _sig("zpm_mul_operand", ctypes.c_int,
+                       [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp])
+zpm_operand_info = _sig("zpm_operand_info", ctypes.c_int, [c_vp, ctypes.POINTER(PlanInfo)])
+zpm_operand_destroy = _sig("zpm_operand_destroy", None, [c_vp])
+
 EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
            "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync",
            "zpm_profile_begin", "zpm_profile_end", "zpm_mul_batch", "zpm_mul_batch_ex",
@@ -156,7 +163,8 @@ EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime
            "zpm_tune_get", "zpm_server_create", "zpm_server_create_ex",
            "zpm_server_create_simulated", "zpm_server_submit", "zpm_server_poll",
            "zpm_server_wait", "zpm_server_completions", "zpm_server_stats",
-           "zpm_server_reset_stats", "zpm_server_destroy"]
+           "zpm_server_reset_stats", "zpm_server_destroy", "zpm_operand_create",
+           "zpm_mul_operand", "zpm_operand_info", "zpm_operand_destroy"]
 
 
 class ZpmError(RuntimeError):

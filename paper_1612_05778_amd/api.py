@@ -202,6 +202,50 @@ class Context:
         nat.check(nat.zpm_sync(self._h, _stream_handle(stream)), "zpm_sync")
 
 
+class Operand:
+    """A factor b transformed once (zpm_operand_*), for products a * b with any a of
+    at most da_max coefficients and Na_max bits.  Keeps a reference to b."""
+
+    def __init__(self, ctx: Context, b: torch.Tensor, Nb: int, da_max: int, Na_max: int,
+                 K: int = 0, stream=None):
+        db = _check_operand(b, Nb, "b")
+        h = nat.c_vp()
+        nat.check(nat.zpm_operand_create(ctx.handle, b.data_ptr(), db, Nb, da_max, Na_max, K,
+                                         ctypes.byref(h), _stream_handle(stream)),
+                  "zpm_operand_create")
+        self._h, self._ctx, self._b = h, ctx, b
+        self.db, self.Nb = db, Nb
+
+    def info(self) -> dict:
+        info = nat.PlanInfo()
+        nat.check(nat.zpm_operand_info(self._h, ctypes.byref(info)), "zpm_operand_info")
+        return info.as_dict()
+
+    def mul(self, a: torch.Tensor, Na: int, out: torch.Tensor | None = None,
+            stream=None) -> torch.Tensor:
+        """c = a * b as a (da + db - 1, wc) int64 tensor."""
+        da = _check_operand(a, Na, "a")
+        n = da + self.db - 1 if da else 0
+        wc = out_words(da, Na, self.db, self.Nb) if n else 1
+        if out is None:
+            out = torch.empty((n, wc), dtype=torch.int64, device=a.device)
+        nat.check(nat.zpm_mul_operand(self._ctx.handle, a.data_ptr(), da, Na, self._h,
+                                      out.data_ptr() if n else None, out.shape[1] if n else wc,
+                                      _stream_handle(stream)), "zpm_mul_operand")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            nat.zpm_operand_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Continuous-batching server over a context (see zpm_server_* in include/zpm.h).
 

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(BLOCK) void kg_col(const JobDev *__restrict__ jobs,
   body_col_pass(s, b - g.start, jb.X, L, 2 * jb.K, jb.col_logn[c], jb.col_S[c],
                 jb.col_logT[c], (outer && !inverse) ? jb.da : L, (outer && !inverse) ? jb.db : L,
                 jb.K, (outer && inverse) ? jb.nout : L, inverse, primes,
-                (jb.square && !inverse) ? jb.K : 2 * jb.K);
+                (jb.square && !inverse) ? jb.K : 2 * jb.K, 0);
 }
 
 template <int LOGK>
@@ -80,7 +80,8 @@ __global__ __launch_bounds__(BLOCK) void kg_convolve_reg(const JobDev *__restric
   const int64_t L = jb.L;
   const bool direct = jb.ncol == 0;
   body_convolve_reg<LOGK>(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.logL1, direct ? jb.da : L,
-                          direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan, jb.square);
+                          direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan,
+                          jb.square ? CM_SQUARE : CM_PRODUCT, nullptr);
 }
 
 __global__ __launch_bounds__(BLOCK) void kg_convolve(const JobDev *__restrict__ jobs,
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(BLOCK) void kg_convolve(const JobDev *__restrict__ 
   while ((1 << logK) < jb.K) ++logK;
   body_convolve(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.K, logK, jb.logL1,
                 direct ? jb.da : L, direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan,
-                jb.square);
+                jb.square ? CM_SQUARE : CM_PRODUCT, nullptr);
 }
 
 hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *segs,

@@ -318,6 +318,109 @@ int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t
   return rc;
 }
 
+// A resident operand: b's spectra under a plan sized for products with any a of at
+// most da_max coefficients and Na_max bits.
+struct zpm_operand {
+  Ctx *cx;
+  Plan pl;             // plan for (da_max, Na_max, db, Nb)
+  uint32_t *spec;      // np * 2K * L words: b's forward transforms
+  const uint64_t *b;   // the operand's words, for the overlap check only
+  int64_t db, da_max;
+  int32_t Nb, Na_max;
+};
+
+int zpm_operand_create(zpm_ctx *ctx, const uint64_t *b, int64_t db, int32_t Nb, int64_t da_max,
+                       int32_t Na_max, int32_t K, zpm_operand **out, void *stream) {
+  if (!ctx || !b || !out || db < 1 || Nb < 1 || da_max < 1 || Na_max < 1 || K < 0)
+    return ZPM_EINVAL;
+  *out = nullptr;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  std::lock_guard<std::mutex> lock(cx->mu);
+  if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  int rc;
+  Plan pl;
+  if ((rc = cx->get_plan(da_max, Na_max, db, Nb, K, 0, &pl)) != ZPM_OK) return rc;
+  const int64_t H = std::max<int64_t>((int64_t)1 << pl.logL, 2 * (int64_t)pl.K);
+  if ((rc = cx->ensure_tables(pl.np, H, (pl.M + 31) / 32 + 1)) != ZPM_OK) return rc;
+  PlanDev *pd = nullptr;
+  if ((rc = cx->plan_consts(pl, &pd)) != ZPM_OK) return rc;
+  zpm_operand *op = new zpm_operand();
+  op->cx = cx;
+  op->pl = pl;
+  op->b = b;
+  op->db = db;
+  op->Nb = Nb;
+  op->da_max = da_max;
+  op->Na_max = Na_max;
+  if (hipMalloc(&op->spec, (size_t)pl.ws_words * 4) != hipSuccess) {
+    delete op;
+    return ZPM_ENOMEM;
+  }
+  DevState ds;
+  ds.X = op->spec;
+  ds.primes = cx->primes;
+  ds.plan = pd;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // b's limbs into rows K..2K-1, their forward column passes, then the spectra
+  bool ok = launch_convert_in(pl, ds, b, db, Nb, pl.K, st) == hipSuccess;
+  for (int c = 0; ok && c < pl.ncol; ++c) ok = launch_col(pl, ds, c, false, st, pl.K, pl.K) == hipSuccess;
+  ok = ok && launch_convolve(pl, ds, st, CM_SPECTRUM) == hipSuccess;
+  if (!ok) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(op->spec);
+    delete op;
+    return ZPM_EDEVICE;
+  }
+  *out = op;
+  return ZPM_OK;
+}
+
+int zpm_mul_operand(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const zpm_operand *op,
+                    uint64_t *c, int32_t wc, void *stream) {
+  if (!ctx || !op || reinterpret_cast<Ctx *>(ctx) != op->cx) return ZPM_EINVAL;
+  if (da > op->da_max || Na > op->Na_max) return ZPM_EINVAL;
+  int rc = check_mul_args(a, da, Na, op->b, op->db, op->Nb, c, wc);
+  if (rc != ZPM_OK) return rc;
+  if (da == 0) return ZPM_OK;
+  Ctx *cx = op->cx;
+  std::lock_guard<std::mutex> lock(cx->mu);
+  if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  // the operand's plan, for this a: K, M, np and L are fixed by the bounds
+  Plan pl = op->pl;
+  pl.da = da;
+  pl.Na = Na;
+  pl.nout = da + op->db - 1;
+  pl.nout_bits = out_bits(da, Na, op->db, op->Nb);
+  pl.square = 0;
+  PlanDev *pd = nullptr;
+  if ((rc = cx->plan_consts(pl, &pd)) != ZPM_OK) return rc;
+  if ((rc = cx->ensure_ws(pl.ws_words)) != ZPM_OK) return rc;
+  DevState ds;
+  ds.X = cx->ws;
+  ds.primes = cx->primes;
+  ds.plan = pd;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  bool ok = launch_convert_in(pl, ds, a, da, Na, 0, st) == hipSuccess;
+  for (int k = 0; ok && k < pl.ncol; ++k) ok = launch_col(pl, ds, k, false, st, pl.K, 0) == hipSuccess;
+  ok = ok && launch_convolve(pl, ds, st, CM_WITH_SPECTRUM, op->spec) == hipSuccess;
+  for (int k = pl.ncol - 1; ok && k >= 0; --k) ok = launch_col(pl, ds, k, true, st) == hipSuccess;
+  ok = ok && launch_recover(pl, ds, c, wc, st) == hipSuccess;
+  return ok ? ZPM_OK : ZPM_EDEVICE;
+}
+
+int zpm_operand_info(const zpm_operand *op, zpm_plan_info *out) {
+  if (!op || !out) return ZPM_EINVAL;
+  fill_info(op->pl, out);
+  return ZPM_OK;
+}
+
+void zpm_operand_destroy(zpm_operand *op) {
+  if (!op) return;
+  (void)hipSetDevice(op->cx->device);
+  if (op->spec) (void)hipFree(op->spec);
+  delete op;
+}
+
 int zpm_sync(zpm_ctx *ctx, void *stream) {
   if (!ctx) return ZPM_EINVAL;
   Ctx *cx = reinterpret_cast<Ctx *>(ctx);

@@ -43,27 +43,29 @@ __global__ __launch_bounds__(BLOCK) void k_bivariate_representation(
 __global__ __launch_bounds__(BLOCK) void k_col_pass(
     uint32_t *__restrict__ X, int64_t L, int32_t twoK, int32_t logn, int64_t S, int32_t logT,
     int64_t nz_a, int64_t nz_b, int32_t K, int64_t nlimit, int32_t inverse,
-    const PrimeDev *__restrict__ primes, int64_t nblocks, int32_t cols) {
+    const PrimeDev *__restrict__ primes, int64_t nblocks, int32_t cols, int32_t col0) {
   extern __shared__ uint32_t s[];
   const int64_t bid = xcd_tile(nblocks);
   if (bid >= nblocks) return;
-  body_col_pass(s, bid, X, L, twoK, logn, S, logT, nz_a, nz_b, K, nlimit, inverse, primes, cols);
+  body_col_pass(s, bid, X, L, twoK, logn, S, logT, nz_a, nz_b, K, nlimit, inverse, primes, cols,
+                col0);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_convolve_rows(
     uint32_t *__restrict__ X, int64_t L, int32_t K, int32_t logK, int32_t logL1, int64_t nz_a,
     int64_t nz_b, int64_t nlimit, const PrimeDev *__restrict__ primes,
-    const PlanDev *__restrict__ pd, int32_t square) {
+    const PlanDev *__restrict__ pd, int32_t mode, const uint32_t *__restrict__ spec) {
   extern __shared__ uint32_t s[];
-  body_convolve(s, blockIdx.x, X, L, K, logK, logL1, nz_a, nz_b, nlimit, primes, pd, square);
+  body_convolve(s, blockIdx.x, X, L, K, logK, logL1, nz_a, nz_b, nlimit, primes, pd, mode, spec);
 }
 
 template <int LOGK>
 __global__ __launch_bounds__(BLOCK) void k_convolve_rows_reg(
     uint32_t *__restrict__ X, int64_t L, int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
-    const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd, int32_t square) {
+    const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd, int32_t mode,
+    const uint32_t *__restrict__ spec) {
   extern __shared__ uint32_t s[];
-  body_convolve_reg<LOGK>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd, square);
+  body_convolve_reg<LOGK>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd, mode, spec);
 }
 
 template <int NP>
@@ -112,14 +114,17 @@ hipError_t launch_convert_in(const Plan &pl, const DevState &ds, const uint64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, hipStream_t st) {
+hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, hipStream_t st,
+                      int32_t fwd_cols, int32_t col0) {
   const int64_t L = (int64_t)1 << pl.logL;
   const int logn = pl.col[c].logn;
   const int64_t S = pl.col[c].S;
   const int T = pl.col_tile[c];
   const int logT = ilog2(T);
   const int64_t tiles = (S >> logT) * (L / (((int64_t)1 << logn) * S));
-  const int32_t cols = (pl.square && !inverse) ? pl.K : 2 * pl.K;   // a square: a's limbs only
+  // forward passes of a square cover a's limbs only; fwd_cols / col0 select other sets
+  const int32_t cols = inverse ? 2 * pl.K : (fwd_cols ? fwd_cols : (pl.square ? pl.K : 2 * pl.K));
+  if (inverse) col0 = 0;
   const int64_t blocks = tiles * pl.np * cols;
   const size_t lds = sizeof(uint32_t) * ((size_t)T << logn);
   const int64_t nz_a = (c == 0 && !inverse) ? pl.da : L;
@@ -128,11 +133,13 @@ hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, h
   const int64_t grid = 8 * ((blocks + 7) / 8);   // xcd_tile's shape
   hipLaunchKernelGGL(k_col_pass, dim3((unsigned)grid), dim3(BLOCK), lds, st, ds.X, L, 2 * pl.K,
                      logn, S, logT, nz_a, nz_b, pl.K, nlimit, inverse ? 1 : 0, ds.primes, blocks,
-                     cols);
+                     cols, col0);
   return hipGetLastError();
 }
 
-hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st) {
+hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, int32_t mode,
+                           const uint32_t *spec) {
+  if (mode < 0) mode = pl.square ? CM_SQUARE : CM_PRODUCT;
   const int64_t L = (int64_t)1 << pl.logL;
   const int64_t blocks = (int64_t)pl.np * (L >> pl.logL1);
   const bool direct = pl.ncol == 0;
@@ -141,7 +148,7 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st) {
     const size_t lds = sizeof(uint32_t) * (size_t)(2 * pl.K) * (((size_t)1 << pl.logL1) + 1);
 #define ZPM_CONV(LK_)                                                                           \
   hipLaunchKernelGGL(k_convolve_rows_reg<LK_>, dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, \
-                     L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, pl.square)
+                     L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, mode, spec)
     switch (ilog2(pl.K)) {
       case 1: ZPM_CONV(1); break;
       case 2: ZPM_CONV(2); break;
@@ -154,7 +161,7 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st) {
   }
   const size_t lds = sizeof(uint32_t) * (size_t)4 * pl.K << pl.logL1;
   hipLaunchKernelGGL(k_convolve_rows, dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, L, pl.K,
-                     ilog2(pl.K), pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, pl.square);
+                     ilog2(pl.K), pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, mode, spec);
   return hipGetLastError();
 }
 

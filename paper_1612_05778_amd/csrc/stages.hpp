@@ -312,12 +312,13 @@ __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__
 // meets the frequencies k = e0, e0 + de, ... of one column, so its twiddles form a
 // geometric progression kept in Montgomery form (no table gathers).
 // ------------------------------------------------------------------------------------
-// cols: columns transformed per prime, the first `cols` of each prime's 2K (K when
-// only a's limbs need a forward transform, for a square).
+// cols: columns transformed per prime, those from col0 on among each prime's 2K (K of
+// them when only one operand's limbs need a forward transform: a square, or one
+// operand of a product with a resident transform).
 __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
                               int32_t twoK, int32_t logn, int64_t S, int32_t logT, int64_t nz_a,
                               int64_t nz_b, int32_t K, int64_t nlimit, int32_t inverse,
-                              const PrimeDev *__restrict__ primes, int32_t cols) {
+                              const PrimeDev *__restrict__ primes, int32_t cols, int32_t col0) {
   const int n = 1 << logn, T = 1 << logT;
   const int64_t inner_tiles = S >> logT;
   const int64_t outers = L / ((int64_t)n * S);
@@ -327,7 +328,7 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   const int64_t outer = tile / inner_tiles;
   const int64_t inner0 = (tile - outer * inner_tiles) << logT;
   const int k = (int)(cidx / cols);
-  const int jc = (int)(cidx - (int64_t)k * cols);
+  const int jc = col0 + (int)(cidx - (int64_t)k * cols);
   const int64_t col = (int64_t)k * twoK + jc;
   const PrimeDev pr = primes[k];
   const uint32_t p = pr.p;
@@ -397,7 +398,8 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
 __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
                               int32_t K, int32_t logK, int32_t logL1, int64_t nz_a, int64_t nz_b,
                               int64_t nlimit, const PrimeDev *__restrict__ primes,
-                              const PlanDev *__restrict__ pd, int32_t square) {
+                              const PlanDev *__restrict__ pd, int32_t mode,
+                              const uint32_t *__restrict__ spec) {
   const int L1 = 1 << logL1;
   const int64_t nrb = L >> logL1;
   const int k = (int)(bid / nrb);
@@ -409,24 +411,40 @@ __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   uint32_t *B = s + twoK * L1;          // 2K rows x L1
   uint32_t *base = X + (int64_t)k * twoK * L + rb * L1;
   const int64_t y0 = rb * L1;
+  // A: a's limb rows (b's for CM_SPECTRUM); the upper K rows are the zero padding
+  const int src_a = mode == CM_SPECTRUM ? K : 0;
+  const int64_t nz_first = mode == CM_SPECTRUM ? nz_b : nz_a;
   staged<8, uint32_t>(K << logL1, [&](int idx) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
-    return (y0 + e < nz_a) ? base[(int64_t)j * L + e] : 0u;
+    return (y0 + e < nz_first) ? base[(int64_t)(src_a + j) * L + e] : 0u;
   }, [&](int idx, uint32_t v) { A[idx] = v; A[(K << logL1) + idx] = 0u; });
-  if (!square) {
+  if (mode == CM_PRODUCT) {
     staged<8, uint32_t>(K << logL1, [&](int idx) {
       const int j = idx >> logL1, e = idx & (L1 - 1);
       return (y0 + e < nz_b) ? base[(int64_t)(K + j) * L + e] : 0u;
     }, [&](int idx, uint32_t v) { B[idx] = v; B[(K << logL1) + idx] = 0u; });
+  } else if (mode == CM_WITH_SPECTRUM) {
+    // b's spectra, in the order the forward transforms below leave A in
+    const uint32_t *sb = spec + (int64_t)k * twoK * L + rb * L1;
+    staged<8, uint32_t>(twoK << logL1, [&](int idx) {
+      return sb[(int64_t)(idx >> logL1) * L + (idx & (L1 - 1))];
+    }, [&](int idx, uint32_t v) { B[idx] = v; });
   }
   __syncthreads();
-  // innermost y factor on the K limb rows of both operands (of a alone for a square)
-  const int ops = square ? 0 : 1;
+  // innermost y factor on the K limb rows of both operands (of one operand otherwise)
+  const int ops = mode == CM_PRODUCT ? 1 : 0;
   lds_dif(s, LdsShape{logK, logL1, L1, 1, twoK * L1, ops}, pr.hf, p);
-  // x: 2K-point transforms down the L1 columns of both operands
+  // x: 2K-point transforms down the L1 columns
   lds_dif(s, LdsShape{logL1, logK + 1, 1, L1, twoK * L1, ops}, pr.hf, p);
+  if (mode == CM_SPECTRUM) {
+    // this block's positions only, all read above: the spectra replace the limbs
+    staged<8, uint32_t>(twoK << logL1, [&](int idx) { return A[idx]; }, [&](int idx, uint32_t v) {
+      base[(int64_t)(idx >> logL1) * L + (idx & (L1 - 1))] = v;
+    });
+    return;
+  }
   const uint2 sc = pd->scale[k];
-  const uint32_t *F = square ? A : B;
+  const uint32_t *F = mode == CM_SQUARE ? A : B;
   for (int idx = threadIdx.x; idx < (twoK << logL1); idx += BLOCK)
     A[idx] = mul_shoup(mont_mul(A[idx], F[idx], p, pr.pinv), sc, p);
   __syncthreads();
@@ -487,7 +505,8 @@ template <int LOGK>
 __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
                                   int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
                                   const PrimeDev *__restrict__ primes,
-                                  const PlanDev *__restrict__ pd, int32_t square) {
+                                  const PlanDev *__restrict__ pd, int32_t mode,
+                                  const uint32_t *__restrict__ spec) {
   constexpr int K = 1 << LOGK, K2 = 2 * K;
   const int L1 = 1 << logL1, RS = L1 + 1;      // odd row stride: rows fall on distinct banks
   const int64_t nrb = L >> logL1;
@@ -497,31 +516,53 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
   const uint32_t p = pr.p;
   uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
   const int64_t y0 = rb * L1;
-  // rows 0..K-1: limbs of a; rows K..2K-1: limbs of b (absent for a square)
-  const int rows = square ? K : K2;
+  // LDS rows 0..K-1: limbs of a (of b for CM_SPECTRUM); rows K..2K-1: limbs of b
+  // (CM_PRODUCT only)
+  const bool one = mode != CM_PRODUCT;
+  const int rows = one ? K : K2;
+  const int src0 = mode == CM_SPECTRUM ? K : 0;
   staged<8, uint32_t>(rows << logL1, [&](int idx) {
-    const int j = idx >> logL1, e = idx & (L1 - 1);
+    const int j = src0 + (idx >> logL1), e = idx & (L1 - 1);
     const int64_t nz = j < K ? nz_a : nz_b;
     return (y0 + e < nz) ? base[(int64_t)j * L + e] : 0u;
   }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
   __syncthreads();
-  lds_dif(s, LdsShape{square ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
+  lds_dif(s, LdsShape{one ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
+  if (mode == CM_SPECTRUM) {
+    // b's 2K spectra per position replace its limbs (this block's positions, all read)
+    for (int e = threadIdx.x; e < L1; e += BLOCK) {
+      uint32_t x[K2];
+#pragma unroll
+      for (int j = 0; j < K; ++j) x[j] = s[j * RS + e];
+      reg_dif<LOGK>(x, pr.hf, p);
+#pragma unroll
+      for (int j = 0; j < K2; ++j) base[(int64_t)j * L + e] = x[j];
+    }
+    return;
+  }
   const uint2 sc = pd->scale[k];
-  if (square) {
-    // one transform per column, multiplied by itself
+  if (one) {
+    // one forward transform per column, times itself or b's stored spectrum
+    const uint32_t *sb = spec + (int64_t)k * K2 * L + rb * L1;
     for (int e = threadIdx.x; e < L1; e += BLOCK) {
       uint32_t a[K2];
 #pragma unroll
       for (int j = 0; j < K; ++j) a[j] = s[j * RS + e];
       reg_dif<LOGK>(a, pr.hf, p);
+      if (mode == CM_SQUARE) {
 #pragma unroll
-      for (int j = 0; j < K2; ++j) a[j] = mul_shoup(mont_mul(a[j], a[j], p, pr.pinv), sc, p);
+        for (int j = 0; j < K2; ++j) a[j] = mul_shoup(mont_mul(a[j], a[j], p, pr.pinv), sc, p);
+      } else {
+#pragma unroll
+        for (int j = 0; j < K2; ++j)
+          a[j] = mul_shoup(mont_mul(a[j], sb[(int64_t)j * L + e], p, pr.pinv), sc, p);
+      }
       reg_dit<LOGK>(a, pr.hi, p);
 #pragma unroll
       for (int j = 0; j < K2; ++j) s[j * RS + e] = a[j];
     }
   }
-  for (int e = threadIdx.x; !square && e < L1; e += BLOCK) {
+  for (int e = threadIdx.x; !one && e < L1; e += BLOCK) {
     // the column of a is transformed and parked back in LDS (this thread owns column e)
     // before b is transformed, so that at most 3K values are live in registers
     uint32_t b[K2];

@@ -54,6 +54,15 @@ struct ColPass {
   int64_t S;      // stride of e, in elements
 };
 
+// What a row-convolution block computes:
+//   CM_PRODUCT        a * b from both operands' limb rows;
+//   CM_SQUARE         a * a from a's rows, transformed once;
+//   CM_SPECTRUM       only the forward transforms of b's rows (rows K..2K-1), whose 2K
+//                     spectra per position are written back over rows 0..2K-1;
+//   CM_WITH_SPECTRUM  a * b from a's rows and b's spectra written earlier by
+//                     CM_SPECTRUM for the same plan.
+enum ConvMode : int32_t { CM_PRODUCT = 0, CM_SQUARE = 1, CM_SPECTRUM = 2, CM_WITH_SPECTRUM = 3 };
+
 struct Plan {
   // caller-visible problem
   int64_t da, db;
