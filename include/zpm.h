@@ -255,6 +255,30 @@ int zpm_server_reset_stats(zpm_server *srv);
 /* Finishes every submitted request, stops the worker and frees the pool. */
 void zpm_server_destroy(zpm_server *srv);
 
+/* Products of very wide coefficients by Kronecker substitution (Section 1, the
+ * balancing remark: a forward and backward Kronecker substitution turns a pair with
+ * N far from Theta(d log d) into one for which it holds).  Each coefficient is cut
+ * into chunks of w bits (lower chunks unsigned, the top one signed), y is replaced
+ * by z^S with S = ceil(Na/w) + ceil(Nb/w) - 1, the reshaped pair (coefficients of
+ * w + 1 bits) is multiplied by the method, and c_k = sum_{r<S} c'_{S k + r} 2^(w r)
+ * is evaluated with carries.  chunk_bits: w, a multiple of 64 in [256, 16384], or 0
+ * for the cheapest by the planner's cost model.  Same arguments and rules as
+ * zpm_mul; the reshaped operands and product live in a context buffer.  zpm_mul
+ * takes this path by itself when no direct plan exists for the sizes (coefficients
+ * beyond what one recovery tile holds, about 98k bits).  zpm_kronecker_plan
+ * (host-only) reports the reshaping that would be used. */
+typedef struct zpm_kron_info {
+  int32_t chunk_bits, s_a, s_b, S;
+  int64_t da2, db2;     /* reshaped lengths */
+  int32_t N2, wc2;      /* reshaped coefficient bits and product words */
+  zpm_plan_info inner;  /* plan of the reshaped product */
+} zpm_kron_info;
+int zpm_mul_kronecker(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
+                      int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t chunk_bits,
+                      void *stream);
+int zpm_kronecker_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t chunk_bits,
+                       zpm_kron_info *out);
+
 /* Resident operand (one factor transformed once, for many products).
  * zpm_operand_create converts b and runs its forward transforms (Section 2.1:
  * BivariateRepresentation, then the y and x transforms of CyclicConvolution and

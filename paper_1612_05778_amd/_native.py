@@ -156,6 +156,22 @@ zpm_mul_operand = _sig("zpm_mul_operand", ctypes.c_int,
 zpm_operand_info = _sig("zpm_operand_info", ctypes.c_int, [c_vp, ctypes.POINTER(PlanInfo)])
 zpm_operand_destroy = _sig("zpm_operand_destroy", None, [c_vp])
 
+class KronInfo(ctypes.Structure):
+    _fields_ = [("chunk_bits", c_i32), ("s_a", c_i32), ("s_b", c_i32), ("S", c_i32),
+                ("da2", c_i64), ("db2", c_i64), ("N2", c_i32), ("wc2", c_i32),
+                ("inner", PlanInfo)]
+
+    def as_dict(self) -> dict:
+        d = {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "inner"}
+        d["inner"] = self.inner.as_dict()
+        return d
+
+
+zpm_mul_kronecker = _sig("zpm_mul_kronecker", ctypes.c_int,
+                         [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_i32, c_vp])
+zpm_kronecker_plan = _sig("zpm_kronecker_plan", ctypes.c_int,
+                          [c_i64, c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(KronInfo)])
+
 EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
            "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync",
            "zpm_profile_begin", "zpm_profile_end", "zpm_mul_batch", "zpm_mul_batch_ex",
@@ -164,7 +180,8 @@ EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime
            "zpm_server_create_simulated", "zpm_server_submit", "zpm_server_poll",
            "zpm_server_wait", "zpm_server_completions", "zpm_server_stats",
            "zpm_server_reset_stats", "zpm_server_destroy", "zpm_operand_create",
-           "zpm_mul_operand", "zpm_operand_info", "zpm_operand_destroy"]
+           "zpm_mul_operand", "zpm_operand_info", "zpm_operand_destroy", "zpm_mul_kronecker",
+           "zpm_kronecker_plan"]
 
 
 class ZpmError(RuntimeError):

@@ -26,6 +26,14 @@ def plan(da: int, Na: int, db: int, Nb: int, K: int = 0, np: int = 0) -> dict:
     return info.as_dict()
 
 
+def kronecker_plan(da: int, Na: int, db: int, Nb: int, chunk_bits: int = 0) -> dict:
+    """The Kronecker reshaping zpm_mul_kronecker would use (host only)."""
+    info = nat.KronInfo()
+    nat.check(nat.zpm_kronecker_plan(da, Na, db, Nb, chunk_bits, ctypes.byref(info)),
+              "zpm_kronecker_plan")
+    return info.as_dict()
+
+
 def device_limits(device: int = 0) -> dict:
     ncu, lb, lc = nat.c_i32(), nat.c_i64(), nat.c_i64()
     nat.check(nat.zpm_device_limits(device, ctypes.byref(ncu), ctypes.byref(lb), ctypes.byref(lc)),
@@ -99,6 +107,21 @@ class Context:
             rc = nat.zpm_mul(self._h, a.data_ptr(), da, Na, b.data_ptr(), db, Nb,
                              out.data_ptr() if n else None, wc, st)
         nat.check(rc, "zpm_mul")
+        return out
+
+    def mul_kronecker(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int,
+                      chunk_bits: int = 0, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+        """c = a * b through Kronecker reshaping (chunks of chunk_bits, 0 = choose)."""
+        da = _check_operand(a, Na, "a")
+        db = _check_operand(b, Nb, "b")
+        n = da + db - 1 if (da and db) else 0
+        wc = out_words(da, Na, db, Nb) if n else 1
+        if out is None:
+            out = torch.empty((n, wc), dtype=torch.int64, device=a.device)
+        nat.check(nat.zpm_mul_kronecker(self._h, a.data_ptr(), da, Na, b.data_ptr(), db, Nb,
+                                        out.data_ptr() if n else None, out.shape[1] if n else wc,
+                                        chunk_bits, _stream_handle(stream)), "zpm_mul_kronecker")
         return out
 
     def mul_stage(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int, stop_after: int,

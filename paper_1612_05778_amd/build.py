@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libzpm.so")
-SOURCES = ["nt.cpp", "plan.cpp", "kernels.hip", "batch.hip", "batch_host.cpp", "capi.hip",
+SOURCES = ["nt.cpp", "plan.cpp", "kernels.hip", "batch.hip", "batch_host.cpp", "capi.hip", "kron.hip",
            "tune.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -145,6 +145,7 @@ Ctx::~Ctx() {
   batch_graph.release();
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
   if (ws) (void)hipFree(ws);
+  if (kbuf) (void)hipFree(kbuf);
   if (heaps) (void)hipFree(heaps);
   if (primes) (void)hipFree(primes);
   for (auto &kv : consts) (void)hipFree(kv.second);
@@ -254,7 +255,11 @@ int zpm_mul_ex(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const ui
   std::lock_guard<std::mutex> lock(cx->mu);
   if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
   Plan pl;
-  if ((rc = cx->get_plan(da, Na, db, Nb, K, np, &pl)) != ZPM_OK) return rc;
+  if ((rc = cx->get_plan(da, Na, db, Nb, K, np, &pl)) != ZPM_OK) {
+    // coefficients too wide for one product: Kronecker reshaping, when nothing is forced
+    if (rc != ZPM_EUNSUPPORTED || K || np || stop_after) return rc;
+    return cx->mul_kronecker(a, da, Na, b, db, Nb, c, wc, 0, reinterpret_cast<hipStream_t>(stream));
+  }
   // c = a^2 when one operand is passed twice: it is converted and transformed once
   // (stage dumps keep the documented layout with both operands' rows)
   pl.square = (a == b && da == db && Na == Nb && !stop_after) ? 1 : 0;
@@ -316,6 +321,38 @@ int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t
   }
   *n_out = n;
   return rc;
+}
+
+int zpm_mul_kronecker(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
+                      int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t chunk_bits,
+                      void *stream) {
+  if (!ctx || chunk_bits < 0 || (chunk_bits & 63)) return ZPM_EINVAL;
+  int rc = check_mul_args(a, da, Na, b, db, Nb, c, wc);
+  if (rc != ZPM_OK) return rc;
+  if (da == 0 || db == 0) return ZPM_OK;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  std::lock_guard<std::mutex> lock(cx->mu);
+  if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  return cx->mul_kronecker(a, da, Na, b, db, Nb, c, wc, chunk_bits,
+                           reinterpret_cast<hipStream_t>(stream));
+}
+
+int zpm_kronecker_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t chunk_bits,
+                       zpm_kron_info *out) {
+  if (!out || da < 1 || db < 1 || Na < 1 || Nb < 1 || chunk_bits < 0 || (chunk_bits & 63))
+    return ZPM_EINVAL;
+  KronPlan kp;
+  if (!kron_plan(da, Na, db, Nb, chunk_bits, &kp)) return ZPM_EUNSUPPORTED;
+  out->chunk_bits = kp.w;
+  out->s_a = kp.sa;
+  out->s_b = kp.sb;
+  out->S = kp.S;
+  out->da2 = kp.da2;
+  out->db2 = kp.db2;
+  out->N2 = kp.N2;
+  out->wc2 = kp.wc2;
+  fill_info(kp.inner, &out->inner);
+  return ZPM_OK;
 }
 
 // A resident operand: b's spectra under a plan sized for products with any a of at

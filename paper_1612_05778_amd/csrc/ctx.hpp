@@ -55,6 +55,17 @@ using TuneTable = std::map<int32_t, TuneChoice>;
 int plan_for_batch(const TuneTable &tuned, int64_t da, int32_t Na, int64_t db, int32_t Nb,
                    int32_t K_force, int32_t T_force, Plan *out);
 
+// Kronecker reshaping of a product with wide coefficients: chunks of w bits, y -> z^S.
+struct KronPlan {
+  int32_t w = 0, wq = 0, sa = 0, sb = 0, S = 0, N2 = 0, wc2 = 0;
+  int64_t da2 = 0, db2 = 0, nout2 = 0;
+  Plan inner;          // plan of the reshaped product (da2, N2) x (db2, N2)
+  double cost = 0;
+};
+// Chooses the chunk width (chunk_bits, a multiple of 64, or 0 for the cheapest of
+// 256 ... 16384 by the planner's cost model); false when no reshaping has a plan.
+bool kron_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t chunk_bits, KronPlan *out);
+
 struct Ctx {
   int device = 0;
   PrimeDev *primes = nullptr;   // MAXNP entries
@@ -66,6 +77,8 @@ struct Ctx {
   std::map<std::tuple<int64_t, int32_t, int64_t, int32_t, int32_t, int32_t, int32_t>, Plan> plans;
   uint32_t *ws = nullptr;
   int64_t ws_words = 0;
+  uint64_t *kbuf = nullptr;     // reshaped operands and product of mul_kronecker
+  int64_t kbuf_words = 0;
   std::mutex mu;
   Profiler prof;
   TuneTable tuned;                             // size class -> choice of zpm_tune
@@ -75,6 +88,9 @@ struct Ctx {
   int ensure_tables(int np, int64_t H, int64_t TP);
   int plan_consts(const Plan &pl, PlanDev **out);
   int ensure_ws(int64_t words);
+  int ensure_kbuf(int64_t words);
+  int mul_kronecker(const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b, int64_t db,
+                    int32_t Nb, uint64_t *c, int32_t wc, int32_t chunk_bits, hipStream_t st);
   int get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np, Plan *out);
   int prepare(const Plan &pl, DevState *ds);
   int get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force,

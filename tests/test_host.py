@@ -104,3 +104,27 @@ def test_out_bits_extremes(nat):
         assert nb == Na + Nb - 1 + t.bit_length()
     assert api.out_bits(1024, 64, 1024, 64) == 138
     assert api.out_bits(65536, 4097, 65536, 4097) == 8210
+
+
+def test_kronecker_plans(nat):
+    from paper_1612_05778_amd import api
+    # too wide for one product, fine after reshaping
+    with pytest.raises(nat.ZpmError):
+        api.plan(32, 262145, 32, 262145)
+    for (da, Na, db, Nb, w) in [(32, 262145, 32, 262145, 0), (8, 300000, 5, 200000, 0),
+                                (50, 3000, 70, 2000, 512), (1, 70000, 1, 70000, 1024),
+                                (100, 64, 100, 64, 256)]:
+        k = api.kronecker_plan(da, Na, db, Nb, w)
+        cw = k["chunk_bits"]
+        assert cw % 64 == 0 and 256 <= cw <= 16384 and (w == 0 or cw == w)
+        sa, sb = -(-Na // cw), -(-Nb // cw)
+        assert (k["s_a"], k["s_b"], k["S"]) == (sa, sb, sa + sb - 1)
+        assert k["da2"] == k["S"] * (da - 1) + sa and k["db2"] == k["S"] * (db - 1) + sb
+        assert k["N2"] == cw + 1
+        inner = k["inner"]
+        assert inner["da"] == k["da2"] and inner["Na"] == cw + 1
+        assert k["wc2"] == -(-nat.zpm_out_bits(k["da2"], cw + 1, k["db2"], cw + 1) // 64)
+        assert k["da2"] + k["db2"] - 1 <= 1 << 21
+    for bad in (100, -64):
+        with pytest.raises(nat.ZpmError):
+            api.kronecker_plan(10, 1000, 10, 1000, bad)
