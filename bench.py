@@ -337,6 +337,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--only-product", action="store_true",
+                    help="time the product alone: no square, resident-operand, batched, served "
+                         "or cpu_baseline legs (for profiling the product's kernels)")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson) leg")
     ap.add_argument("--served-requests", type=int, default=20000)
@@ -442,6 +445,11 @@ def main() -> int:
         "roofline": roof,
         "kernels": kinfo,
     }
+    if args.only_product:
+        args.no_batch = args.no_served = args.no_cpu = True
+        print(json.dumps(line), flush=True)
+        ctx.close()
+        return 0
     # the same workload squared (a passed twice): one conversion and forward transform
     sq = ctx.mul(a, prod.Na, a, prod.Na)
     torch.cuda.synchronize()

@@ -44,12 +44,20 @@ def kernel_work(plan: dict, name: str) -> dict:
         return {"ops": bfly * OPS_BFLY + twists * OPS_TWIDDLE + pw * OPS_POINTWISE,
                 "bytes": 4 * 2 * words_in}
     if name in ("col_pass_fwd", "col_pass_inv"):
-        # per launch = one pass; use the mean pass length
+        # per launch = one pass; the mean over the passes.  The first forward pass
+        # reads only the rows below da (db) of a's (b's) columns, the rest being zero.
         cols = plan["col_log2n"]
-        logn = sum(cols) / max(len(cols), 1)
+        npass = max(len(cols), 1)
+        logn = sum(cols) / npass
         bfly = np_ * K * L * logn
         tw = np_ * 2 * K * L
-        return {"ops": bfly * OPS_BFLY + tw * OPS_TWIDDLE, "bytes": 4 * 2 * np_ * 2 * K * L}
+        full = 4 * np_ * 2 * K * L
+        if name == "col_pass_fwd":
+            first_read = 4 * np_ * K * (min(da, L) + min(db, L))
+            read = (first_read + (npass - 1) * full) / npass
+        else:
+            read = full
+        return {"ops": bfly * OPS_BFLY + tw * OPS_TWIDDLE, "bytes": read + full}
     if name == "bivariate_representation":
         # per launch = one operand; the mean of the two
         w = ((plan["Na"] + 63) // 64 * da + (plan["Nb"] + 63) // 64 * db) / 2
