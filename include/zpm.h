@@ -60,6 +60,7 @@ typedef struct zpm_plan_info {
   int32_t log2_L1;       /* inner y factor done inside the row-convolution kernel */
   int32_t ncol;          /* strided column passes of the y-transform */
   int32_t col_log2n[4];  /* their lengths, outermost first */
+  int32_t col_tile[4];   /* inner indices per workgroup of each pass */
   int32_t W;             /* 32-bit words of each CRT value */
   int32_t log2P;         /* bit length of the prime product */
   int32_t nout_bits;     /* == zpm_out_bits(...) */

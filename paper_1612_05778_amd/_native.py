@@ -41,13 +41,14 @@ class PlanInfo(ctypes.Structure):
         ("da", c_i64), ("db", c_i64), ("Na", c_i32), ("Nb", c_i32),
         ("K", c_i32), ("M", c_i32), ("np", c_i32),
         ("log2_L", c_i32), ("log2_L1", c_i32), ("ncol", c_i32), ("col_log2n", c_i32 * 4),
-        ("W", c_i32), ("log2P", c_i32), ("nout_bits", c_i32),
+        ("col_tile", c_i32 * 4), ("W", c_i32), ("log2P", c_i32), ("nout_bits", c_i32),
         ("workspace_bytes", c_i64),
     ]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["col_log2n"] = list(self.col_log2n)[: self.ncol]
+        d["col_tile"] = list(self.col_tile)[: self.ncol]
         return d
 
 

@@ -174,6 +174,8 @@ size_t stage_lds(const Plan &pl, int kind, int pass) {
 
 bool batch_supports(const Plan &pl) {
   if (pl.np < 1 || pl.np > 16) return false;
+  for (int c = 0; c < pl.ncol; ++c)
+    if (pl.col_tile[c] < 1 || pl.col_tile[c] > BLOCK) return false;   // steps by BLOCK / T
   if (pl.conv_reg && pl.K > 16) return false;
   return true;
 }

@@ -21,7 +21,10 @@ static void fill_info(const Plan &pl, zpm_plan_info *o) {
   o->da = pl.da; o->db = pl.db; o->Na = pl.Na; o->Nb = pl.Nb;
   o->K = pl.K; o->M = pl.M; o->np = pl.np;
   o->log2_L = pl.logL; o->log2_L1 = pl.logL1; o->ncol = pl.ncol;
-  for (int c = 0; c < pl.ncol && c < 4; ++c) o->col_log2n[c] = pl.col[c].logn;
+  for (int c = 0; c < pl.ncol && c < 4; ++c) {
+    o->col_log2n[c] = pl.col[c].logn;
+    o->col_tile[c] = pl.col_tile[c];
+  }
   o->W = pl.W; o->log2P = pl.log2P; o->nout_bits = pl.nout_bits;
   o->workspace_bytes = pl.ws_words * 4;
 }

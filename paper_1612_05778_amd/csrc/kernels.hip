@@ -120,6 +120,7 @@ hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, h
   const int logn = pl.col[c].logn;
   const int64_t S = pl.col[c].S;
   const int T = pl.col_tile[c];
+  if (T < 1 || T > BLOCK) return hipErrorInvalidValue;   // the kernel steps by BLOCK / T
   const int logT = ilog2(T);
   const int64_t tiles = (S >> logT) * (L / (((int64_t)1 << logn) * S));
   // forward passes of a square cover a's limbs only; fwd_cols / col0 select other sets

@@ -77,8 +77,11 @@ static bool split_y(Plan &pl, int reg_k_max, int col_tile) {
     pl.col[c].logn = take;
     S >>= take;
     pl.col[c].S = S;
-    // inner indices per workgroup: T * n <= LDS_WORDS, T <= S, T <= 64
-    const int64_t want = col_tile > 0 ? col_tile : col_tile_max();
+    // inner indices per workgroup: T * n <= LDS_WORDS, T <= S, and T <= BLOCK (each
+    // thread owns one inner index and steps through the frequencies by BLOCK / T);
+    // short passes get wider tiles so that a workgroup holds up to 2048 elements
+    int64_t want = std::max<int64_t>(col_tile > 0 ? col_tile : col_tile_max(), 2048 >> take);
+    want = std::min<int64_t>(want, BLOCK);
     int64_t T = std::min<int64_t>(S, std::min<int64_t>(want, LDS_WORDS >> take));
     pl.col_tile[c] = (int32_t)std::max<int64_t>(T, 1);
   }

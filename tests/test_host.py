@@ -78,6 +78,28 @@ def test_plan_invariants(nat, da, Na, db, Nb):
     assert pl["log2_L1"] + sum(pl["col_log2n"]) == pl["log2_L"]
     assert pl["workspace_bytes"] == 4 * np_ * 2 * K * L
     assert pl["nout_bits"] == api.out_bits(da, Na, db, Nb)
+    check_col_tiles(pl)
+
+
+def check_col_tiles(pl):
+    """Column-pass tiles the kernels accept: each of the 256 threads owns one inner index
+    and steps by 256 / T, the tile fits LDS, and it does not exceed the pass stride."""
+    S = 1 << pl["log2_L"]
+    for logn, T in zip(pl["col_log2n"], pl["col_tile"]):
+        S >>= logn
+        assert 1 <= T <= 256 and T & (T - 1) == 0, pl
+        assert T * (1 << logn) <= 16384 and T <= S, pl
+
+
+def test_col_tiles_for_every_K(nat):
+    from paper_1612_05778_amd import api
+    for (da, Na) in [(777, 901), (5000, 64), (65536, 4097), (3000, 700), (100000, 200)]:
+        for logK in range(1, 11):
+            try:
+                pl = api.plan(da, Na, da, Na, K=1 << logK)
+            except nat.ZpmError:
+                continue
+            check_col_tiles(pl)
 
 
 def test_forced_plans(nat):
