@@ -69,7 +69,7 @@ __global__ __launch_bounds__(BLOCK) void kg_col(const JobDev *__restrict__ jobs,
                 (jb.square && !inverse) ? jb.K : 2 * jb.K, 0);
 }
 
-template <int LOGK>
+template <int LOGK, int MODE>
 __global__ __launch_bounds__(BLOCK) void kg_convolve_reg(const JobDev *__restrict__ jobs,
                                                          const GroupSeg *__restrict__ segs,
                                                          int32_t nseg,
@@ -79,9 +79,9 @@ __global__ __launch_bounds__(BLOCK) void kg_convolve_reg(const JobDev *__restric
   const JobDev &jb = jobs[g.job];
   const int64_t L = jb.L;
   const bool direct = jb.ncol == 0;
-  body_convolve_reg<LOGK>(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.logL1, direct ? jb.da : L,
-                          direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan,
-                          jb.square ? CM_SQUARE : CM_PRODUCT, nullptr);
+  body_convolve_reg<LOGK, MODE>(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.logL1,
+                                direct ? jb.da : L, direct ? jb.db : L, direct ? jb.nout : L,
+                                primes, jb.plan, nullptr);
 }
 
 __global__ __launch_bounds__(BLOCK) void kg_convolve(const JobDev *__restrict__ jobs,
@@ -131,16 +131,22 @@ hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *seg
       hipLaunchKernelGGL(kg_col, dim3((unsigned)(8 * ((gr.blocks + 7) / 8))), blk, gr.lds, st, jobs,
                          sg, ns, gr.kind == SK_COL_INV ? 1 : 0, primes, gr.blocks);
       break;
-    case SK_CONVOLVE:
-      switch (gr.variant) {
-        case 1: hipLaunchKernelGGL(kg_convolve_reg<1>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
-        case 2: hipLaunchKernelGGL(kg_convolve_reg<2>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
-        case 3: hipLaunchKernelGGL(kg_convolve_reg<3>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
-        case 4: hipLaunchKernelGGL(kg_convolve_reg<4>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+    case SK_CONVOLVE: {
+      // variant: log2 K of the register kernel plus 16 for squares, 0 for the LDS kernel
+      const bool sq = gr.variant >= 16;
+      switch (gr.variant & 15) {
+#define ZPM_G(LK_)                                                                            \
+  case LK_:                                                                                   \
+    if (sq) hipLaunchKernelGGL((kg_convolve_reg<LK_, CM_SQUARE>), grid, blk, gr.lds, st, jobs, sg, ns, primes); \
+    else hipLaunchKernelGGL((kg_convolve_reg<LK_, CM_PRODUCT>), grid, blk, gr.lds, st, jobs, sg, ns, primes); \
+    break;
+        ZPM_G(1) ZPM_G(2) ZPM_G(3) ZPM_G(4)
+#undef ZPM_G
         case 0: hipLaunchKernelGGL(kg_convolve, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
         default: return hipErrorInvalidValue;
       }
       break;
+    }
     default:
       return hipErrorInvalidValue;
   }

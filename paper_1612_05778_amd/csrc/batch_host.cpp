@@ -148,7 +148,7 @@ static int stage_variant(const Plan &pl, int kind) {
   if (kind == SK_CONVOLVE && pl.conv_reg) {
     int lk = 0;
     while ((1 << lk) < pl.K) ++lk;
-    return lk;
+    return lk + (pl.square ? 16 : 0);   // squares have a register kernel of their own
   }
   return 0;
 }

@@ -59,13 +59,13 @@ __global__ __launch_bounds__(BLOCK) void k_convolve_rows(
   body_convolve(s, blockIdx.x, X, L, K, logK, logL1, nz_a, nz_b, nlimit, primes, pd, mode, spec);
 }
 
-template <int LOGK>
+template <int LOGK, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_convolve_rows_reg(
     uint32_t *__restrict__ X, int64_t L, int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
-    const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd, int32_t mode,
+    const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd,
     const uint32_t *__restrict__ spec) {
   extern __shared__ uint32_t s[];
-  body_convolve_reg<LOGK>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd, mode, spec);
+  body_convolve_reg<LOGK, MODE>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd, spec);
 }
 
 template <int NP>
@@ -147,9 +147,16 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
   const int64_t nz_a = direct ? pl.da : L, nz_b = direct ? pl.db : L, nl = direct ? pl.nout : L;
   if (pl.conv_reg) {
     const size_t lds = sizeof(uint32_t) * (size_t)(2 * pl.K) * (((size_t)1 << pl.logL1) + 1);
-#define ZPM_CONV(LK_)                                                                           \
-  hipLaunchKernelGGL(k_convolve_rows_reg<LK_>, dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, \
-                     L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, mode, spec)
+#define ZPM_CONV_M(LK_, M_)                                                                   \
+  hipLaunchKernelGGL((k_convolve_rows_reg<LK_, M_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, \
+                     ds.X, L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, spec)
+#define ZPM_CONV(LK_)                                        \
+  switch (mode) {                                            \
+    case CM_PRODUCT: ZPM_CONV_M(LK_, CM_PRODUCT); break;     \
+    case CM_SQUARE: ZPM_CONV_M(LK_, CM_SQUARE); break;       \
+    case CM_SPECTRUM: ZPM_CONV_M(LK_, CM_SPECTRUM); break;   \
+    default: ZPM_CONV_M(LK_, CM_WITH_SPECTRUM); break;       \
+  }
     switch (ilog2(pl.K)) {
       case 1: ZPM_CONV(1); break;
       case 2: ZPM_CONV(2); break;
@@ -158,6 +165,7 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
       default: ZPM_CONV(5); break;
     }
 #undef ZPM_CONV
+#undef ZPM_CONV_M
     return hipGetLastError();
   }
   const size_t lds = sizeof(uint32_t) * (size_t)4 * pl.K << pl.logL1;

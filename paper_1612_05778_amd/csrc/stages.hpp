@@ -148,12 +148,20 @@ __device__ void dit_group(uint32_t *s, const LdsShape &sh, int logh0, const uint
   }
 }
 
+// Stages per register group: the fewest groups of at most 4 stages (radix 16), as even
+// as possible, larger groups first (8 -> 4+4, 9 -> 3+3+3, 7 -> 4+3, 6 -> 3+3).
+__device__ __forceinline__ int group_stages(int left) {
+  const int ngroups = (left + 3) >> 2;
+  return (left + ngroups - 1) / ngroups;
+}
+
 // Full forward transform (all logn stages); caller synchronises before and after.
 __device__ void lds_dif(uint32_t *s, const LdsShape &sh, const uint2 *__restrict__ tw, uint32_t p) {
   int st = sh.logn;
   while (st > 0) {
-    const int r = st >= 3 ? 3 : st;
-    if (r == 3) dif_group<3>(s, sh, st - 1, tw, p);
+    const int r = group_stages(st);
+    if (r == 4) dif_group<4>(s, sh, st - 1, tw, p);
+    else if (r == 3) dif_group<3>(s, sh, st - 1, tw, p);
     else if (r == 2) dif_group<2>(s, sh, st - 1, tw, p);
     else dif_group<1>(s, sh, st - 1, tw, p);
     st -= r;
@@ -164,9 +172,9 @@ __device__ void lds_dif(uint32_t *s, const LdsShape &sh, const uint2 *__restrict
 __device__ void lds_dit(uint32_t *s, const LdsShape &sh, const uint2 *__restrict__ tw, uint32_t p) {
   int done = 0;
   while (done < sh.logn) {
-    const int left = sh.logn - done;
-    const int r = left >= 3 ? 3 : left;
-    if (r == 3) dit_group<3>(s, sh, done, tw, p);
+    const int r = group_stages(sh.logn - done);
+    if (r == 4) dit_group<4>(s, sh, done, tw, p);
+    else if (r == 3) dit_group<3>(s, sh, done, tw, p);
     else if (r == 2) dit_group<2>(s, sh, done, tw, p);
     else dit_group<1>(s, sh, done, tw, p);
     done += r;
@@ -501,11 +509,13 @@ __device__ __forceinline__ void reg_dit(uint32_t (&x)[2 << LOGK], const uint2 *_
   }
 }
 
-template <int LOGK>
+// MODE is a ConvMode, fixed at compile time so that each variant keeps only its own
+// register footprint (the product's is the largest that matters for occupancy).
+template <int LOGK, int MODE>
 __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
                                   int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
                                   const PrimeDev *__restrict__ primes,
-                                  const PlanDev *__restrict__ pd, int32_t mode,
+                                  const PlanDev *__restrict__ pd,
                                   const uint32_t *__restrict__ spec) {
   constexpr int K = 1 << LOGK, K2 = 2 * K;
   const int L1 = 1 << logL1, RS = L1 + 1;      // odd row stride: rows fall on distinct banks
@@ -518,9 +528,9 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
   const int64_t y0 = rb * L1;
   // LDS rows 0..K-1: limbs of a (of b for CM_SPECTRUM); rows K..2K-1: limbs of b
   // (CM_PRODUCT only)
-  const bool one = mode != CM_PRODUCT;
-  const int rows = one ? K : K2;
-  const int src0 = mode == CM_SPECTRUM ? K : 0;
+  constexpr bool one = MODE != CM_PRODUCT;
+  constexpr int rows = one ? K : K2;
+  constexpr int src0 = MODE == CM_SPECTRUM ? K : 0;
   staged<8, uint32_t>(rows << logL1, [&](int idx) {
     const int j = src0 + (idx >> logL1), e = idx & (L1 - 1);
     const int64_t nz = j < K ? nz_a : nz_b;
@@ -528,7 +538,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
   }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
   __syncthreads();
   lds_dif(s, LdsShape{one ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
-  if (mode == CM_SPECTRUM) {
+  if constexpr (MODE == CM_SPECTRUM) {
     // b's 2K spectra per position replace its limbs (this block's positions, all read)
     for (int e = threadIdx.x; e < L1; e += BLOCK) {
       uint32_t x[K2];
@@ -541,7 +551,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
     return;
   }
   const uint2 sc = pd->scale[k];
-  if (one) {
+  if constexpr (one) {
     // one forward transform per column, times itself or b's stored spectrum
     const uint32_t *sb = spec + (int64_t)k * K2 * L + rb * L1;
     for (int e = threadIdx.x; e < L1; e += BLOCK) {
@@ -549,7 +559,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
 #pragma unroll
       for (int j = 0; j < K; ++j) a[j] = s[j * RS + e];
       reg_dif<LOGK>(a, pr.hf, p);
-      if (mode == CM_SQUARE) {
+      if constexpr (MODE == CM_SQUARE) {
 #pragma unroll
         for (int j = 0; j < K2; ++j) a[j] = mul_shoup(mont_mul(a[j], a[j], p, pr.pinv), sc, p);
       } else {
@@ -562,7 +572,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
       for (int j = 0; j < K2; ++j) s[j * RS + e] = a[j];
     }
   }
-  for (int e = threadIdx.x; !one && e < L1; e += BLOCK) {
+  if constexpr (!one) for (int e = threadIdx.x; e < L1; e += BLOCK) {
     // the column of a is transformed and parked back in LDS (this thread owns column e)
     // before b is transformed, so that at most 3K values are live in registers
     uint32_t b[K2];
@@ -680,8 +690,7 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
         const uint2 qq = *reinterpret_cast<const uint2 *>(cq + u * NPE + k);
         uint64_t pr2 = (uint64_t)cc[k + 1] * qq.y;
         pr2 += (uint64_t)cc[k] * qq.x;
-        lo += pr2;
-        hi += lo < pr2 ? 1u : 0u;
+        hi += __builtin_add_overflow(lo, pr2, &lo) ? 1u : 0u;
       }
       const uint64_t tp = (uint64_t)tq * cp[u];
       const uint64_t D = lo - tp;
