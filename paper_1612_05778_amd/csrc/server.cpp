@@ -367,7 +367,6 @@ bool Server::take(int ln, Flight &f) {
 
 // Picks the lane whose head arrived first among those allowed a stream (under m).
 bool Server::form(Flight &f, int busy_large) {
-  const int S = cfg.n_streams;
   const bool large_ok = !lane[1].empty() && busy_large < cfg.large_streams;
   const bool small_ok = !lane[0].empty();
   int order[2] = {0, 1};
