@@ -194,3 +194,16 @@ def test_synth_config_shapes():
     assert degs.min() >= 15 and degs.max() <= 65535 and bits.min() >= 16 and bits.max() <= 8192
     _, degs, bits = synth.batch_sizes(4, 4096)
     assert degs.min() >= 63 and degs.max() <= 8191 and bits.min() >= 32 and bits.max() <= 2048
+
+
+def test_stored_digest_matches_oracle():
+    """tests/golden/digests.json holds digests written by tests/golden/make_digests.py
+    from the generators and the oracle; the small one is recomputed here."""
+    import hashlib
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")
+    ref = json.load(open(path))["int64_1k"]
+    p = synth.int64_1k(1)
+    c = oracle.polymul(p.a, p.da, p.Na, p.b, p.db, p.Nb, wc=ref["wc"])
+    assert hashlib.sha256(c.tobytes()).hexdigest() == ref["sha256"]
