@@ -47,6 +47,32 @@ def prime(k: int) -> tuple[int, int]:
     return p.value, r.value
 
 
+def from_ints(values, N: int | None = None, device="cuda") -> tuple[torch.Tensor, int]:
+    """Python ints -> (d, ceil(N/64)) int64 tensor of N-bit two's complement words, N.
+
+    N defaults to the smallest width that holds every value (at least 2)."""
+    vals = [int(v) for v in values]
+    if N is None:
+        N = max([2] + [v.bit_length() + 1 for v in vals])
+    lo, hi = -(1 << (N - 1)), (1 << (N - 1)) - 1
+    w = (N + 63) // 64
+    buf = bytearray()
+    for v in vals:
+        if not lo <= v <= hi:
+            raise ValueError(f"{v} does not fit in {N}-bit two's complement")
+        buf += v.to_bytes(8 * w, "little", signed=True)
+    t = torch.frombuffer(buf, dtype=torch.int64).clone() if vals else torch.empty(0, dtype=torch.int64)
+    return t.reshape(len(vals), w).to(device), N
+
+
+def to_ints(t: torch.Tensor) -> list[int]:
+    """(d, w) int64 tensor of two's complement words -> Python ints."""
+    raw = t.detach().cpu().contiguous().numpy().tobytes()
+    w = t.shape[1] if t.dim() == 2 else 1
+    return [int.from_bytes(raw[8 * w * i: 8 * w * (i + 1)], "little", signed=True)
+            for i in range(t.shape[0])]
+
+
 def _stream_handle(stream) -> int | None:
     if stream is None:
         stream = torch.cuda.current_stream()

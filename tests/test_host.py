@@ -150,3 +150,15 @@ def test_kronecker_plans(nat):
     for bad in (100, -64):
         with pytest.raises(nat.ZpmError):
             api.kronecker_plan(10, 1000, 10, 1000, bad)
+
+
+def test_from_to_ints_roundtrip(nat):
+    from paper_1612_05778_amd import api
+    vals = [0, 1, -1, 2**63, -(2**63), 2**200 - 7, -(2**200), 12345]
+    t, N = api.from_ints(vals, device="cpu")
+    assert N == 202 and t.shape == (len(vals), 4)
+    assert api.to_ints(t) == vals
+    t, N = api.from_ints([5, -3], 300, device="cpu")
+    assert N == 300 and api.to_ints(t) == [5, -3]
+    with pytest.raises(ValueError):
+        api.from_ints([2**10], 10, device="cpu")
