@@ -25,6 +25,13 @@
 
 namespace zpm {
 
+// Smallest log2 K whose x-transforms run one K-point half at a time (below it the whole
+// 2K-point transform fits in registers).  K = 32 is the largest register plan: for
+// K = 64 the halves still need about 256 VGPRs and the LDS kernel is faster.
+#ifndef ZPM_SPLIT_LOGK
+#define ZPM_SPLIT_LOGK 5
+#endif
+
 static inline int64_t xcd_grid(int64_t ntiles) { return 8 * ((ntiles + 7) >> 3); }
 
 template <int NP>
@@ -66,6 +73,15 @@ __global__ __launch_bounds__(BLOCK) void k_convolve_rows_reg(
     const uint32_t *__restrict__ spec) {
   extern __shared__ uint32_t s[];
   body_convolve_reg<LOGK, MODE>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd, spec);
+}
+
+template <int LOGK, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_convolve_rows_split(
+    uint32_t *__restrict__ X, int64_t L, int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
+    const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd,
+    const uint32_t *__restrict__ spec) {
+  extern __shared__ uint32_t s[];
+  body_convolve_split<LOGK, MODE>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd, spec);
 }
 
 template <int NP>
@@ -147,9 +163,13 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
   const int64_t nz_a = direct ? pl.da : L, nz_b = direct ? pl.db : L, nl = direct ? pl.nout : L;
   if (pl.conv_reg) {
     const size_t lds = sizeof(uint32_t) * (size_t)(2 * pl.K) * (((size_t)1 << pl.logL1) + 1);
-#define ZPM_CONV_M(LK_, M_)                                                                   \
-  hipLaunchKernelGGL((k_convolve_rows_reg<LK_, M_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, \
-                     ds.X, L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, spec)
+#define ZPM_CONV_M(LK_, M_)                                                                    \
+  if constexpr (LK_ >= ZPM_SPLIT_LOGK)                                                         \
+    hipLaunchKernelGGL((k_convolve_rows_split<LK_, M_>), dim3((unsigned)blocks), dim3(BLOCK), lds, \
+                       st, ds.X, L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, spec);           \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_convolve_rows_reg<LK_, M_>), dim3((unsigned)blocks), dim3(BLOCK), lds,  \
+                       st, ds.X, L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, spec)
 #define ZPM_CONV(LK_)                                        \
   switch (mode) {                                            \
     case CM_PRODUCT: ZPM_CONV_M(LK_, CM_PRODUCT); break;     \

@@ -9,7 +9,7 @@ int32_t out_bits(int64_t da, int32_t Na, int64_t db, int32_t Nb);
 struct PlanLimits {
   int32_t np_max = MAXNP;    // largest prime count
   int32_t k_max = 1 << 20;   // largest K
-  int32_t reg_k_max = 32;    // largest K for the register x-transform kernel
+  int32_t reg_k_max = 32;    // largest K for the register x-transform kernels
   int32_t col_tile = 0;      // widest column tile (power of two); 0 = the default
 };
 

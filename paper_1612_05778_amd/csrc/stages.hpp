@@ -604,6 +604,185 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
 }
 
 // ------------------------------------------------------------------------------------
+// The same convolutions for larger K (32), one K-point half of each 2K-point
+// x-transform at a time in registers.  A zero-padded column's first DIF stage is the
+// twist (upper half = lower half times theta^j), after which the two halves are
+// independent K-point DIFs; the inverse is two K-point DITs and a joining stage that
+// applies theta^-j.  Each thread owns one column of the LDS tile, so halves are parked
+// there between steps; at most two halves are live in registers.
+// ------------------------------------------------------------------------------------
+// Twiddle tables read through the constant address space: the indices are the same for
+// every lane, so the loads can be scalar and the twiddles need no vector registers.
+typedef const __attribute__((address_space(4))) uint64_t *ctw_ptr;
+__device__ __forceinline__ uint2 ctw(ctw_ptr t, int i) {
+  const uint64_t w = t[i];   // (w, Shoup companion) as one 64-bit word
+  return make_uint2((uint32_t)w, (uint32_t)(w >> 32));
+}
+
+template <int LOGN>
+__device__ __forceinline__ void reg_half_dif(uint32_t (&x)[1 << LOGN], ctw_ptr tw, uint32_t p) {
+  constexpr int N = 1 << LOGN;
+#pragma unroll
+  for (int h = N / 2; h >= 1; h >>= 1) {
+#pragma unroll
+    for (int blk = 0; blk < N; blk += 2 * h) {
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        const uint32_t u = x[blk + j], v = x[blk + j + h];
+        x[blk + j] = add_mod(u, v, p);
+        x[blk + j + h] = j ? mul_shoup(u - v + p, ctw(tw, h + j), p) : sub_mod(u, v, p);
+      }
+    }
+  }
+}
+
+template <int LOGN>
+__device__ __forceinline__ void reg_half_dit(uint32_t (&x)[1 << LOGN], ctw_ptr tw, uint32_t p) {
+  constexpr int N = 1 << LOGN;
+#pragma unroll
+  for (int h = 1; h < N; h <<= 1) {
+#pragma unroll
+    for (int blk = 0; blk < N; blk += 2 * h) {
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        const uint32_t u = x[blk + j];
+        const uint32_t v = j ? mul_shoup(x[blk + j + h], ctw(tw, h + j), p) : x[blk + j + h];
+        x[blk + j] = add_mod(u, v, p);
+        x[blk + j + h] = sub_mod(u, v, p);
+      }
+    }
+  }
+}
+
+template <int LOGK, int MODE>
+__device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
+                                    int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
+                                    const PrimeDev *__restrict__ primes,
+                                    const PlanDev *__restrict__ pd,
+                                    const uint32_t *__restrict__ spec) {
+  constexpr int K = 1 << LOGK, K2 = 2 * K;
+  const int L1 = 1 << logL1, RS = L1 + 1;
+  const int64_t nrb = L >> logL1;
+  const int k = (int)(bid / nrb);
+  const int64_t rb = bid - (int64_t)k * nrb;
+  const PrimeDev pr = primes[k];
+  const uint32_t p = pr.p;
+  uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
+  const int64_t y0 = rb * L1;
+  constexpr bool one = MODE != CM_PRODUCT;
+  constexpr int rows = one ? K : K2;
+  constexpr int src0 = MODE == CM_SPECTRUM ? K : 0;
+  staged<8, uint32_t>(rows << logL1, [&](int idx) {
+    const int j = src0 + (idx >> logL1), e = idx & (L1 - 1);
+    const int64_t nz = j < K ? nz_a : nz_b;
+    return (y0 + e < nz) ? base[(int64_t)j * L + e] : 0u;
+  }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
+  __syncthreads();
+  lds_dif(s, LdsShape{one ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
+  ctw_ptr hf = (ctw_ptr)(const void *)pr.hf;
+  ctw_ptr hi = (ctw_ptr)(const void *)pr.hi;
+  // the twisted half: x_j theta^j, then its K-point DIF (rows K..2K-1 of the spectrum)
+  auto twisted = [&](uint32_t (&x)[K]) {
+#pragma unroll
+    for (int j = 1; j < K; ++j) x[j] = mul_shoup(x[j], ctw(hf, K + j), p);
+    reg_half_dif<LOGK>(x, hf, p);
+  };
+  if constexpr (MODE == CM_SPECTRUM) {
+    for (int e = threadIdx.x; e < L1; e += BLOCK) {
+      uint32_t x[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) x[j] = s[j * RS + e];
+      twisted(x);
+#pragma unroll
+      for (int j = 0; j < K; ++j) base[(int64_t)(K + j) * L + e] = x[j];
+#pragma unroll
+      for (int j = 0; j < K; ++j) x[j] = s[j * RS + e];
+      reg_half_dif<LOGK>(x, hf, p);
+#pragma unroll
+      for (int j = 0; j < K; ++j) base[(int64_t)j * L + e] = x[j];
+    }
+    return;
+  }
+  const uint2 sc = pd->scale[k];
+  const uint32_t *sb = spec + (int64_t)k * K2 * L + rb * L1;
+  for (int e = threadIdx.x; e < L1; e += BLOCK) {
+    uint32_t x[K];
+    if constexpr (MODE == CM_PRODUCT) {
+      uint32_t b[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) b[j] = s[(K + j) * RS + e];
+      // a: twisted half over b's limb rows (b is in registers), then the plain half
+#pragma unroll
+      for (int j = 0; j < K; ++j) x[j] = s[j * RS + e];
+      twisted(x);
+#pragma unroll
+      for (int j = 0; j < K; ++j) s[(K + j) * RS + e] = x[j];
+#pragma unroll
+      for (int j = 0; j < K; ++j) x[j] = s[j * RS + e];
+      reg_half_dif<LOGK>(x, hf, p);
+#pragma unroll
+      for (int j = 0; j < K; ++j) s[j * RS + e] = x[j];
+      // b: each half times a's, the product replacing a's spectrum
+#pragma unroll
+      for (int j = 0; j < K; ++j) x[j] = b[j];
+      twisted(x);
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        s[(K + j) * RS + e] = mul_shoup(mont_mul(s[(K + j) * RS + e], x[j], p, pr.pinv), sc, p);
+      reg_half_dif<LOGK>(b, hf, p);
+#pragma unroll
+      for (int j = 0; j < K; ++j) s[j * RS + e] = mul_shoup(mont_mul(s[j * RS + e], b[j], p, pr.pinv), sc, p);
+    } else {
+      // one operand transformed once: times itself, or times b's stored spectra
+#pragma unroll
+      for (int j = 0; j < K; ++j) x[j] = s[j * RS + e];
+      twisted(x);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const uint32_t f = MODE == CM_SQUARE ? x[j] : sb[(int64_t)(K + j) * L + e];
+        x[j] = mul_shoup(mont_mul(x[j], f, p, pr.pinv), sc, p);
+      }
+      uint32_t t[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) t[j] = s[j * RS + e];
+#pragma unroll
+      for (int j = 0; j < K; ++j) s[(K + j) * RS + e] = x[j];
+      reg_half_dif<LOGK>(t, hf, p);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const uint32_t f = MODE == CM_SQUARE ? t[j] : sb[(int64_t)j * L + e];
+        s[j * RS + e] = mul_shoup(mont_mul(t[j], f, p, pr.pinv), sc, p);
+      }
+    }
+    // inverse: the two K-point DITs, then the joining stage with theta^-j
+#pragma unroll
+    for (int j = 0; j < K; ++j) x[j] = s[j * RS + e];
+    reg_half_dit<LOGK>(x, hi, p);
+    {
+      uint32_t y[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) y[j] = s[(K + j) * RS + e];
+      reg_half_dit<LOGK>(y, hi, p);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const uint32_t u = x[j];
+        const uint32_t v = j ? mul_shoup(y[j], ctw(hi, K + j), p) : y[j];
+        s[j * RS + e] = add_mod(u, v, p);
+        s[(K + j) * RS + e] = sub_mod(u, v, p);
+      }
+    }
+  }
+  __syncthreads();
+  lds_dit(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hi, p);
+  staged<8, uint32_t>(K2 << logL1, [&](int idx) {
+    return s[(idx >> logL1) * RS + (idx & (L1 - 1))];
+  }, [&](int idx, uint32_t v) {
+    const int j = idx >> logL1, e = idx & (L1 - 1);
+    if (y0 + e < nlimit) base[(int64_t)j * L + e] = v;
+  });
+}
+
+// ------------------------------------------------------------------------------------
 // RecoveringProduct.  For each output coefficient i and each j < 2K-1:
 //   c_{i,j} from its np residues by CRT into (-P/2, P/2) (exact because
 //   |c_{i,j}| < d K 2^(2M) < P/4), as W-word two's complement;

@@ -28,6 +28,8 @@ def ctx():
     (300, 513, 400, 600, 0),
     (2000, 257, 3000, 300, 0),        # column passes
     (700, 900, 800, 1000, 64),        # x-transforms in LDS
+    (900, 700, 1200, 800, 32),        # x-transforms one half at a time
+    (4000, 600, 5000, 700, 32),
     (5000, 64, 5000, 64, 0),
     (1, 4000, 50, 4000, 0),
 ])

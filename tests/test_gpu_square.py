@@ -40,6 +40,7 @@ def square_check(ctx, A, d, N, **kw):
     (1, 63, 0), (7, 200, 0), (300, 513, 0), (1000, 64, 0), (2500, 1500, 0),
     (5000, 300, 0),                       # column passes
     (700, 900, 64), (3000, 2000, 128),    # x-transforms in LDS
+    (900, 700, 32), (6000, 1000, 32),     # x-transforms one half at a time
     (4097, 257, 8), (3, 5000, 0),
 ])
 def test_square_random(ctx, d, bits, K):
