@@ -351,6 +351,9 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   const uint32_t R = pr.c32;   // 2^32 mod p
   uint32_t cur = mul_shoup(R, heap_root(tab, m, (inner * e0) & (m - 1), p), p);
   const uint32_t step = mul_shoup(R, heap_root(tab, m, (inner * de) & (m - 1), p), p);
+  // offsets inside the column stay below L <= 2^21: 32-bit index arithmetic
+  const int S32 = (int)S;
+  const int lim_store = (int)std::min<int64_t>(std::max<int64_t>(nlimit - first, 0), L);
   if (!inverse) {
     staged<8, uint32_t>(n << logT, [&](int idx) {
       const int tt = idx & (T - 1), e = idx >> logT;
@@ -362,7 +365,7 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     for (int e = e0; e < n; e += de) {
       const uint32_t v = mont_mul(s[(bitrev(e, logn) << logT) + t], cur, p, pr.pinv);
       cur = mont_mul(cur, step, p, pr.pinv);
-      base[t + S * (int64_t)e] = v;
+      base[t + S32 * e] = v;
     }
   } else {
     // eight independent loads in flight per thread, then the twiddle progression
@@ -371,7 +374,7 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int ee = e + u * de;
-        v[u] = ee < n ? base[t + S * (int64_t)ee] : 0u;
+        v[u] = ee < n ? base[t + S32 * ee] : 0u;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -385,9 +388,8 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     __syncthreads();
     lds_dit(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hi, p);
     staged<8, uint32_t>(n << logT, [&](int idx) { return s[idx]; }, [&](int idx, uint32_t v) {
-      const int tt = idx & (T - 1), e = idx >> logT;
-      const int64_t off = tt + S * (int64_t)e;
-      if (first + off < nlimit) base[off] = v;
+      const int off = (idx & (T - 1)) + S32 * (idx >> logT);
+      if (off < lim_store) base[off] = v;
     });
   }
 }
@@ -526,6 +528,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
   const uint32_t p = pr.p;
   uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
   const int64_t y0 = rb * L1;
+  const int L32 = (int)L;   // 2K rows of at most 2^21 words: 32-bit row offsets
   // LDS rows 0..K-1: limbs of a (of b for CM_SPECTRUM); rows K..2K-1: limbs of b
   // (CM_PRODUCT only)
   constexpr bool one = MODE != CM_PRODUCT;
@@ -534,7 +537,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
   staged<8, uint32_t>(rows << logL1, [&](int idx) {
     const int j = src0 + (idx >> logL1), e = idx & (L1 - 1);
     const int64_t nz = j < K ? nz_a : nz_b;
-    return (y0 + e < nz) ? base[(int64_t)j * L + e] : 0u;
+    return (y0 + e < nz) ? base[j * L32 + e] : 0u;
   }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
   __syncthreads();
   lds_dif(s, LdsShape{one ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
@@ -546,7 +549,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
       for (int j = 0; j < K; ++j) x[j] = s[j * RS + e];
       reg_dif<LOGK>(x, pr.hf, p);
 #pragma unroll
-      for (int j = 0; j < K2; ++j) base[(int64_t)j * L + e] = x[j];
+      for (int j = 0; j < K2; ++j) base[j * L32 + e] = x[j];
     }
     return;
   }
@@ -565,7 +568,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
       } else {
 #pragma unroll
         for (int j = 0; j < K2; ++j)
-          a[j] = mul_shoup(mont_mul(a[j], sb[(int64_t)j * L + e], p, pr.pinv), sc, p);
+          a[j] = mul_shoup(mont_mul(a[j], sb[j * L32 + e], p, pr.pinv), sc, p);
       }
       reg_dit<LOGK>(a, pr.hi, p);
 #pragma unroll
@@ -599,7 +602,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
     return s[(idx >> logL1) * RS + (idx & (L1 - 1))];
   }, [&](int idx, uint32_t v) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
-    if (y0 + e < nlimit) base[(int64_t)j * L + e] = v;
+    if (y0 + e < nlimit) base[j * L32 + e] = v;
   });
 }
 
@@ -669,13 +672,14 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
   const uint32_t p = pr.p;
   uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
   const int64_t y0 = rb * L1;
+  const int L32 = (int)L;   // 2K rows of at most 2^21 words: 32-bit row offsets
   constexpr bool one = MODE != CM_PRODUCT;
   constexpr int rows = one ? K : K2;
   constexpr int src0 = MODE == CM_SPECTRUM ? K : 0;
   staged<8, uint32_t>(rows << logL1, [&](int idx) {
     const int j = src0 + (idx >> logL1), e = idx & (L1 - 1);
     const int64_t nz = j < K ? nz_a : nz_b;
-    return (y0 + e < nz) ? base[(int64_t)j * L + e] : 0u;
+    return (y0 + e < nz) ? base[j * L32 + e] : 0u;
   }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
   __syncthreads();
   lds_dif(s, LdsShape{one ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
@@ -694,12 +698,12 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
       for (int j = 0; j < K; ++j) x[j] = s[j * RS + e];
       twisted(x);
 #pragma unroll
-      for (int j = 0; j < K; ++j) base[(int64_t)(K + j) * L + e] = x[j];
+      for (int j = 0; j < K; ++j) base[(K + j) * L32 + e] = x[j];
 #pragma unroll
       for (int j = 0; j < K; ++j) x[j] = s[j * RS + e];
       reg_half_dif<LOGK>(x, hf, p);
 #pragma unroll
-      for (int j = 0; j < K; ++j) base[(int64_t)j * L + e] = x[j];
+      for (int j = 0; j < K; ++j) base[j * L32 + e] = x[j];
     }
     return;
   }
@@ -739,7 +743,7 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
       twisted(x);
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        const uint32_t f = MODE == CM_SQUARE ? x[j] : sb[(int64_t)(K + j) * L + e];
+        const uint32_t f = MODE == CM_SQUARE ? x[j] : sb[(K + j) * L32 + e];
         x[j] = mul_shoup(mont_mul(x[j], f, p, pr.pinv), sc, p);
       }
       uint32_t t[K];
@@ -750,7 +754,7 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
       reg_half_dif<LOGK>(t, hf, p);
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        const uint32_t f = MODE == CM_SQUARE ? t[j] : sb[(int64_t)j * L + e];
+        const uint32_t f = MODE == CM_SQUARE ? t[j] : sb[j * L32 + e];
         s[j * RS + e] = mul_shoup(mont_mul(t[j], f, p, pr.pinv), sc, p);
       }
     }
@@ -778,7 +782,7 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
     return s[(idx >> logL1) * RS + (idx & (L1 - 1))];
   }, [&](int idx, uint32_t v) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
-    if (y0 + e < nlimit) base[(int64_t)j * L + e] = v;
+    if (y0 + e < nlimit) base[j * L32 + e] = v;
   });
 }
 
