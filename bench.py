@@ -328,6 +328,45 @@ def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: 
     return out
 
 
+def p64_leg(ctx, a, b, prod, steps: int, product_ms: float, configs=((0, 0), (128, 2))) -> dict:
+    """The 64-bit machine-word prime variant on the same operands: the planner's choice and
+    the paper's own two-prime configuration (K = 128, M = 33 for N = 4097)."""
+    import torch
+    from paper_1612_05778_amd.api import plan_p64
+    from paper_1612_05778_amd.workmodel import product_bits
+    bits = product_bits(prod.da, prod.Na, prod.db, prod.Nb)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    res = []
+    for K, np_ in configs:
+        try:
+            pl = plan_p64(prod.da, prod.Na, prod.db, prod.Nb, K=K, np=np_)
+        except RuntimeError:
+            continue
+        print(f"[bench] p64 K={pl['K']} M={pl['M']} np={pl['np']}", file=sys.stderr, flush=True)
+        out = ctx.mul_p64(a, prod.Na, b, prod.Nb, K=K, np=np_)
+        for _ in range(2):
+            ctx.mul_p64(a, prod.Na, b, prod.Nb, K=K, np=np_, out=out)
+        torch.cuda.synchronize()
+        ctx.profile_begin()
+        e0.record(stream)
+        for _ in range(steps):
+            ctx.mul_p64(a, prod.Na, b, prod.Nb, K=K, np=np_, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kernels = ctx.profile_end()
+        ms = e0.elapsed_time(e1) / steps
+        res.append({"K": pl["K"], "M": pl["M"], "np": pl["np"], "log2_L": pl["log2_L"],
+                    "y_passes_log2n": pl["pass_log2n"], "ms": ms, "value": bits / (ms / 1e3),
+                    "vs_product": product_ms / ms,
+                    "kernels": {k: {"launches_per_step": n / steps, "ms_per_step": t / steps}
+                                for k, (n, t) in kernels.items()}})
+        del out
+        torch.cuda.empty_cache()
+    return {"plans": res}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -340,6 +379,9 @@ def main() -> int:
     ap.add_argument("--only-product", action="store_true",
                     help="time the product alone: no square, resident-operand, batched, served "
                          "or cpu_baseline legs (for profiling the product's kernels)")
+    ap.add_argument("--no-p64", action="store_true", help="skip the 64-bit prime leg")
+    ap.add_argument("--only-p64", action="store_true",
+                    help="time the 64-bit prime variant alone (for profiling its kernels)")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson) leg")
     ap.add_argument("--served-requests", type=int, default=20000)
@@ -445,6 +487,11 @@ def main() -> int:
         "roofline": roof,
         "kernels": kinfo,
     }
+    if args.only_p64:
+        print(json.dumps({"workload": args.workload,
+                          "p64": p64_leg(ctx, a, b, prod, args.steps, ms)}), flush=True)
+        ctx.close()
+        return 0
     if args.only_product:
         args.no_batch = args.no_served = args.no_cpu = True
         print(json.dumps(line), flush=True)
@@ -474,6 +521,8 @@ def main() -> int:
     op_ms = e0.elapsed_time(e1) / args.steps
     line["resident_operand"] = {"ms": op_ms, "value": bits / (op_ms / 1e3), "vs_product": ms / op_ms}
     op.close()
+    if not args.no_p64:
+        line["p64"] = p64_leg(ctx, a, b, prod, args.steps, ms)
     if not args.no_batch:
         line["batched"] = batch_leg(ctx, args.batch_reps)
     if not args.no_served:

@@ -300,6 +300,41 @@ int zpm_mul_operand(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, con
 int zpm_operand_info(const zpm_operand *op, zpm_plan_info *out);
 void zpm_operand_destroy(zpm_operand *op);
 
+/* 64-bit machine-word primes (Section 4: the modulus is one machine-word Fourier
+ * prime or the product of two or three of them, combined by the Chinese remaindering
+ * algorithm; the paper's implementation uses two).  Same method and result as
+ * zpm_mul: K limbs of M bits, the 2K x L cyclic convolution of the zero-padded limb
+ * arrays (cyclic and negacyclic parts of Section 2.1 as the even and odd x-frequencies),
+ * Garner's CRT into (-P/2, P/2) and evaluation at 2^M with carries (Section 2.2).
+ * Primes are the three largest p < 2^62 with 2^21 | p - 1.  np <= 3 bounds M:
+ * 2M + log2(4 max(da, db) K) < log2 P <= 186.  K: power of two up to 512. */
+typedef struct zpm_p64_info {
+  int64_t da, db;
+  int32_t Na, Nb;
+  int32_t K, M, np;
+  int32_t log2_L;         /* cyclic length along y */
+  int32_t npass;          /* strided passes of the y-transform */
+  int32_t pass_log2n[3];  /* their lengths, outermost first */
+  int32_t log2_tx;        /* y positions per workgroup of the x-convolution kernel */
+  int32_t log2_ti;        /* coefficients per workgroup of the recovery */
+  int32_t log2P;          /* bit length of the prime product */
+  int32_t nout_bits;
+  int64_t workspace_bytes;  /* np * 2K * L * 8 */
+} zpm_p64_info;
+
+/* Planner of the 64-bit prime variant (host only).  K, np: 0 = choose.  ZPM_EINVAL for
+ * bad sizes, ZPM_EUNSUPPORTED when no plan with np <= 3 exists. */
+int zpm_plan_p64(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np,
+                 zpm_p64_info *out);
+/* The k-th 64-bit prime (k < 3, largest first) and a primitive 2^21-th root of unity. */
+int zpm_prime64(int32_t k, uint64_t *p, uint64_t *root);
+/* c = a * b with 64-bit primes; arguments, encodings, ownership, errors and stream
+ * rules as for zpm_mul (a square when b is a); K, np as in zpm_plan_p64.  The context
+ * keeps this variant's tables and workspace apart from zpm_mul's. */
+int zpm_mul_p64(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
+                int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t K, int32_t np,
+                void *stream);
+
 /* Wait for the stream and report any device error raised by earlier calls. */
 int zpm_sync(zpm_ctx *ctx, void *stream);
 

@@ -173,6 +173,27 @@ zpm_mul_kronecker = _sig("zpm_mul_kronecker", ctypes.c_int,
 zpm_kronecker_plan = _sig("zpm_kronecker_plan", ctypes.c_int,
                           [c_i64, c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(KronInfo)])
 
+
+
+class P64Info(ctypes.Structure):
+    _fields_ = [("da", c_i64), ("db", c_i64), ("Na", c_i32), ("Nb", c_i32), ("K", c_i32),
+                ("M", c_i32), ("np", c_i32), ("log2_L", c_i32), ("npass", c_i32),
+                ("pass_log2n", c_i32 * 3), ("log2_tx", c_i32), ("log2_ti", c_i32),
+                ("log2P", c_i32), ("nout_bits", c_i32), ("workspace_bytes", c_i64)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["pass_log2n"] = list(self.pass_log2n)[: self.npass]
+        return d
+
+
+zpm_plan_p64 = _sig("zpm_plan_p64", ctypes.c_int,
+                    [c_i64, c_i32, c_i64, c_i32, c_i32, c_i32, ctypes.POINTER(P64Info)])
+zpm_prime64 = _sig("zpm_prime64", ctypes.c_int,
+                   [c_i32, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)])
+zpm_mul_p64 = _sig("zpm_mul_p64", ctypes.c_int,
+                   [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp])
+
 EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
            "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync",
            "zpm_profile_begin", "zpm_profile_end", "zpm_mul_batch", "zpm_mul_batch_ex",
@@ -182,7 +203,7 @@ EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime
            "zpm_server_wait", "zpm_server_completions", "zpm_server_stats",
            "zpm_server_reset_stats", "zpm_server_destroy", "zpm_operand_create",
            "zpm_mul_operand", "zpm_operand_info", "zpm_operand_destroy", "zpm_mul_kronecker",
-           "zpm_kronecker_plan"]
+           "zpm_kronecker_plan", "zpm_plan_p64", "zpm_prime64", "zpm_mul_p64"]
 
 
 class ZpmError(RuntimeError):

@@ -34,6 +34,20 @@ def kronecker_plan(da: int, Na: int, db: int, Nb: int, chunk_bits: int = 0) -> d
     return info.as_dict()
 
 
+def plan_p64(da: int, Na: int, db: int, Nb: int, K: int = 0, np: int = 0) -> dict:
+    """Plan of the 64-bit prime variant (host only); K, np: 0 = choose."""
+    info = nat.P64Info()
+    nat.check(nat.zpm_plan_p64(da, Na, db, Nb, K, np, ctypes.byref(info)), "zpm_plan_p64")
+    return info.as_dict()
+
+
+def prime64(k: int) -> tuple[int, int]:
+    """The k-th 64-bit prime (largest first) and a primitive 2^21-th root of unity."""
+    p, r = ctypes.c_uint64(), ctypes.c_uint64()
+    nat.check(nat.zpm_prime64(k, ctypes.byref(p), ctypes.byref(r)), "zpm_prime64")
+    return p.value, r.value
+
+
 def device_limits(device: int = 0) -> dict:
     ncu, lb, lc = nat.c_i32(), nat.c_i64(), nat.c_i64()
     nat.check(nat.zpm_device_limits(device, ctypes.byref(ncu), ctypes.byref(lb), ctypes.byref(lc)),
@@ -148,6 +162,22 @@ class Context:
         nat.check(nat.zpm_mul_kronecker(self._h, a.data_ptr(), da, Na, b.data_ptr(), db, Nb,
                                         out.data_ptr() if n else None, out.shape[1] if n else wc,
                                         chunk_bits, _stream_handle(stream)), "zpm_mul_kronecker")
+        return out
+
+    def mul_p64(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int, K: int = 0, np: int = 0,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """c = a * b with one to three 64-bit primes (zpm_mul_p64); K, np: 0 = choose."""
+        da = _check_operand(a, Na, "a")
+        db = _check_operand(b, Nb, "b")
+        n = da + db - 1 if (da and db) else 0
+        wc = out_words(da, Na, db, Nb) if n else 1
+        if out is None:
+            out = torch.empty((n, wc), dtype=torch.int64, device=a.device)
+        elif out.shape != (n, wc) or out.dtype != torch.int64 or not out.is_contiguous():
+            raise ValueError("out has the wrong shape or dtype")
+        nat.check(nat.zpm_mul_p64(self._h, a.data_ptr(), da, Na, b.data_ptr(), db, Nb,
+                                  out.data_ptr() if n else None, wc, K, np, _stream_handle(stream)),
+                  "zpm_mul_p64")
         return out
 
     def mul_stage(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int, stop_after: int,

@@ -11,6 +11,7 @@
 #include "../../include/zpm.h"
 #include "ctx.hpp"
 #include "kernels.hpp"
+#include "p64.hpp"
 #include "nt.hpp"
 #include "plan.hpp"
 
@@ -141,6 +142,7 @@ int Ctx::prepare(const Plan &pl, DevState *ds) {
 }
 
 Ctx::~Ctx() {
+  p64_release(*this);
   if (!primes) return;   // a host-only context (planning) owns no device resources
   (void)hipSetDevice(device);
   (void)hipDeviceSynchronize();
@@ -298,7 +300,9 @@ int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t
   std::lock_guard<std::mutex> lock(cx->mu);
   static const char *names[KK_COUNT] = {"bivariate_representation", "col_pass_fwd",
                                         "convolve_rows", "col_pass_inv",
-                                        "recovering_product", "batch"};
+                                        "recovering_product", "batch",
+                                        "p64_convert_in", "p64_y_fwd", "p64_x_convolve",
+                                        "p64_y_inv", "p64_recover"};
   double ms[KK_COUNT] = {0};
   int64_t cnt[KK_COUNT] = {0};
   int rc = ZPM_OK;
@@ -356,6 +360,56 @@ int zpm_kronecker_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t c
   out->wc2 = kp.wc2;
   fill_info(kp.inner, &out->inner);
   return ZPM_OK;
+}
+
+static void fill_info64(const Plan64 &pl, zpm_p64_info *out) {
+  std::memset(out, 0, sizeof(*out));
+  out->da = pl.da;
+  out->db = pl.db;
+  out->Na = pl.Na;
+  out->Nb = pl.Nb;
+  out->K = pl.K;
+  out->M = pl.M;
+  out->np = pl.np;
+  out->log2_L = pl.logL;
+  out->npass = pl.npass;
+  for (int q = 0; q < pl.npass; ++q) out->pass_log2n[q] = pl.pass[q].logn;
+  out->log2_tx = pl.logTX;
+  out->log2_ti = pl.logTI;
+  out->log2P = pl.log2P;
+  out->nout_bits = pl.nout_bits;
+  out->workspace_bytes = pl.ws_words * 8;
+}
+
+int zpm_plan_p64(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np,
+                 zpm_p64_info *out) {
+  if (!out || K < 0 || np < 0 || da < 1 || db < 1 || Na < 1 || Nb < 1) return ZPM_EINVAL;
+  Plan64 pl;
+  if (!make_plan64(da, Na, db, Nb, K, np, pl, nullptr)) return ZPM_EUNSUPPORTED;
+  fill_info64(pl, out);
+  return ZPM_OK;
+}
+
+int zpm_prime64(int32_t k, uint64_t *p, uint64_t *root) {
+  if (k < 0 || k >= MAXNP64 || !p || !root) return ZPM_EINVAL;
+  *p = prime64_table()[k].p;
+  *root = prime64_table()[k].root;
+  return ZPM_OK;
+}
+
+int zpm_mul_p64(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b, int64_t db,
+                int32_t Nb, uint64_t *c, int32_t wc, int32_t K, int32_t np, void *stream) {
+  if (!ctx || K < 0 || np < 0) return ZPM_EINVAL;
+  int rc = check_mul_args(a, da, Na, b, db, Nb, c, wc);
+  if (rc != ZPM_OK) return rc;
+  if (da == 0 || db == 0) return ZPM_OK;
+  Plan64 pl;
+  if (!make_plan64(da, Na, db, Nb, K, np, pl, nullptr)) return ZPM_EUNSUPPORTED;
+  pl.square = (a == b && da == db && Na == Nb) ? 1 : 0;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  std::lock_guard<std::mutex> lock(cx->mu);
+  if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  return mul_p64(*cx, pl, a, b, c, wc, reinterpret_cast<hipStream_t>(stream));
 }
 
 // A resident operand: b's spectra under a plan sized for products with any a of at

@@ -13,7 +13,12 @@ enum KernelKind {
   KK_COL_INV = 3,
   KK_RECOVER = 4,
   KK_BATCH = 5,
-  KK_COUNT = 6
+  KK_P64_CONVERT = 6,   // 64-bit prime variant
+  KK_P64_YFWD = 7,
+  KK_P64_X = 8,
+  KK_P64_YINV = 9,
+  KK_P64_RECOVER = 10,
+  KK_COUNT = 11
 };
 
 struct Profiler {
