@@ -328,6 +328,51 @@ def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: 
     return out
 
 
+P64_CONFIGS = {"default": ((0, 0),), "paper": ((128, 2),), "both": ((0, 0), (128, 2))}
+
+
+def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
+    """Achieved HBM bytes/s (read + write) of a plain device copy of `mib` MiB."""
+    import torch
+    n = mib << 17
+    src = torch.ones(n, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / (ms / 1e3)
+
+
+def p64_bytes(pl: dict, prod) -> dict:
+    """Algorithmic HBM bytes per step of each 64-bit-prime kernel group: every residue
+    read and written once per pass; the first forward pass reads only the d nonzero rows,
+    the last inverse pass writes only the da + db - 1 output rows."""
+    np_, K, L = pl["np"], pl["K"], 1 << pl["log2_L"]
+    nout = prod.da + prod.db - 1
+    wa, wb = (prod.Na + 63) // 64, (prod.Nb + 63) // 64
+    wc = (pl["nout_bits"] + 63) // 64
+    col = 8 * np_ * 2 * K * L                     # one full pass over the spectra
+    npass = len(pl["pass_log2n"])
+    rows_in = 8 * np_ * K * (prod.da + prod.db)   # nonzero limb rows of a and b
+    last_out = 8 * np_ * 2 * K * nout
+    return {
+        "p64_convert_in": 8 * (prod.da * wa + prod.db * wb) + rows_in,
+        "p64_y_fwd": (rows_in + col + 2 * col * (npass - 1)) if npass else 0,
+        "p64_x_convolve": 2 * col,
+        "p64_y_inv": (2 * col * (npass - 1) + col + last_out) if npass else 0,
+        "p64_recover": last_out + 8 * nout * wc,
+    }
+
+
 def p64_leg(ctx, a, b, prod, steps: int, product_ms: float, configs=((0, 0), (128, 2))) -> dict:
     """The 64-bit machine-word prime variant on the same operands: the planner's choice and
     the paper's own two-prime configuration (K = 128, M = 33 for N = 4097)."""
@@ -357,11 +402,17 @@ def p64_leg(ctx, a, b, prod, steps: int, product_ms: float, configs=((0, 0), (12
         torch.cuda.synchronize()
         kernels = ctx.profile_end()
         ms = e0.elapsed_time(e1) / steps
+        alg = p64_bytes(pl, prod)
+        kin = {}
+        for k, (n, t) in kernels.items():
+            kin[k] = {"launches_per_step": n / steps, "ms_per_step": t / steps,
+                      "algorithmic_bytes": alg.get(k)}
+            if alg.get(k):
+                kin[k]["GBps"] = alg[k] / (t / steps / 1e3) / 1e9
+                kin[k]["hbm_frac"] = alg[k] / (t / steps / 1e3) / 8.0e12
         res.append({"K": pl["K"], "M": pl["M"], "np": pl["np"], "log2_L": pl["log2_L"],
                     "y_passes_log2n": pl["pass_log2n"], "ms": ms, "value": bits / (ms / 1e3),
-                    "vs_product": product_ms / ms,
-                    "kernels": {k: {"launches_per_step": n / steps, "ms_per_step": t / steps}
-                                for k, (n, t) in kernels.items()}})
+                    "vs_product": product_ms / ms, "kernels": kin})
         del out
         torch.cuda.empty_cache()
     return {"plans": res}
@@ -382,6 +433,8 @@ def main() -> int:
     ap.add_argument("--no-p64", action="store_true", help="skip the 64-bit prime leg")
     ap.add_argument("--only-p64", action="store_true",
                     help="time the 64-bit prime variant alone (for profiling its kernels)")
+    ap.add_argument("--p64-config", default="both", choices=["default", "paper", "both"],
+                    help="64-bit prime plans to time: the planner's, the paper's two-prime one, or both")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson) leg")
     ap.add_argument("--served-requests", type=int, default=20000)
@@ -433,7 +486,17 @@ def main() -> int:
     print(f"[bench] plan K={pl['K']} M={pl['M']} np={pl['np']} L=2^{pl['log2_L']}; timing "
           f"{args.steps} steps", file=sys.stderr, flush=True)
 
+    # per-kernel breakdown: every kernel bracketed by events (a few microseconds each,
+    # so this run is not the headline timing)
     ctx.profile_begin()
+    for _ in range(args.steps):
+        ctx.mul(a, prod.Na, b, prod.Nb, out=out)
+    torch.cuda.synchronize()
+    kernels = ctx.profile_end()
+    dom = max(kernels, key=lambda k: kernels[k][1])
+
+    # timed region: events around the dominant kernel only, for its live duration
+    ctx.profile_begin(kinds=[dom])
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -444,7 +507,7 @@ def main() -> int:
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    kernels = ctx.profile_end()
+    kernels_timed = ctx.profile_end()
     ctx.sync()
     ms = e0.elapsed_time(e1) / args.steps
     bits = product_bits(prod.da, prod.Na, prod.db, prod.Nb)
@@ -453,11 +516,13 @@ def main() -> int:
     # dominant kernel and its roofline
     kinfo = {}
     for name, (launches, tot) in kernels.items():
+        if name == dom:
+            launches, tot = kernels_timed[name]
         work = kernel_work(pl, name)
         per = tot / launches
         kinfo[name] = {"launches_per_step": launches / args.steps, "avg_ms": per,
-                       "share": tot / (ms * args.steps), **work}
-    dom = max(kinfo, key=lambda k: kinfo[k]["avg_ms"] * kinfo[k]["launches_per_step"])
+                       "share": tot / (ms * args.steps), **work,
+                       "timed_in": "timed region" if name == dom else "breakdown run"}
     d = kinfo[dom]
     if d["ops"]:
         achieved = d["ops"] / (d["avg_ms"] / 1e3)
@@ -476,6 +541,49 @@ def main() -> int:
             v["int32_Tops"] = v["ops"] / (v["avg_ms"] / 1e3) / 1e12
         v["GBps"] = v["bytes"] / (v["avg_ms"] / 1e3) / 1e9
 
+    # per-step distribution (a second run of the same steps, one event pair per step)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record(stream)
+    for s_ in range(args.steps):
+        ctx.mul(a, prod.Na, b, prod.Nb, out=out)
+        ev[s_ + 1].record(stream)
+    torch.cuda.synchronize()
+    per_step = sorted(ev[s_].elapsed_time(ev[s_ + 1]) for s_ in range(args.steps))
+    step_stats = {"median_ms": per_step[len(per_step) // 2],
+                  "p99_ms": per_step[min(len(per_step) - 1, int(0.99 * len(per_step)))],
+                  "min_ms": per_step[0]}
+
+    # the whole path against its roofline: T* = sum over kernels of max(bytes / BW, ops / ALU)
+    copy_bw = copy_bandwidth()
+
+    def t_star(bw):
+        return 1e3 * sum(v["launches_per_step"] * max(v["bytes"] / bw, (v["ops"] or 0) / INT32_PEAK)
+                         for v in kinfo.values())
+    path = {"t_star_ms": t_star(HBM_PEAK), "frac": t_star(HBM_PEAK) / ms,
+            "t_star_measured_copy_ms": t_star(copy_bw), "frac_measured_copy": t_star(copy_bw) / ms,
+            "copy_GBps": copy_bw / 1e9, "alu_peak_Tops": INT32_PEAK / 1e12}
+
+    # host <-> device transfers of the operands and the product (pinned host buffers);
+    # not part of the timed region
+    ha = torch.empty(a.shape, dtype=a.dtype, pin_memory=True)
+    hb = torch.empty(b.shape, dtype=b.dtype, pin_memory=True)
+    hc = torch.empty(out.shape, dtype=out.dtype, pin_memory=True)
+    ha.copy_(a); hb.copy_(b)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    a.copy_(ha, non_blocking=True)
+    b.copy_(hb, non_blocking=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    h2d = e0.elapsed_time(e1)
+    e0.record(stream)
+    hc.copy_(out, non_blocking=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    d2h = e0.elapsed_time(e1)
+    pcie = {"h2d_ms": h2d, "d2h_ms": d2h, "value_with_transfers": bits / ((ms + h2d + d2h) / 1e3)}
+    del ha, hb, hc
+
     line = {
         "metric": METRIC, "value": value, "unit": "coeff-bits/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -485,11 +593,14 @@ def main() -> int:
                    "plan": {k: pl[k] for k in ("K", "M", "np", "log2_L", "log2_L1", "col_log2n", "W")},
                    "wall_ms_per_step": wall * 1e3 / args.steps},
         "roofline": roof,
+        "path_roofline": path,
+        "step_ms": step_stats,
+        "transfers": pcie,
         "kernels": kinfo,
     }
     if args.only_p64:
         print(json.dumps({"workload": args.workload,
-                          "p64": p64_leg(ctx, a, b, prod, args.steps, ms)}), flush=True)
+                          "p64": p64_leg(ctx, a, b, prod, args.steps, ms, P64_CONFIGS[args.p64_config])}), flush=True)
         ctx.close()
         return 0
     if args.only_product:
@@ -522,7 +633,7 @@ def main() -> int:
     line["resident_operand"] = {"ms": op_ms, "value": bits / (op_ms / 1e3), "vs_product": ms / op_ms}
     op.close()
     if not args.no_p64:
-        line["p64"] = p64_leg(ctx, a, b, prod, args.steps, ms)
+        line["p64"] = p64_leg(ctx, a, b, prod, args.steps, ms, P64_CONFIGS[args.p64_config])
     if not args.no_batch:
         line["batched"] = batch_leg(ctx, args.batch_reps)
     if not args.no_served:

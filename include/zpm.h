@@ -177,6 +177,12 @@ typedef struct zpm_kernel_time {
   double total_ms;
 } zpm_kernel_time;
 int zpm_profile_begin(zpm_ctx *ctx);
+/* As zpm_profile_begin, but only kernels whose kind k has bit k set in `kinds` are
+ * bracketed (each pair of events adds a few microseconds between kernels).  Kinds:
+ * 0 bivariate_representation, 1 col_pass_fwd, 2 convolve_rows, 3 col_pass_inv,
+ * 4 recovering_product, 5 batch, 6 p64_convert_in, 7 p64_y_fwd, 8 p64_x_convolve,
+ * 9 p64_y_inv, 10 p64_recover. */
+int zpm_profile_begin_kinds(zpm_ctx *ctx, uint32_t kinds);
 int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t *n_out);
 
 /* Serving by continuous batching.  A server runs a worker thread with n_streams

@@ -104,6 +104,7 @@ class KernelTime(ctypes.Structure):
 
 
 zpm_profile_begin = _sig("zpm_profile_begin", ctypes.c_int, [c_vp])
+zpm_profile_begin_kinds = _sig("zpm_profile_begin_kinds", ctypes.c_int, [c_vp, ctypes.c_uint32])
 zpm_profile_end = _sig("zpm_profile_end", ctypes.c_int,
                        [c_vp, ctypes.POINTER(KernelTime), c_i32, ctypes.POINTER(c_i32)])
 
@@ -196,7 +197,7 @@ zpm_mul_p64 = _sig("zpm_mul_p64", ctypes.c_int,
 
 EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
            "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync",
-           "zpm_profile_begin", "zpm_profile_end", "zpm_mul_batch", "zpm_mul_batch_ex",
+           "zpm_profile_begin", "zpm_profile_begin_kinds", "zpm_profile_end", "zpm_mul_batch", "zpm_mul_batch_ex",
            "zpm_device_limits", "zpm_batch_schedule", "zpm_tune", "zpm_tune_load",
            "zpm_tune_get", "zpm_server_create", "zpm_server_create_ex",
            "zpm_server_create_simulated", "zpm_server_submit", "zpm_server_poll",

@@ -34,6 +34,11 @@ def kronecker_plan(da: int, Na: int, db: int, Nb: int, chunk_bits: int = 0) -> d
     return info.as_dict()
 
 
+KERNEL_KINDS = ["bivariate_representation", "col_pass_fwd", "convolve_rows", "col_pass_inv",
+                "recovering_product", "batch", "p64_convert_in", "p64_y_fwd", "p64_x_convolve",
+                "p64_y_inv", "p64_recover"]
+
+
 def plan_p64(da: int, Na: int, db: int, Nb: int, K: int = 0, np: int = 0) -> dict:
     """Plan of the 64-bit prime variant (host only); K, np: 0 = choose."""
     info = nat.P64Info()
@@ -267,8 +272,15 @@ class Context:
         nat.check(nat.zpm_tune_get(self._h, cl, ks, ts, n.value, ctypes.byref(n)), "zpm_tune_get")
         return {cl[i]: (ks[i], ts[i]) for i in range(n.value)}
 
-    def profile_begin(self) -> None:
-        nat.check(nat.zpm_profile_begin(self._h), "zpm_profile_begin")
+    def profile_begin(self, kinds=None) -> None:
+        """Start per-kernel timing, of every kernel or only of the named kinds."""
+        if kinds is None:
+            nat.check(nat.zpm_profile_begin(self._h), "zpm_profile_begin")
+        else:
+            mask = 0
+            for k in kinds:
+                mask |= 1 << KERNEL_KINDS.index(k)
+            nat.check(nat.zpm_profile_begin_kinds(self._h, mask), "zpm_profile_begin_kinds")
 
     def profile_end(self) -> dict:
         """{kernel name: (launches, total GPU ms)} since profile_begin."""

@@ -285,14 +285,17 @@ int zpm_mul(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint6
   return zpm_mul_ex(ctx, a, da, Na, b, db, Nb, c, wc, 0, 0, 0, nullptr, stream);
 }
 
-int zpm_profile_begin(zpm_ctx *ctx) {
+int zpm_profile_begin_kinds(zpm_ctx *ctx, uint32_t kinds) {
   if (!ctx) return ZPM_EINVAL;
   Ctx *cx = reinterpret_cast<Ctx *>(ctx);
   std::lock_guard<std::mutex> lock(cx->mu);
   cx->prof.reset();
+  cx->prof.mask = kinds;
   cx->prof.on = true;
   return ZPM_OK;
 }
+
+int zpm_profile_begin(zpm_ctx *ctx) { return zpm_profile_begin_kinds(ctx, ~0u); }
 
 int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t *n_out) {
   if (!ctx || !n_out || (max_out > 0 && !out)) return ZPM_EINVAL;

@@ -23,6 +23,8 @@ enum KernelKind {
 
 struct Profiler {
   bool on = false;
+  uint32_t mask = ~0u;   // kinds recorded while on (bit k = KernelKind k)
+  bool open = false;     // begin() recorded a start event that end() has not closed
   struct Rec {
     int kind;
     hipEvent_t a, b;
@@ -40,20 +42,24 @@ struct Profiler {
     return pool[used++];
   }
   void begin(int kind, hipStream_t st) {
-    if (!on) return;
+    open = false;
+    if (!on || !((mask >> kind) & 1u)) return;
     Rec r{kind, take(), take()};
     if (r.a && r.b) {
       (void)hipEventRecord(r.a, st);
       recs.push_back(r);
+      open = true;
     }
   }
   void end(hipStream_t st) {
-    if (!on || recs.empty()) return;
+    if (!on || !open) return;
     (void)hipEventRecord(recs.back().b, st);
+    open = false;
   }
   void reset() {
     recs.clear();
     used = 0;
+    open = false;
   }
   ~Profiler() {
     for (auto e : pool) (void)hipEventDestroy(e);
