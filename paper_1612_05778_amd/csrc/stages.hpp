@@ -21,18 +21,20 @@ __device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t p) 
   return min(d, d + p);
 }
 // x * w mod p for a constant w with Shoup companion ws = floor(w 2^32 / p); any x < 2^32.
+// x w - q p is written x w + q (2^32 - p), which compiles to one multiply-add.
 __device__ __forceinline__ uint32_t mul_shoup(uint32_t x, uint2 w, uint32_t p) {
-  uint32_t q = __umulhi(x, w.y);
-  uint32_t r = x * w.x - q * p;   // in [0, 2p)
-  return min(r, r - p);
+  const uint32_t q = __umulhi(x, w.y);
+  const uint32_t negp = 0u - p;
+  const uint32_t r = x * w.x + q * negp;   // in [0, 2p)
+  return min(r, r + negp);
 }
 // a * b * 2^-32 mod p (Montgomery), a, b < p.
 __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
   uint32_t lo = a * b, hi = __umulhi(a, b);
   uint32_t m = lo * pinv;
   uint32_t mp = __umulhi(m, p);
-  uint32_t r = hi - mp;
-  return hi < mp ? r + p : r;
+  uint32_t r = hi - mp;   // wraps above 2^32 - p when hi < mp, and then r + p < r
+  return min(r, r + p);
 }
 // w_m^e from a heap table (tab[m/2 + e] = w_m^e for e < m/2), any e in [0, m).
 __device__ __forceinline__ uint2 heap_root(const uint2 *__restrict__ tab, int64_t m, int64_t e, uint32_t p) {
