@@ -94,18 +94,23 @@ static bool finish(Plan &pl) {
   if (pl.W > MAXW) return false;
   const int wa = (pl.Na + 63) / 64, wb = (pl.Nb + 63) / 64;
   const int wmax = std::max(wa, wb);
-  // convert-in: stage TI coefficients (2w+1 words each) in LDS
+  // convert-in: stage TI coefficients (2w+1 words each) in LDS; the smallest tile whose
+  // K TI limbs still give every thread of the workgroup one
   const int pw_words = 2 * ((pl.M + 31) / 32) * pl.np + 2;   // staged 2^(32t) mod p table
   int lt = 6;
-  while (lt > 0 && ((2 * wmax + 1) << lt) + pw_words > LDS_WORDS) --lt;
+  while (lt > 0 && ((((2 * wmax + 1) << lt) + pw_words > LDS_WORDS) ||
+                    ((int64_t)pl.K << (lt - 1)) >= BLOCK))
+    --lt;
   if (((2 * wmax + 1) << lt) + pw_words > LDS_WORDS) return false;
   pl.log_ti_in = lt;
-  // recovery: TI coefficients x nw32 64-bit partial sums (<= 48 KiB), about 256-1024 items
+  // recovery: TI coefficients x nw32 64-bit partial sums (<= 48 KiB); the smallest tile
+  // that still gives the workgroup at least 192 of its 256 threads' worth of items, so
+  // that more workgroups share a CU's LDS
   const int64_t J = 2 * (int64_t)pl.K - 1;
   const int64_t nw32 = 2 * (int64_t)((pl.nout_bits + 63) / 64);
   lt = 6;
   const int64_t crt_words = (int64_t)(pl.np + 1) * pl.W + pl.W + 5 * pl.np + 2;
-  while (lt > 0 && ((nw32 << lt) * 2 > 12288 || (J << lt) > 1024)) --lt;
+  while (lt > 0 && ((nw32 << lt) * 2 > 12288 || (J << lt) > 1024 || (J << (lt - 1)) >= 192)) --lt;
   if ((nw32 << lt) * 2 + crt_words > LDS_WORDS) return false;
   pl.log_ti_out = lt;
   pl.ws_words = (int64_t)pl.np * 2 * pl.K << pl.logL;
