@@ -47,6 +47,9 @@ __global__ __launch_bounds__(BLOCK) void k_bivariate_representation(
 // Neighbouring tiles of a column read the two halves of the same 128-byte lines when
 // a tile is 16 columns wide: they are placed on one XCD, next to each other in its
 // dispatch order, so that the second read hits that XCD's L2.
+// CLOGN / CLOGT >= 0: a pass of 2^CLOGN points on tiles of 2^CLOGT columns, fixed at
+// compile time; -1, -1: any pass.
+template <int CLOGN, int CLOGT>
 __global__ __launch_bounds__(BLOCK) void k_col_pass(
     uint32_t *__restrict__ X, int64_t L, int32_t twoK, int32_t logn, int64_t S, int32_t logT,
     int64_t nz_a, int64_t nz_b, int32_t K, int64_t nlimit, int32_t inverse,
@@ -54,8 +57,8 @@ __global__ __launch_bounds__(BLOCK) void k_col_pass(
   extern __shared__ uint32_t s[];
   const int64_t bid = xcd_tile(nblocks);
   if (bid >= nblocks) return;
-  body_col_pass(s, bid, X, L, twoK, logn, S, logT, nz_a, nz_b, K, nlimit, inverse, primes, cols,
-                col0);
+  body_col_pass<CLOGN, CLOGT>(s, bid, X, L, twoK, logn, S, logT, nz_a, nz_b, K, nlimit, inverse,
+                              primes, cols, col0);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_convolve_rows(
@@ -66,22 +69,26 @@ __global__ __launch_bounds__(BLOCK) void k_convolve_rows(
   body_convolve(s, blockIdx.x, X, L, K, logK, logL1, nz_a, nz_b, nlimit, primes, pd, mode, spec);
 }
 
-template <int LOGK, int MODE>
+// CLOGL1 >= 0: inner factor fixed at compile time (the largest that fits, 2^(12 - LOGK));
+// -1: any.
+template <int LOGK, int MODE, int CLOGL1>
 __global__ __launch_bounds__(BLOCK) void k_convolve_rows_reg(
     uint32_t *__restrict__ X, int64_t L, int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
     const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd,
     const uint32_t *__restrict__ spec) {
   extern __shared__ uint32_t s[];
-  body_convolve_reg<LOGK, MODE>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd, spec);
+  body_convolve_reg<LOGK, MODE, CLOGL1>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd,
+                                        spec);
 }
 
-template <int LOGK, int MODE>
+template <int LOGK, int MODE, int CLOGL1>
 __global__ __launch_bounds__(BLOCK) void k_convolve_rows_split(
     uint32_t *__restrict__ X, int64_t L, int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
     const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd,
     const uint32_t *__restrict__ spec) {
   extern __shared__ uint32_t s[];
-  body_convolve_split<LOGK, MODE>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes, pd, spec);
+  body_convolve_split<LOGK, MODE, CLOGL1>(s, blockIdx.x, X, L, logL1, nz_a, nz_b, nlimit, primes,
+                                          pd, spec);
 }
 
 template <int NP>
@@ -148,9 +155,20 @@ hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, h
   const int64_t nz_b = (c == 0 && !inverse) ? pl.db : L;
   const int64_t nlimit = (c == 0 && inverse) ? pl.nout : L;
   const int64_t grid = 8 * ((blocks + 7) / 8);   // xcd_tile's shape
-  hipLaunchKernelGGL(k_col_pass, dim3((unsigned)grid), dim3(BLOCK), lds, st, ds.X, L, 2 * pl.K,
-                     logn, S, logT, nz_a, nz_b, pl.K, nlimit, inverse ? 1 : 0, ds.primes, blocks,
-                     cols, col0);
+#define ZPM_COL_ARGS                                                                         \
+  dim3((unsigned)grid), dim3(BLOCK), lds, st, ds.X, L, 2 * pl.K, logn, S, logT, nz_a, nz_b,   \
+      pl.K, nlimit, inverse ? 1 : 0, ds.primes, blocks, cols, col0
+#define ZPM_COL_FIXED(LN, LT)                                                                \
+  if (logn == LN && logT == LT) {                                                            \
+    hipLaunchKernelGGL((k_col_pass<LN, LT>), ZPM_COL_ARGS);                                  \
+    return hipGetLastError();                                                                \
+  }
+  // the planner's default tile for each pass length from 2^5 to 2^10
+  ZPM_COL_FIXED(5, 6) ZPM_COL_FIXED(6, 5) ZPM_COL_FIXED(7, 4) ZPM_COL_FIXED(8, 3)
+  ZPM_COL_FIXED(9, 3) ZPM_COL_FIXED(10, 3)
+#undef ZPM_COL_FIXED
+  hipLaunchKernelGGL((k_col_pass<-1, -1>), ZPM_COL_ARGS);
+#undef ZPM_COL_ARGS
   return hipGetLastError();
 }
 
@@ -163,13 +181,20 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
   const int64_t nz_a = direct ? pl.da : L, nz_b = direct ? pl.db : L, nl = direct ? pl.nout : L;
   if (pl.conv_reg) {
     const size_t lds = sizeof(uint32_t) * (size_t)(2 * pl.K) * (((size_t)1 << pl.logL1) + 1);
+    // the planner's inner factor for long products is the largest whose 2K rows fit:
+    // 2K (L1 + 1) <= LDS_WORDS, i.e. L1 = 2^(12 - log2 K)
+    const bool full_l1 = pl.logL1 == 12 - ilog2(pl.K);
+#define ZPM_CONV_LAUNCH(KERN, LK_, M_, C_)                                                     \
+  hipLaunchKernelGGL((KERN<LK_, M_, C_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, L, \
+                     pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, spec)
 #define ZPM_CONV_M(LK_, M_)                                                                    \
-  if constexpr (LK_ >= ZPM_SPLIT_LOGK)                                                         \
-    hipLaunchKernelGGL((k_convolve_rows_split<LK_, M_>), dim3((unsigned)blocks), dim3(BLOCK), lds, \
-                       st, ds.X, L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, spec);           \
-  else                                                                                         \
-    hipLaunchKernelGGL((k_convolve_rows_reg<LK_, M_>), dim3((unsigned)blocks), dim3(BLOCK), lds,  \
-                       st, ds.X, L, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, spec)
+  if constexpr (LK_ >= ZPM_SPLIT_LOGK) {                                                       \
+    /* a fixed L1 raises this kernel to 192 VGPRs (two waves per SIMD instead of three) */     \
+    ZPM_CONV_LAUNCH(k_convolve_rows_split, LK_, M_, -1);                                        \
+  } else {                                                                                     \
+    if (full_l1) ZPM_CONV_LAUNCH(k_convolve_rows_reg, LK_, M_, 12 - LK_);                       \
+    else ZPM_CONV_LAUNCH(k_convolve_rows_reg, LK_, M_, -1);                                     \
+  }
 #define ZPM_CONV(LK_)                                        \
   switch (mode) {                                            \
     case CM_PRODUCT: ZPM_CONV_M(LK_, CM_PRODUCT); break;     \
@@ -186,6 +211,7 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
     }
 #undef ZPM_CONV
 #undef ZPM_CONV_M
+#undef ZPM_CONV_LAUNCH
     return hipGetLastError();
   }
   const size_t lds = sizeof(uint32_t) * (size_t)4 * pl.K << pl.logL1;

@@ -52,17 +52,27 @@ __device__ __forceinline__ uint2 heap_root(const uint2 *__restrict__ tab, int64_
 struct LdsShape {
   int logntr, logn, ts, es, off2, logops;
 };
+// The same shape fixed at compile time, so that every LDS offset of a group folds into
+// the instructions' immediates.
+template <int LOGNTR, int LOGN, int TS, int ES, int OFF2 = 0, int LOGOPS = 0>
+struct CShape {
+  static constexpr int logntr = LOGNTR, logn = LOGN, ts = TS, es = ES, off2 = OFF2,
+                       logops = LOGOPS;
+};
 
-__device__ __forceinline__ int lds_base(const LdsShape &sh, int t) {
+template <class SH>
+__device__ __forceinline__ int lds_base(const SH &sh, int t) {
   return (t & ((1 << sh.logntr) - 1)) * sh.ts + (t >> sh.logntr) * sh.off2;
 }
 
 // DIF (Gentleman-Sande) stages with half-sizes h0, h0/2, ..., h0/2^(R-1); output of the
 // whole transform is in bit-reversed order.
-template <int R>
-__device__ void dif_group(uint32_t *s, const LdsShape &sh, int logh0, const uint2 *__restrict__ tw,
+// LOGH0 >= 0 fixes logh0 at compile time (with a compile-time shape).
+template <int R, class SH = LdsShape, int LOGH0 = -1>
+__device__ void dif_group(uint32_t *s, const SH &sh, int logh0_rt, const uint2 *__restrict__ tw,
                           uint32_t p) {
   constexpr int NR = 1 << R;
+  const int logh0 = LOGH0 >= 0 ? LOGH0 : logh0_rt;
   const int loghl = logh0 - (R - 1);
   const int hl = 1 << loghl;
   const int lgpt = sh.logn - R;                       // groups per transform (log)
@@ -106,10 +116,11 @@ __device__ void dif_group(uint32_t *s, const LdsShape &sh, int logh0, const uint
 
 // DIT (Cooley-Tukey) stages with half-sizes h0, 2 h0, ..., h0 2^(R-1); input in
 // bit-reversed order, output natural.
-template <int R>
-__device__ void dit_group(uint32_t *s, const LdsShape &sh, int logh0, const uint2 *__restrict__ tw,
+template <int R, class SH = LdsShape, int LOGH0 = -1>
+__device__ void dit_group(uint32_t *s, const SH &sh, int logh0_rt, const uint2 *__restrict__ tw,
                           uint32_t p) {
   constexpr int NR = 1 << R;
+  const int logh0 = LOGH0 >= 0 ? LOGH0 : logh0_rt;
   const int h0 = 1 << logh0;
   const int loghr = logh0 + R - 1;
   const int lgpt = sh.logn - R;
@@ -181,6 +192,30 @@ __device__ void lds_dit(uint32_t *s, const LdsShape &sh, const uint2 *__restrict
     else dit_group<1>(s, sh, done, tw, p);
     done += r;
     __syncthreads();
+  }
+}
+
+// Full transforms of a compile-time shape: the groups of lds_dif / lds_dit, each with its
+// stages fixed at compile time.  ST: stages left (DIF) / done (DIT).
+__device__ constexpr int group_stages_c(int left) {
+  return (left + ((left + 3) >> 2) - 1) / ((left + 3) >> 2);
+}
+template <class SH, int ST = SH::logn>
+__device__ __forceinline__ void lds_dif_c(uint32_t *s, const uint2 *__restrict__ tw, uint32_t p) {
+  if constexpr (ST > 0) {
+    constexpr int R = group_stages_c(ST);
+    dif_group<R, SH, ST - 1>(s, SH{}, 0, tw, p);
+    __syncthreads();
+    lds_dif_c<SH, ST - R>(s, tw, p);
+  }
+}
+template <class SH, int DONE = 0>
+__device__ __forceinline__ void lds_dit_c(uint32_t *s, const uint2 *__restrict__ tw, uint32_t p) {
+  if constexpr (DONE < SH::logn) {
+    constexpr int R = group_stages_c(SH::logn - DONE);
+    dit_group<R, SH, DONE>(s, SH{}, 0, tw, p);
+    __syncthreads();
+    lds_dit_c<SH, DONE + R>(s, tw, p);
   }
 }
 
@@ -325,10 +360,17 @@ __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__
 // cols: columns transformed per prime, those from col0 on among each prime's 2K (K of
 // them when only one operand's limbs need a forward transform: a square, or one
 // operand of a product with a resident transform).
+// CLOGN / CLOGT >= 0: the pass length and tile width fixed at compile time (they must
+// equal logn_rt / logT_rt).
+template <int CLOGN = -1, int CLOGT = -1>
 __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
-                              int32_t twoK, int32_t logn, int64_t S, int32_t logT, int64_t nz_a,
+                              int32_t twoK, int32_t logn_rt, int64_t S, int32_t logT_rt, int64_t nz_a,
                               int64_t nz_b, int32_t K, int64_t nlimit, int32_t inverse,
                               const PrimeDev *__restrict__ primes, int32_t cols, int32_t col0) {
+  constexpr bool fixed = CLOGN >= 0 && CLOGT >= 0;
+  const int logn = fixed ? CLOGN : logn_rt, logT = fixed ? CLOGT : logT_rt;
+  using CSH = CShape<(CLOGT >= 0 ? CLOGT : 0), (CLOGN >= 0 ? CLOGN : 1), 1,
+                     (1 << (CLOGT >= 0 ? CLOGT : 0))>;
   const int n = 1 << logn, T = 1 << logT;
   const int64_t inner_tiles = S >> logT;
   const int64_t outers = L / ((int64_t)n * S);
@@ -363,7 +405,8 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
       return (first + off < nz) ? base[off] : 0u;
     }, [&](int idx, uint32_t v) { s[idx] = v; });
     __syncthreads();
-    lds_dif(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hf, p);
+    if constexpr (fixed) lds_dif_c<CSH>(s, pr.hf, p);
+    else lds_dif(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hf, p);
     for (int e = e0; e < n; e += de) {
       const uint32_t v = mont_mul(s[(bitrev(e, logn) << logT) + t], cur, p, pr.pinv);
       cur = mont_mul(cur, step, p, pr.pinv);
@@ -388,7 +431,8 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
       }
     }
     __syncthreads();
-    lds_dit(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hi, p);
+    if constexpr (fixed) lds_dit_c<CSH>(s, pr.hi, p);
+    else lds_dit(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hi, p);
     staged<8, uint32_t>(n << logT, [&](int idx) { return s[idx]; }, [&](int idx, uint32_t v) {
       const int off = (idx & (T - 1)) + S32 * (idx >> logT);
       if (off < lim_store) base[off] = v;
@@ -515,13 +559,15 @@ __device__ __forceinline__ void reg_dit(uint32_t (&x)[2 << LOGK], const uint2 *_
 
 // MODE is a ConvMode, fixed at compile time so that each variant keeps only its own
 // register footprint (the product's is the largest that matters for occupancy).
-template <int LOGK, int MODE>
+// CLOGL1 >= 0: the inner factor L1 = 2^CLOGL1 fixed at compile time (== logL1_rt).
+template <int LOGK, int MODE, int CLOGL1 = -1>
 __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
-                                  int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
+                                  int32_t logL1_rt, int64_t nz_a, int64_t nz_b, int64_t nlimit,
                                   const PrimeDev *__restrict__ primes,
                                   const PlanDev *__restrict__ pd,
                                   const uint32_t *__restrict__ spec) {
   constexpr int K = 1 << LOGK, K2 = 2 * K;
+  const int logL1 = CLOGL1 >= 0 ? CLOGL1 : logL1_rt;
   const int L1 = 1 << logL1, RS = L1 + 1;      // odd row stride: rows fall on distinct banks
   const int64_t nrb = L >> logL1;
   const int k = (int)(bid / nrb);
@@ -542,7 +588,11 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
     return (y0 + e < nz) ? base[j * L32 + e] : 0u;
   }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
   __syncthreads();
-  lds_dif(s, LdsShape{one ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
+  if constexpr (CLOGL1 >= 0)
+    lds_dif_c<CShape<(one ? LOGK : LOGK + 1), (CLOGL1 >= 0 ? CLOGL1 : 1), (1 << (CLOGL1 >= 0 ? CLOGL1 : 1)) + 1, 1>>(
+        s, pr.hf, p);
+  else
+    lds_dif(s, LdsShape{one ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
   if constexpr (MODE == CM_SPECTRUM) {
     // b's 2K spectra per position replace its limbs (this block's positions, all read)
     for (int e = threadIdx.x; e < L1; e += BLOCK) {
@@ -599,7 +649,11 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
     for (int j = 0; j < K2; ++j) s[j * RS + e] = b[j];
   }
   __syncthreads();
-  lds_dit(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hi, p);
+  if constexpr (CLOGL1 >= 0)
+    lds_dit_c<CShape<LOGK + 1, (CLOGL1 >= 0 ? CLOGL1 : 1), (1 << (CLOGL1 >= 0 ? CLOGL1 : 1)) + 1, 1>>(
+        s, pr.hi, p);
+  else
+    lds_dit(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hi, p);
   staged<8, uint32_t>(K2 << logL1, [&](int idx) {
     return s[(idx >> logL1) * RS + (idx & (L1 - 1))];
   }, [&](int idx, uint32_t v) {
@@ -659,13 +713,15 @@ __device__ __forceinline__ void reg_half_dit(uint32_t (&x)[1 << LOGN], ctw_ptr t
   }
 }
 
-template <int LOGK, int MODE>
+// CLOGL1 >= 0: the inner factor L1 = 2^CLOGL1 fixed at compile time (== logL1_rt).
+template <int LOGK, int MODE, int CLOGL1 = -1>
 __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
-                                    int32_t logL1, int64_t nz_a, int64_t nz_b, int64_t nlimit,
+                                    int32_t logL1_rt, int64_t nz_a, int64_t nz_b, int64_t nlimit,
                                     const PrimeDev *__restrict__ primes,
                                     const PlanDev *__restrict__ pd,
                                     const uint32_t *__restrict__ spec) {
   constexpr int K = 1 << LOGK, K2 = 2 * K;
+  const int logL1 = CLOGL1 >= 0 ? CLOGL1 : logL1_rt;
   const int L1 = 1 << logL1, RS = L1 + 1;
   const int64_t nrb = L >> logL1;
   const int k = (int)(bid / nrb);
@@ -684,7 +740,11 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
     return (y0 + e < nz) ? base[j * L32 + e] : 0u;
   }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
   __syncthreads();
-  lds_dif(s, LdsShape{one ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
+  if constexpr (CLOGL1 >= 0)
+    lds_dif_c<CShape<(one ? LOGK : LOGK + 1), (CLOGL1 >= 0 ? CLOGL1 : 1), (1 << (CLOGL1 >= 0 ? CLOGL1 : 1)) + 1, 1>>(
+        s, pr.hf, p);
+  else
+    lds_dif(s, LdsShape{one ? LOGK : LOGK + 1, logL1, RS, 1, 0, 0}, pr.hf, p);
   ctw_ptr hf = (ctw_ptr)(const void *)pr.hf;
   ctw_ptr hi = (ctw_ptr)(const void *)pr.hi;
   // the twisted half: x_j theta^j, then its K-point DIF (rows K..2K-1 of the spectrum)
@@ -779,7 +839,11 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
     }
   }
   __syncthreads();
-  lds_dit(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hi, p);
+  if constexpr (CLOGL1 >= 0)
+    lds_dit_c<CShape<LOGK + 1, (CLOGL1 >= 0 ? CLOGL1 : 1), (1 << (CLOGL1 >= 0 ? CLOGL1 : 1)) + 1, 1>>(
+        s, pr.hi, p);
+  else
+    lds_dit(s, LdsShape{LOGK + 1, logL1, RS, 1, 0, 0}, pr.hi, p);
   staged<8, uint32_t>(K2 << logL1, [&](int idx) {
     return s[(idx >> logL1) * RS + (idx & (L1 - 1))];
   }, [&](int idx, uint32_t v) {

@@ -1,0 +1,62 @@
+"""Products that reach the kernels with compile-time transform shapes.
+
+Long products use the row kernel with the inner y-factor L1 = 2^(12 - log2 K) fixed at
+compile time, and column passes of 2^5 ... 2^10 points with fixed tile widths.  Every K
+of the register row kernels (2, 4, 8, 16) is run with a column pass of each length, as
+a product and as a square, and compared with the oracle at sampled output indices (the
+first, last and middle coefficients, the operand boundary and random ones).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1612_05778_amd import api, synth
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+CASES = [(K, logn) for K in (2, 4, 8, 16) for logn in (5, 6, 7, 8, 9, 10)
+         if (12 - (K.bit_length() - 1)) + logn <= 21]
+
+
+def sampled(prod, got, seed, n=40):
+    nout = prod.da + prod.db - 1
+    rng = np.random.default_rng(seed)
+    rows = sorted(set([0, 1, prod.da - 1, prod.da, nout // 2, nout - 2, nout - 1] +
+                      rng.choice(nout, size=min(n, nout), replace=False).tolist()))
+    ref = oracle.polymul_rows(prod.a, prod.da, prod.Na, prod.b, prod.db, prod.Nb, rows,
+                              wc=got.shape[1])
+    bad = [r for r, g, w in zip(rows, got[rows], ref) if not np.array_equal(g, w)]
+    assert not bad, f"rows {bad[:8]} differ from the oracle"
+
+
+@pytest.mark.parametrize("K,logn", CASES)
+def test_fixed_shapes(ctx, K, logn):
+    logL1 = 12 - (K.bit_length() - 1)
+    logL = logL1 + logn
+    d = (1 << (logL - 2)) + 1                  # da + db - 1 = 2^(logL-1) + 1: L = 2^logL
+    N = 17 * K                                 # M = 17
+    r = np.random.default_rng(K * 100 + logn)
+    a, _ = synth.signed_words(r, d, N - 1)
+    b, _ = synth.signed_words(r, d, N - 1)
+    prod = synth.Product(a, N, b, N)
+    pl = api.plan(d, N, d, N, K=K)
+    assert (pl["log2_L"], pl["log2_L1"], pl["col_log2n"]) == (logL, logL1, [logn])
+    print(f"[fixed] K={K} L1=2^{logL1} pass=2^{logn} tile={pl['col_tile']} d={d}", flush=True)
+    A, B = dev(a), dev(b)
+    got = host(ctx.mul(A, N, B, N, K=K))
+    sampled(prod, got, logn)
+    sq = synth.Product(a, N, a, N)
+    got_sq = host(ctx.mul(A, N, A, N, K=K))
+    sampled(sq, got_sq, logn + 1)
+    del A, B
+    torch.cuda.empty_cache()
