@@ -61,12 +61,14 @@ __global__ __launch_bounds__(BLOCK) void k_col_pass(
                               primes, cols, col0);
 }
 
+template <int CLOGK, int CLOGL1>
 __global__ __launch_bounds__(BLOCK) void k_convolve_rows(
     uint32_t *__restrict__ X, int64_t L, int32_t K, int32_t logK, int32_t logL1, int64_t nz_a,
     int64_t nz_b, int64_t nlimit, const PrimeDev *__restrict__ primes,
     const PlanDev *__restrict__ pd, int32_t mode, const uint32_t *__restrict__ spec) {
   extern __shared__ uint32_t s[];
-  body_convolve(s, blockIdx.x, X, L, K, logK, logL1, nz_a, nz_b, nlimit, primes, pd, mode, spec);
+  body_convolve<CLOGK, CLOGL1>(s, blockIdx.x, X, L, K, logK, logL1, nz_a, nz_b, nlimit, primes, pd,
+                               mode, spec);
 }
 
 // CLOGL1 >= 0: inner factor fixed at compile time (the largest that fits, 2^(12 - LOGK));
@@ -215,8 +217,16 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
     return hipGetLastError();
   }
   const size_t lds = sizeof(uint32_t) * (size_t)4 * pl.K << pl.logL1;
-  hipLaunchKernelGGL(k_convolve_rows, dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, L, pl.K,
-                     ilog2(pl.K), pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, mode, spec);
+  // K = 64, 128, 256 with their full inner factor (4 K L1 = LDS_WORDS) fixed at compile time
+  const int lk = ilog2(pl.K);
+#define ZPM_CONV_LDS(LK_, LL1_)                                                                \
+  hipLaunchKernelGGL((k_convolve_rows<LK_, LL1_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, \
+                     ds.X, L, pl.K, lk, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, mode, spec)
+  if (lk == 6 && pl.logL1 == 6) ZPM_CONV_LDS(6, 6);
+  else if (lk == 7 && pl.logL1 == 5) ZPM_CONV_LDS(7, 5);
+  else if (lk == 8 && pl.logL1 == 4) ZPM_CONV_LDS(8, 4);
+  else ZPM_CONV_LDS(-1, -1);
+#undef ZPM_CONV_LDS
   return hipGetLastError();
 }
 

@@ -451,11 +451,18 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
 // after the 1/(2K) in the scale constant are c_{i,j} and c_{i,j+K} (Section 2,
 // C+ and C- through Relation (recoveringC)).
 // ------------------------------------------------------------------------------------
+// CLOGK / CLOGL1 >= 0: K and L1 fixed at compile time (== the runtime values).
+template <int CLOGK = -1, int CLOGL1 = -1>
 __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X, int64_t L,
-                              int32_t K, int32_t logK, int32_t logL1, int64_t nz_a, int64_t nz_b,
-                              int64_t nlimit, const PrimeDev *__restrict__ primes,
+                              int32_t K_rt, int32_t logK_rt, int32_t logL1_rt, int64_t nz_a,
+                              int64_t nz_b, int64_t nlimit, const PrimeDev *__restrict__ primes,
                               const PlanDev *__restrict__ pd, int32_t mode,
                               const uint32_t *__restrict__ spec) {
+  constexpr bool fixed = CLOGK >= 0 && CLOGL1 >= 0;
+  constexpr int FK = fixed ? CLOGK : 1, FL1 = fixed ? CLOGL1 : 1;   // valid when fixed
+  constexpr int FTWOKL1 = (2 << FK) << FL1;
+  const int logK = fixed ? CLOGK : logK_rt, logL1 = fixed ? CLOGL1 : logL1_rt;
+  const int K = fixed ? (1 << CLOGK) : K_rt;
   const int L1 = 1 << logL1;
   const int64_t nrb = L >> logL1;
   const int k = (int)(bid / nrb);
@@ -489,9 +496,19 @@ __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   __syncthreads();
   // innermost y factor on the K limb rows of both operands (of one operand otherwise)
   const int ops = mode == CM_PRODUCT ? 1 : 0;
-  lds_dif(s, LdsShape{logK, logL1, L1, 1, twoK * L1, ops}, pr.hf, p);
-  // x: 2K-point transforms down the L1 columns
-  lds_dif(s, LdsShape{logL1, logK + 1, 1, L1, twoK * L1, ops}, pr.hf, p);
+  if constexpr (fixed) {
+    if (ops) {
+      lds_dif_c<CShape<FK, FL1, (1 << FL1), 1, FTWOKL1, 1>>(s, pr.hf, p);
+      lds_dif_c<CShape<FL1, FK + 1, 1, (1 << FL1), FTWOKL1, 1>>(s, pr.hf, p);
+    } else {
+      lds_dif_c<CShape<FK, FL1, (1 << FL1), 1, FTWOKL1, 0>>(s, pr.hf, p);
+      lds_dif_c<CShape<FL1, FK + 1, 1, (1 << FL1), FTWOKL1, 0>>(s, pr.hf, p);
+    }
+  } else {
+    lds_dif(s, LdsShape{logK, logL1, L1, 1, twoK * L1, ops}, pr.hf, p);
+    // x: 2K-point transforms down the L1 columns
+    lds_dif(s, LdsShape{logL1, logK + 1, 1, L1, twoK * L1, ops}, pr.hf, p);
+  }
   if (mode == CM_SPECTRUM) {
     // this block's positions only, all read above: the spectra replace the limbs
     staged<8, uint32_t>(twoK << logL1, [&](int idx) { return A[idx]; }, [&](int idx, uint32_t v) {
@@ -504,8 +521,13 @@ __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   for (int idx = threadIdx.x; idx < (twoK << logL1); idx += BLOCK)
     A[idx] = mul_shoup(mont_mul(A[idx], F[idx], p, pr.pinv), sc, p);
   __syncthreads();
-  lds_dit(s, LdsShape{logL1, logK + 1, 1, L1, 0, 0}, pr.hi, p);
-  lds_dit(s, LdsShape{logK + 1, logL1, L1, 1, 0, 0}, pr.hi, p);
+  if constexpr (fixed) {
+    lds_dit_c<CShape<FL1, FK + 1, 1, (1 << FL1)>>(s, pr.hi, p);
+    lds_dit_c<CShape<FK + 1, FL1, (1 << FL1), 1>>(s, pr.hi, p);
+  } else {
+    lds_dit(s, LdsShape{logL1, logK + 1, 1, L1, 0, 0}, pr.hi, p);
+    lds_dit(s, LdsShape{logK + 1, logL1, L1, 1, 0, 0}, pr.hi, p);
+  }
   staged<8, uint32_t>(twoK << logL1, [&](int idx) { return A[idx]; }, [&](int idx, uint32_t v) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
     if (y0 + e < nlimit) base[(int64_t)j * L + e] = v;

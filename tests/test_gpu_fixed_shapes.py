@@ -60,3 +60,31 @@ def test_fixed_shapes(ctx, K, logn):
     sampled(sq, got_sq, logn + 1)
     del A, B
     torch.cuda.empty_cache()
+
+
+# the LDS row kernel (K >= 64) with its full inner factor: 4 K L1 = 16384 words
+LDS_CASES = [(K, logn) for K in (64, 128, 256) for logn in (5, 7, 9)]
+
+
+@pytest.mark.parametrize("K,logn", LDS_CASES)
+def test_fixed_shapes_lds_kernel(ctx, K, logn):
+    logL1 = 14 - 2 - (K.bit_length() - 1)
+    logL = logL1 + logn
+    d = (1 << (logL - 2)) + 1
+    N = 3 * K                                  # M = 3
+    r = np.random.default_rng(K + logn)
+    a, _ = synth.signed_words(r, d, N - 1)
+    b, _ = synth.signed_words(r, d, N - 1)
+    prod = synth.Product(a, N, b, N)
+    pl = api.plan(d, N, d, N, K=K)
+    assert (pl["log2_L"], pl["log2_L1"], pl["col_log2n"]) == (logL, logL1, [logn])
+    print(f"[fixed lds] K={K} L1=2^{logL1} pass=2^{logn} d={d}", flush=True)
+    A, B = dev(a), dev(b)
+    sampled(prod, host(ctx.mul(A, N, B, N, K=K)), logn)
+    sampled(synth.Product(a, N, a, N), host(ctx.mul(A, N, A, N, K=K)), logn + 1)
+    if logn == 7:
+        op = api.Operand(ctx, B, N, d, N, K=K)   # b's spectra resident, then a * b
+        sampled(prod, host(op.mul(A, N)), logn + 2)
+        op.close()
+    del A, B
+    torch.cuda.empty_cache()
