@@ -881,6 +881,16 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
 // then c_i = sum_j c_{i,j} 2^(M j) (evaluation at beta = 2^M) by per-word sums of
 // shifted windows and a wave-wide carry scan.
 // ------------------------------------------------------------------------------------
+// lo += a b over 64 bits, hi += the carry out: the multiply-add's own carry feeds one
+// add-with-carry (the compiler would compare and select instead).  Register-only ALU.
+__device__ __forceinline__ void mac_carry(uint64_t &lo, uint32_t &hi, uint32_t a, uint32_t b) {
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t"
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc"
+      : "+v"(lo), "+v"(hi)
+      : "v"(a), "v"(b)
+      : "vcc");
+}
+
 __device__ __forceinline__ int fapply(int code, int y) { return ((code >> (2 * (y + 1))) & 3) - 1; }
 __device__ __forceinline__ int fcompose(int g, int f) {   // g after f
   int r = 0;
@@ -942,9 +952,9 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
     }
     // c_{i,j} = sum_k c_k (P/p_k) - t P, where sum_k c_k P/p_k = c + t P with |c| < P/4,
     // so t = round(sum_k c_k / p_k).  The value is produced one 32-bit word u at a time
-    // (column sums of the products, primes taken in pairs so that each pair's sum stays
-    // below 2^64, a signed carry between words) and its shifted digits are added into
-    // the output words at once.
+    // (column sums of the products over 64 bits, with the carries out of bit 63 counted
+    // in a third word, and a signed carry between words) and its shifted digits are
+    // added into the output words at once.
     const uint32_t tq = (uint32_t)__double2int_rn(f);
     const int64_t bit = (int64_t)M * j;
     const int64_t q0 = bit >> 5;
@@ -959,9 +969,8 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
 #pragma unroll
       for (int k = 0; k < NPE; k += 2) {
         const uint2 qq = *reinterpret_cast<const uint2 *>(cq + u * NPE + k);
-        uint64_t pr2 = (uint64_t)cc[k + 1] * qq.y;
-        pr2 += (uint64_t)cc[k] * qq.x;
-        hi += __builtin_add_overflow(lo, pr2, &lo) ? 1u : 0u;
+        mac_carry(lo, hi, cc[k], qq.x);
+        mac_carry(lo, hi, cc[k + 1], qq.y);
       }
       const uint64_t tp = (uint64_t)tq * cp[u];
       const uint64_t D = lo - tp;
