@@ -51,6 +51,7 @@ __global__ __launch_bounds__(BLOCK) void kg_recover(const JobDev *__restrict__ j
 
 // Blocks are remapped with xcd_tile (as in the single-product column pass) so that
 // neighbouring tiles, which share 128-byte lines, run on one XCD.
+template <int CLOGN, int CLOGT>
 __global__ __launch_bounds__(BLOCK) void kg_col(const JobDev *__restrict__ jobs,
                                                 const GroupSeg *__restrict__ segs, int32_t nseg,
                                                 int32_t inverse, const PrimeDev *__restrict__ primes,
@@ -63,13 +64,13 @@ __global__ __launch_bounds__(BLOCK) void kg_col(const JobDev *__restrict__ jobs,
   const int c = g.pass;
   const bool outer = c == 0;
   const int64_t L = jb.L;
-  body_col_pass(s, b - g.start, jb.X, L, 2 * jb.K, jb.col_logn[c], jb.col_S[c],
+  body_col_pass<CLOGN, CLOGT>(s, b - g.start, jb.X, L, 2 * jb.K, jb.col_logn[c], jb.col_S[c],
                 jb.col_logT[c], (outer && !inverse) ? jb.da : L, (outer && !inverse) ? jb.db : L,
                 jb.K, (outer && inverse) ? jb.nout : L, inverse, primes,
                 (jb.square && !inverse) ? jb.K : 2 * jb.K, 0);
 }
 
-template <int LOGK, int MODE>
+template <int LOGK, int MODE, int CLOGL1>
 __global__ __launch_bounds__(BLOCK) void kg_convolve_reg(const JobDev *__restrict__ jobs,
                                                          const GroupSeg *__restrict__ segs,
                                                          int32_t nseg,
@@ -79,11 +80,12 @@ __global__ __launch_bounds__(BLOCK) void kg_convolve_reg(const JobDev *__restric
   const JobDev &jb = jobs[g.job];
   const int64_t L = jb.L;
   const bool direct = jb.ncol == 0;
-  body_convolve_reg<LOGK, MODE>(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.logL1,
+  body_convolve_reg<LOGK, MODE, CLOGL1>(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.logL1,
                                 direct ? jb.da : L, direct ? jb.db : L, direct ? jb.nout : L,
                                 primes, jb.plan, nullptr);
 }
 
+template <int CLOGK, int CLOGL1>
 __global__ __launch_bounds__(BLOCK) void kg_convolve(const JobDev *__restrict__ jobs,
                                                      const GroupSeg *__restrict__ segs, int32_t nseg,
                                                      const PrimeDev *__restrict__ primes) {
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(BLOCK) void kg_convolve(const JobDev *__restrict__ 
   const bool direct = jb.ncol == 0;
   int logK = 0;
   while ((1 << logK) < jb.K) ++logK;
-  body_convolve(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.K, logK, jb.logL1,
+  body_convolve<CLOGK, CLOGL1>(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.K, logK, jb.logL1,
                 direct ? jb.da : L, direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan,
                 jb.square ? CM_SQUARE : CM_PRODUCT, nullptr);
 }
@@ -127,22 +129,45 @@ hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *seg
       }
       break;
     case SK_COL_FWD:
-    case SK_COL_INV:
-      hipLaunchKernelGGL(kg_col, dim3((unsigned)(8 * ((gr.blocks + 7) / 8))), blk, gr.lds, st, jobs,
-                         sg, ns, gr.kind == SK_COL_INV ? 1 : 0, primes, gr.blocks);
+    case SK_COL_INV: {
+      // variant: fixed_col_index of the pass shape (0: any shape)
+      const dim3 g8((unsigned)(8 * ((gr.blocks + 7) / 8)));
+      const int32_t inv = gr.kind == SK_COL_INV ? 1 : 0;
+      switch (gr.variant) {
+#define ZPM_G(I, LN, LT)                                                                      \
+  case I: hipLaunchKernelGGL((kg_col<LN, LT>), g8, blk, gr.lds, st, jobs, sg, ns, inv, primes, gr.blocks); break;
+        ZPM_G(0, -1, -1) ZPM_G(1, 5, 6) ZPM_G(2, 6, 5) ZPM_G(3, 7, 4) ZPM_G(4, 8, 3) ZPM_G(5, 9, 3)
+        ZPM_G(6, 10, 3)
+#undef ZPM_G
+        default: return hipErrorInvalidValue;
+      }
       break;
+    }
     case SK_CONVOLVE: {
-      // variant: log2 K of the register kernel plus 16 for squares, 0 for the LDS kernel
-      const bool sq = gr.variant >= 16;
+      // variant: register kernel: log2 K, plus 16 for squares, plus 32 for the full inner
+      // factor; LDS kernel: 0 (any K), or 64 + log2 K with its full inner factor
+      if (gr.variant >= 64) {
+        switch (gr.variant - 64) {
+          case 6: hipLaunchKernelGGL((kg_convolve<6, 6>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+          case 7: hipLaunchKernelGGL((kg_convolve<7, 5>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+          case 8: hipLaunchKernelGGL((kg_convolve<8, 4>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+          default: return hipErrorInvalidValue;
+        }
+        break;
+      }
+      const bool sq = (gr.variant & 16) != 0, full = (gr.variant & 32) != 0;
       switch (gr.variant & 15) {
+#define ZPM_GM(LK_, M_)                                                                                      \
+  if (full) hipLaunchKernelGGL((kg_convolve_reg<LK_, M_, 12 - LK_>), grid, blk, gr.lds, st, jobs, sg, ns, primes); \
+  else hipLaunchKernelGGL((kg_convolve_reg<LK_, M_, -1>), grid, blk, gr.lds, st, jobs, sg, ns, primes);
 #define ZPM_G(LK_)                                                                            \
   case LK_:                                                                                   \
-    if (sq) hipLaunchKernelGGL((kg_convolve_reg<LK_, CM_SQUARE>), grid, blk, gr.lds, st, jobs, sg, ns, primes); \
-    else hipLaunchKernelGGL((kg_convolve_reg<LK_, CM_PRODUCT>), grid, blk, gr.lds, st, jobs, sg, ns, primes); \
+    if (sq) { ZPM_GM(LK_, CM_SQUARE) } else { ZPM_GM(LK_, CM_PRODUCT) }                        \
     break;
         ZPM_G(1) ZPM_G(2) ZPM_G(3) ZPM_G(4)
 #undef ZPM_G
-        case 0: hipLaunchKernelGGL(kg_convolve, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+#undef ZPM_GM
+        case 0: hipLaunchKernelGGL((kg_convolve<-1, -1>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
         default: return hipErrorInvalidValue;
       }
       break;

@@ -143,12 +143,21 @@ static int64_t stage_tiles(const Plan &pl, int kind, int pass) {
   }
 }
 
-static int stage_variant(const Plan &pl, int kind) {
+// Compiled kernel a stage's tiles run in (tiles of one level with the same kind and
+// variant share a launch).
+static int stage_variant(const Plan &pl, int kind, int pass) {
   if (kind == SK_CONVERT || kind == SK_RECOVER) return pl.np;
+  int lk = 0;
+  while ((1 << lk) < pl.K) ++lk;
   if (kind == SK_CONVOLVE && pl.conv_reg) {
-    int lk = 0;
-    while ((1 << lk) < pl.K) ++lk;
-    return lk + (pl.square ? 16 : 0);   // squares have a register kernel of their own
+    // squares have a register kernel of their own; so has the full inner factor
+    return lk + (pl.square ? 16 : 0) + (fixed_reg_l1(lk, pl.logL1) ? 32 : 0);
+  }
+  if (kind == SK_CONVOLVE) return fixed_lds_kl1(lk, pl.logL1) ? 64 + lk : 0;
+  if (kind == SK_COL_FWD || kind == SK_COL_INV) {
+    int lt = 0;
+    while ((1 << lt) < pl.col_tile[pass]) ++lt;
+    return fixed_col_index(pl.col[pass].logn, lt);
   }
   return 0;
 }
@@ -222,7 +231,7 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
       if (lev >= 3 + 2 * pl.ncol) continue;
       int kind, pass;
       stage_of(pl, lev, &kind, &pass);
-      const auto key = std::make_pair(kind, stage_variant(pl, kind));
+      const auto key = std::make_pair(kind, stage_variant(pl, kind, pass));
       GroupSeg g;
       std::memset(&g, 0, sizeof(g));
       g.ntiles = stage_tiles(pl, kind, pass);

@@ -160,16 +160,14 @@ hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, h
 #define ZPM_COL_ARGS                                                                         \
   dim3((unsigned)grid), dim3(BLOCK), lds, st, ds.X, L, 2 * pl.K, logn, S, logT, nz_a, nz_b,   \
       pl.K, nlimit, inverse ? 1 : 0, ds.primes, blocks, cols, col0
-#define ZPM_COL_FIXED(LN, LT)                                                                \
-  if (logn == LN && logT == LT) {                                                            \
-    hipLaunchKernelGGL((k_col_pass<LN, LT>), ZPM_COL_ARGS);                                  \
-    return hipGetLastError();                                                                \
-  }
-  // the planner's default tile for each pass length from 2^5 to 2^10
-  ZPM_COL_FIXED(5, 6) ZPM_COL_FIXED(6, 5) ZPM_COL_FIXED(7, 4) ZPM_COL_FIXED(8, 3)
-  ZPM_COL_FIXED(9, 3) ZPM_COL_FIXED(10, 3)
+  switch (fixed_col_index(logn, logT)) {
+#define ZPM_COL_FIXED(I, LN, LT)                                                             \
+  case I: hipLaunchKernelGGL((k_col_pass<LN, LT>), ZPM_COL_ARGS); break;
+    ZPM_COL_FIXED(1, 5, 6) ZPM_COL_FIXED(2, 6, 5) ZPM_COL_FIXED(3, 7, 4)
+    ZPM_COL_FIXED(4, 8, 3) ZPM_COL_FIXED(5, 9, 3) ZPM_COL_FIXED(6, 10, 3)
 #undef ZPM_COL_FIXED
-  hipLaunchKernelGGL((k_col_pass<-1, -1>), ZPM_COL_ARGS);
+    default: hipLaunchKernelGGL((k_col_pass<-1, -1>), ZPM_COL_ARGS); break;
+  }
 #undef ZPM_COL_ARGS
   return hipGetLastError();
 }
@@ -185,7 +183,7 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
     const size_t lds = sizeof(uint32_t) * (size_t)(2 * pl.K) * (((size_t)1 << pl.logL1) + 1);
     // the planner's inner factor for long products is the largest whose 2K rows fit:
     // 2K (L1 + 1) <= LDS_WORDS, i.e. L1 = 2^(12 - log2 K)
-    const bool full_l1 = pl.logL1 == 12 - ilog2(pl.K);
+    const bool full_l1 = fixed_reg_l1(ilog2(pl.K), pl.logL1);
 #define ZPM_CONV_LAUNCH(KERN, LK_, M_, C_)                                                     \
   hipLaunchKernelGGL((KERN<LK_, M_, C_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, L, \
                      pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, spec)
@@ -222,10 +220,10 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
 #define ZPM_CONV_LDS(LK_, LL1_)                                                                \
   hipLaunchKernelGGL((k_convolve_rows<LK_, LL1_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, \
                      ds.X, L, pl.K, lk, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, mode, spec)
-  if (lk == 6 && pl.logL1 == 6) ZPM_CONV_LDS(6, 6);
-  else if (lk == 7 && pl.logL1 == 5) ZPM_CONV_LDS(7, 5);
-  else if (lk == 8 && pl.logL1 == 4) ZPM_CONV_LDS(8, 4);
-  else ZPM_CONV_LDS(-1, -1);
+  if (!fixed_lds_kl1(lk, pl.logL1)) ZPM_CONV_LDS(-1, -1);
+  else if (lk == 6) ZPM_CONV_LDS(6, 6);
+  else if (lk == 7) ZPM_CONV_LDS(7, 5);
+  else ZPM_CONV_LDS(8, 4);
 #undef ZPM_CONV_LDS
   return hipGetLastError();
 }

@@ -7,6 +7,19 @@
 
 namespace zpm {
 
+// Column-pass shapes with a compile-time kernel: the planner's default tile for each pass
+// length from 2^5 to 2^10 (log2 length, log2 tile).  Index + 1, or 0 for any other shape.
+constexpr int FIXED_COL[][2] = {{5, 6}, {6, 5}, {7, 4}, {8, 3}, {9, 3}, {10, 3}};
+inline int fixed_col_index(int logn, int logT) {
+  for (int i = 0; i < (int)(sizeof(FIXED_COL) / sizeof(FIXED_COL[0])); ++i)
+    if (FIXED_COL[i][0] == logn && FIXED_COL[i][1] == logT) return i + 1;
+  return 0;
+}
+// Register row kernels have a compile-time kernel for their full inner factor
+// 2^(12 - log2 K); the LDS row kernel for K = 64, 128, 256 with 4 K L1 = 16384 words.
+inline bool fixed_reg_l1(int logK, int logL1) { return logL1 == 12 - logK; }
+inline bool fixed_lds_kl1(int logK, int logL1) { return logK >= 6 && logK <= 8 && logL1 == 12 - logK; }
+
 // Device pointers a launch needs.
 struct DevState {
   uint32_t *X;               // workspace, np * 2K * L words
