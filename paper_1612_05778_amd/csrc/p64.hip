@@ -263,10 +263,11 @@ __device__ __forceinline__ W64 heap_root64(const W64 *__restrict__ tab, int64_t 
 
 // Radix-2^R groups of DIF / DIT stages on transforms in LDS, in the layout of
 // LdsShape (transform t, element e at lds_base(t) + e es).
-template <int R>
-__device__ void dif64_group(uint64_t *s, const LdsShape &sh, int logh0, const W64 *__restrict__ tw,
+template <int R, class SH = LdsShape, int LOGH0 = -1>
+__device__ void dif64_group(uint64_t *s, const SH &sh, int logh0_rt, const W64 *__restrict__ tw,
                             uint64_t p) {
   constexpr int NR = 1 << R;
+  const int logh0 = LOGH0 >= 0 ? LOGH0 : logh0_rt;
   const int loghl = logh0 - (R - 1);
   const int hl = 1 << loghl;
   const int lgpt = sh.logn - R;
@@ -306,10 +307,11 @@ __device__ void dif64_group(uint64_t *s, const LdsShape &sh, int logh0, const W6
   }
 }
 
-template <int R>
-__device__ void dit64_group(uint64_t *s, const LdsShape &sh, int logh0, const W64 *__restrict__ tw,
+template <int R, class SH = LdsShape, int LOGH0 = -1>
+__device__ void dit64_group(uint64_t *s, const SH &sh, int logh0_rt, const W64 *__restrict__ tw,
                             uint64_t p) {
   constexpr int NR = 1 << R;
+  const int logh0 = LOGH0 >= 0 ? LOGH0 : logh0_rt;
   const int h0 = 1 << logh0;
   const int loghr = logh0 + R - 1;
   const int lgpt = sh.logn - R;
@@ -380,6 +382,27 @@ __device__ void lds64_dit(uint64_t *s, const LdsShape &sh, const W64 *__restrict
   }
 }
 
+// The same transforms for a compile-time shape (CShape), every group's stages fixed.
+__device__ constexpr int group_stages64_c(int left) { return (left + (left + 2) / 3 - 1) / ((left + 2) / 3); }
+template <class SH, int ST = SH::logn>
+__device__ __forceinline__ void lds64_dif_c(uint64_t *s, const W64 *__restrict__ tw, uint64_t p) {
+  if constexpr (ST > 0) {
+    constexpr int R = group_stages64_c(ST);
+    dif64_group<R, SH, ST - 1>(s, SH{}, 0, tw, p);
+    __syncthreads();
+    lds64_dif_c<SH, ST - R>(s, tw, p);
+  }
+}
+template <class SH, int DONE = 0>
+__device__ __forceinline__ void lds64_dit_c(uint64_t *s, const W64 *__restrict__ tw, uint64_t p) {
+  if constexpr (DONE < SH::logn) {
+    constexpr int R = group_stages64_c(SH::logn - DONE);
+    dit64_group<R, SH, DONE>(s, SH{}, 0, tw, p);
+    __syncthreads();
+    lds64_dit_c<SH, DONE + R>(s, tw, p);
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // BivariateRepresentation: a workgroup takes 64 coefficients and all their K limbs;
 // a wave reads one limb of 64 coefficients and writes 64 consecutive residues per prime.
@@ -446,13 +469,20 @@ __global__ __launch_bounds__(BLOCK) void k64_convert(const uint64_t *__restrict_
 // w_{nS}^(-u k), then DIT.  Rows i >= nz read as zero (first forward pass), rows
 // i >= nlimit are not stored (last inverse pass).
 // ------------------------------------------------------------------------------------
-template <int INV>
+// CLOGN, CLOGT, CLOGG >= 0: the workgroup's shape fixed at compile time (== the runtime
+// values); -1: any shape.
+template <int INV, int CLOGN, int CLOGT, int CLOGG>
 __global__ __launch_bounds__(BLOCK) void k64_ypass(uint64_t *__restrict__ X, int64_t L, int32_t twoK,
-                                                   int32_t cols, int32_t logn, int32_t logS,
-                                                   int32_t logT, int32_t logG, int64_t nz_a,
+                                                   int32_t cols, int32_t logn_rt, int32_t logS,
+                                                   int32_t logT_rt, int32_t logG_rt, int64_t nz_a,
                                                    int64_t nz_b, int32_t K, int64_t nlimit,
                                                    const Prime64Dev *__restrict__ primes) {
   __shared__ uint64_t s[LDS64];
+  constexpr bool fixed = CLOGN >= 0;
+  constexpr int FN = fixed ? CLOGN : 1, FT = fixed ? CLOGT : 0, FG = fixed ? CLOGG : 0;
+  using CSH = CShape<FT, FN, 1, (1 << FT), (1 << FN) << FT, FG>;
+  const int logn = fixed ? CLOGN : logn_rt, logT = fixed ? CLOGT : logT_rt,
+            logG = fixed ? CLOGG : logG_rt;
   const int n = 1 << logn, T = 1 << logT;
   const int64_t S = (int64_t)1 << logS;
   const int64_t inner_tiles = S >> logT;
@@ -484,7 +514,8 @@ __global__ __launch_bounds__(BLOCK) void k64_ypass(uint64_t *__restrict__ X, int
       return i < nz ? base[i] : 0ull;
     }, [&](int idx, uint64_t v) { s[idx] = v; });
     __syncthreads();
-    lds64_dif(s, sh, pr.hf, p);
+    if constexpr (fixed) lds64_dif_c<CSH>(s, pr.hf, p);
+    else lds64_dif(s, sh, pr.hf, p);
     for (int idx = threadIdx.x; idx < total; idx += BLOCK) {
       uint64_t v = s[slot_rev(idx)];
       if (logS) {
@@ -505,7 +536,8 @@ __global__ __launch_bounds__(BLOCK) void k64_ypass(uint64_t *__restrict__ X, int
       return v;
     }, [&](int idx, uint64_t v) { s[slot_rev(idx)] = v; });
     __syncthreads();
-    lds64_dit(s, sh, pr.hi, p);
+    if constexpr (fixed) lds64_dit_c<CSH>(s, pr.hi, p);
+    else lds64_dit(s, sh, pr.hi, p);
     for (int idx = threadIdx.x; idx < total; idx += BLOCK) {
       const int64_t i = gidx(idx);
       if (i < nlimit) base[i] = s[idx];
@@ -519,11 +551,15 @@ __global__ __launch_bounds__(BLOCK) void k64_ypass(uint64_t *__restrict__ X, int
 // scale 2^64 / (2 K L), 2K-point DIT; row j of the result is c_{., j} (row 2K - 1 is 0).
 // SQ: b is a (one forward transform).
 // ------------------------------------------------------------------------------------
-template <int SQ>
-__global__ __launch_bounds__(BLOCK) void k64_xconv(uint64_t *__restrict__ X, int64_t L, int32_t logK,
-                                                   int32_t logTX, const Prime64Dev *__restrict__ primes,
+// CLOGK, CLOGTX >= 0: K and the tile fixed at compile time; -1: any.
+template <int SQ, int CLOGK, int CLOGTX>
+__global__ __launch_bounds__(BLOCK) void k64_xconv(uint64_t *__restrict__ X, int64_t L, int32_t logK_rt,
+                                                   int32_t logTX_rt, const Prime64Dev *__restrict__ primes,
                                                    const Plan64Dev *__restrict__ pd) {
   __shared__ uint64_t s[LDS64];
+  constexpr bool fixed = CLOGK >= 0;
+  constexpr int FK = fixed ? CLOGK : 1, FX = fixed ? CLOGTX : 0;
+  const int logK = fixed ? CLOGK : logK_rt, logTX = fixed ? CLOGTX : logTX_rt;
   const int K = 1 << logK, twoK = 2 * K, TX = 1 << logTX;
   const int64_t tiles = L >> logTX;
   const int k = (int)(blockIdx.x / tiles);
@@ -543,7 +579,10 @@ __global__ __launch_bounds__(BLOCK) void k64_xconv(uint64_t *__restrict__ X, int
     s[((op * twoK + K + j) << logTX) + tt] = 0;
   });
   __syncthreads();
-  lds64_dif(s, LdsShape{logTX, logK + 1, 1, TX, twoK << logTX, SQ ? 0 : 1}, pr.hf, p);
+  if constexpr (fixed)
+    lds64_dif_c<CShape<FX, FK + 1, 1, (1 << FX), (2 << FK) << FX, SQ ? 0 : 1>>(s, pr.hf, p);
+  else
+    lds64_dif(s, LdsShape{logTX, logK + 1, 1, TX, twoK << logTX, SQ ? 0 : 1}, pr.hf, p);
   const W64 sc = pd->scale[k];
   for (int idx = threadIdx.x; idx < (twoK << logTX); idx += BLOCK) {
     const uint64_t u = s[idx];
@@ -551,7 +590,10 @@ __global__ __launch_bounds__(BLOCK) void k64_xconv(uint64_t *__restrict__ X, int
     s[idx] = mulsh64(mont64(u, v, p, pr.pinv), sc, p);
   }
   __syncthreads();
-  lds64_dit(s, LdsShape{logTX, logK + 1, 1, TX, 0, 0}, pr.hi, p);
+  if constexpr (fixed)
+    lds64_dit_c<CShape<FX, FK + 1, 1, (1 << FX)>>(s, pr.hi, p);
+  else
+    lds64_dit(s, LdsShape{logTX, logK + 1, 1, TX, 0, 0}, pr.hi, p);
   for (int idx = threadIdx.x; idx < (twoK << logTX); idx += BLOCK)
     base[(idx >> logTX) * L32 + (idx & (TX - 1))] = s[idx];
 }
@@ -852,12 +894,31 @@ static void launch_pass(const Plan64 &pl, const P64State &S, uint64_t *X, int q,
   const int64_t blocks = (int64_t)pl.np * cols * tiles;
   const int64_t nz_a = q == 0 ? pl.da : L, nz_b = q == 0 ? (pl.square ? pl.da : pl.db) : L;
   const int64_t nlimit = q == 0 ? pl.nout : L;
-  if (!inverse)
-    hipLaunchKernelGGL(k64_ypass<0>, dim3((unsigned)blocks), dim3(BLOCK), 0, st, X, L, 2 * pl.K, cols,
-                       ps.logn, ps.logS, ps.logT, ps.logG, nz_a, nz_b, pl.K, L, S.primes);
-  else
-    hipLaunchKernelGGL(k64_ypass<1>, dim3((unsigned)blocks), dim3(BLOCK), 0, st, X, L, 2 * pl.K, cols,
-                       ps.logn, ps.logS, ps.logT, ps.logG, L, L, pl.K, nlimit, S.primes);
+  // the shapes of the planner's passes for L = 2^17 ... 2^21: the innermost 2^9-point
+  // pass (16 transforms per workgroup) and outer passes of 2^8 and 2^9 points on
+  // 16-column tiles
+  const int shape = (ps.logn == 9 && ps.logT == 0 && ps.logG == 4)   ? 1
+                    : (ps.logn == 8 && ps.logT == 4 && ps.logG == 0) ? 2
+                    : (ps.logn == 9 && ps.logT == 4 && ps.logG == 0) ? 3
+                                                                     : 0;
+#define ZPM_YP(INV_, LN, LT, LG)                                                              \
+  hipLaunchKernelGGL((k64_ypass<INV_, LN, LT, LG>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, X, L, \
+                     2 * pl.K, cols, ps.logn, ps.logS, ps.logT, ps.logG, INV_ ? L : nz_a,      \
+                     INV_ ? L : nz_b, pl.K, INV_ ? nlimit : L, S.primes)
+#define ZPM_YP_ALL(INV_)                          \
+  switch (shape) {                                \
+    case 1: ZPM_YP(INV_, 9, 0, 4); break;         \
+    case 2: ZPM_YP(INV_, 8, 4, 0); break;         \
+    case 3: ZPM_YP(INV_, 9, 4, 0); break;         \
+    default: ZPM_YP(INV_, -1, -1, -1); break;     \
+  }
+  if (!inverse) {
+    ZPM_YP_ALL(0)
+  } else {
+    ZPM_YP_ALL(1)
+  }
+#undef ZPM_YP_ALL
+#undef ZPM_YP
 }
 
 int mul_p64(Ctx &cx, const Plan64 &pl, const uint64_t *a, const uint64_t *b, uint64_t *c, int32_t wc,
@@ -902,12 +963,25 @@ int mul_p64(Ctx &cx, const Plan64 &pl, const uint64_t *a, const uint64_t *b, uin
   }
   prof.begin(KK_P64_X, st);
   const int64_t xblocks = (int64_t)pl.np * (L >> pl.logTX);
-  if (pl.square)
-    hipLaunchKernelGGL(k64_xconv<1>, dim3((unsigned)xblocks), dim3(BLOCK), 0, st, X, L,
-                       __builtin_ctz(pl.K), pl.logTX, S.primes, pd);
-  else
-    hipLaunchKernelGGL(k64_xconv<0>, dim3((unsigned)xblocks), dim3(BLOCK), 0, st, X, L,
-                       __builtin_ctz(pl.K), pl.logTX, S.primes, pd);
+  // K = 64 and 128 with their widest tiles have compile-time kernels
+  const int lk = __builtin_ctz(pl.K);
+  const int xshape = (lk == 6 && pl.logTX == 5) ? 1 : (lk == 7 && pl.logTX == 4) ? 2 : 0;
+#define ZPM_XC(SQ_, LK_, LT_)                                                                 \
+  hipLaunchKernelGGL((k64_xconv<SQ_, LK_, LT_>), dim3((unsigned)xblocks), dim3(BLOCK), 0, st, X, L, \
+                     lk, pl.logTX, S.primes, pd)
+#define ZPM_XC_ALL(SQ_)                          \
+  switch (xshape) {                              \
+    case 1: ZPM_XC(SQ_, 6, 5); break;            \
+    case 2: ZPM_XC(SQ_, 7, 4); break;            \
+    default: ZPM_XC(SQ_, -1, -1); break;         \
+  }
+  if (pl.square) {
+    ZPM_XC_ALL(1)
+  } else {
+    ZPM_XC_ALL(0)
+  }
+#undef ZPM_XC_ALL
+#undef ZPM_XC
   prof.end(st);
   if (pl.npass) {
     prof.begin(KK_P64_YINV, st);

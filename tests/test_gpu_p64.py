@@ -142,3 +142,21 @@ def test_p64_bits4096_64k(ctx, K, np_):
     torch.cuda.empty_cache()
     if not check_digest("bits4096_64k", got):
         full_checks(prod, got, 16, 9)
+
+
+@pytest.mark.parametrize("K", [64, 128])
+def test_p64_square_fixed_shapes(ctx, K):
+    """Squares on the compile-time x-kernels (K = 64, 128) and the fixed innermost y pass:
+    sampled rows against the oracle and every word against the 31-bit prime path."""
+    d, N = 4097, 20 * K
+    p = synth.dense(64 + K, d, N - 1)
+    pl = api.plan_p64(d, N, d, N, K=K)
+    assert pl["pass_log2n"][-1] == 9
+    print(f"[p64 square] K={K} d={d} N={N} np={pl['np']}", flush=True)
+    A = dev(p.a)
+    got = host(ctx.mul_p64(A, N, A, N, K=K))
+    other = host(ctx.mul(A, N, A, N))
+    assert np.array_equal(got, other), "64-bit and 31-bit prime squares disagree"
+    rows = [0, 1, d - 1, d, 2 * d - 3, 2 * d - 2, 1234, 5000]
+    ref = oracle.polymul_rows(p.a, d, N, p.a, d, N, rows, wc=got.shape[1])
+    assert np.array_equal(got[rows], ref)
