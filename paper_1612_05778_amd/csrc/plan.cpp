@@ -103,14 +103,17 @@ static bool finish(Plan &pl) {
     --lt;
   if (((2 * wmax + 1) << lt) + pw_words > LDS_WORDS) return false;
   pl.log_ti_in = lt;
-  // recovery: TI coefficients x nw32 64-bit partial sums (<= 48 KiB); the smallest tile
-  // that still gives the workgroup at least 192 of its 256 threads' worth of items, so
-  // that more workgroups share a CU's LDS
+  // recovery: TI coefficients x nw32 64-bit partial sums (<= 48 KiB) and at most 1024
+  // items; then the smallest tile that still gives the workgroup at least 192 of its 256
+  // threads' worth of items, so that more workgroups share a CU's LDS, but not below 4
+  // coefficients: a tile's residue loads take TI consecutive words of each row, and
+  // narrower tiles waste most of each line (wide outputs, large K)
   const int64_t J = 2 * (int64_t)pl.K - 1;
   const int64_t nw32 = 2 * (int64_t)((pl.nout_bits + 63) / 64);
   lt = 6;
   const int64_t crt_words = (int64_t)(pl.np + 1) * pl.W + pl.W + 5 * pl.np + 2;
-  while (lt > 0 && ((nw32 << lt) * 2 > 12288 || (J << lt) > 1024 || (J << (lt - 1)) >= 192)) --lt;
+  while (lt > 0 && ((nw32 << lt) * 2 > 12288 || (J << lt) > 1024)) --lt;
+  while (lt > 2 && (J << (lt - 1)) >= 192) --lt;
   if ((nw32 << lt) * 2 + crt_words > LDS_WORDS) return false;
   pl.log_ti_out = lt;
   pl.ws_words = (int64_t)pl.np * 2 * pl.K << pl.logL;
