@@ -66,7 +66,11 @@ def test_forced_K_and_invalid():
     for K in (4, 8, 16):
         L = schedule(sizes, K)
         conv = L[L[:, 1] == 2]
-        assert len(conv) == 1 and conv[0, 2] == int(np.log2(K)) and conv[0, 3] == 3
+        # variant: log2 K of the register kernel, + 32 when the inner factor is the
+        # full 2^(12 - log2 K) (the compile-time kernel)
+        pl = api.plan(300, 500, 200, 400, K=K)
+        full = 32 if pl["log2_L1"] == 12 - int(np.log2(K)) else 0
+        assert len(conv) == 1 and conv[0, 2] == int(np.log2(K)) + full and conv[0, 3] == 3
     jobs = jobs_for([(3, 8, 3, 8)])
     jobs[0].wc = 0
     n = nat.c_i64()
