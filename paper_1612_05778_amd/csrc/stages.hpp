@@ -266,6 +266,16 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
   return (int64_t)(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
 }
 
+// lo += a b over 64 bits, hi += the carry out: the multiply-add's own carry feeds one
+// add-with-carry (the compiler would compare and select instead).  Register-only ALU.
+__device__ __forceinline__ void mac_carry(uint64_t &lo, uint32_t &hi, uint32_t a, uint32_t b) {
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t"
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc"
+      : "+v"(lo), "+v"(hi)
+      : "v"(a), "v"(b)
+      : "vcc");
+}
+
 // NP = np exactly: per-prime accumulators stay in registers, loops fully unrolled.
 template <int NP>
 __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__restrict__ src,
@@ -302,11 +312,11 @@ __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__
   const int nchunks = (M + 31) >> 5;
   const uint32_t lastmask = (M & 31) ? ((1u << (M & 31)) - 1u) : 0xFFFFFFFFu;
   const int64_t twoK = 2 * (int64_t)K;
-  // 2^(32 t) mod p_k with Shoup companions, [t][k], after the staged tile
-  uint2 *pw = reinterpret_cast<uint2 *>(s + (((ti * stride) + 1) & ~1));
+  // 2^(32 t) mod p_k, [t][k], after the staged tile
+  uint32_t *pw = s + (((ti * stride) + 1) & ~1);
   for (int idx = threadIdx.x; idx < nchunks * np; idx += BLOCK) {
     const int t = idx / np, k = idx - t * np;
-    pw[idx] = primes[k].pow32[t];
+    pw[idx] = primes[k].pow32[t].x;
   }
   __syncthreads();
   uint32_t pk[NP];
@@ -319,20 +329,18 @@ __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__
     const uint32_t *row = s + il * stride;
     const uint32_t sgn = (uint32_t)((int32_t)row[nw - 1] >> 31);
     const int64_t b = (int64_t)M * j;
-    // unsigned value of bits [b, b + M): sum_t chunk_t 2^(32 t), reduced lazily per prime
-    uint64_t acc[NP];
+    // unsigned value of bits [b, b + M): sum_t chunk_t (2^(32 t) mod p), summed exactly
+    // per prime as lo + 2^64 hi (each term is below 2^63), reduced once at the end
+    uint64_t lo[NP];
+    uint32_t hi[NP];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) acc[k] = 0;
+    for (int k = 0; k < NP; ++k) { lo[k] = 0; hi[k] = 0; }
     for (int t = 0; t < nchunks; ++t) {
       uint32_t c = get32(row, nw, sgn, b + 32 * (int64_t)t);
       if (t == nchunks - 1) c &= lastmask;
-      const uint2 *pwt = pw + t * NP;
+      const uint32_t *pwt = pw + t * NP;
 #pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        const uint2 w2 = pwt[k];
-        const uint32_t q = __umulhi(c, w2.y);
-        acc[k] += (uint32_t)(c * w2.x - q * pk[k]);   // in [0, 2p)
-      }
+      for (int k = 0; k < NP; ++k) mac_carry(lo[k], hi[k], c, pwt[k]);
     }
     // the top limb is signed: subtract 2^M when its top bit (bit M K - 1) is set
     const bool neg_top = (j == K - 1) && ((get32(row, nw, sgn, b + M - 1) & 1u) != 0);
@@ -341,8 +349,9 @@ __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__
       const uint32_t p = pk[k];
       const uint2 one = make_uint2(1u, primes[k].ones);
       const uint2 c32 = make_uint2(primes[k].c32, primes[k].c32s);
-      uint32_t r = add_mod(mul_shoup((uint32_t)acc[k], one, p),
-                           mul_shoup((uint32_t)(acc[k] >> 32), c32, p), p);
+      uint32_t r = add_mod(mul_shoup((uint32_t)lo[k], one, p),
+                           mul_shoup((uint32_t)(lo[k] >> 32), c32, p), p);
+      r = add_mod(r, mul_shoup(hi[k], primes[k].pow32[2], p), p);   // 2^64 mod p
       if (neg_top) r = sub_mod(r, pd->pow2M[k], p);
       X[((int64_t)k * twoK + col_off + j) * L + i0 + il] = r;
     }
@@ -881,16 +890,6 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
 // then c_i = sum_j c_{i,j} 2^(M j) (evaluation at beta = 2^M) by per-word sums of
 // shifted windows and a wave-wide carry scan.
 // ------------------------------------------------------------------------------------
-// lo += a b over 64 bits, hi += the carry out: the multiply-add's own carry feeds one
-// add-with-carry (the compiler would compare and select instead).  Register-only ALU.
-__device__ __forceinline__ void mac_carry(uint64_t &lo, uint32_t &hi, uint32_t a, uint32_t b) {
-  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t"
-      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc"
-      : "+v"(lo), "+v"(hi)
-      : "v"(a), "v"(b)
-      : "vcc");
-}
-
 __device__ __forceinline__ int fapply(int code, int y) { return ((code >> (2 * (y + 1))) & 3) - 1; }
 __device__ __forceinline__ int fcompose(int g, int f) {   // g after f
   int r = 0;
