@@ -195,7 +195,7 @@ size_t stage_lds(const Plan &pl, int kind, int pass) {
     case SK_RECOVER: {
       const int nw32 = 2 * ((pl.nout_bits + 63) / 64);
       return sizeof(uint64_t) * ((size_t)nw32 << pl.log_ti_out) +
-             sizeof(uint32_t) * ((size_t)((pl.np + 1) & ~1) * pl.np + pl.np + ((3 * pl.np + 1) & ~1)) +
+             sizeof(uint32_t) * ((size_t)((pl.np + 2) & ~1) * pl.np + ((3 * pl.np + 1) & ~1)) +
              sizeof(double) * pl.np;
     }
     default:

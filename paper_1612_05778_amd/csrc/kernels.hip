@@ -235,7 +235,7 @@ hipError_t launch_recover(const Plan &pl, const DevState &ds, uint64_t *out, int
   const int logTI = pl.log_ti_out;
   const int64_t blocks = xcd_grid((pl.nout + (1 << logTI) - 1) >> logTI);
   const size_t lds = sizeof(uint64_t) * ((size_t)nw32 << logTI) +
-                     sizeof(uint32_t) * ((size_t)((pl.np + 1) & ~1) * pl.np + pl.np + ((3 * pl.np + 1) & ~1)) +
+                     sizeof(uint32_t) * ((size_t)((pl.np + 2) & ~1) * pl.np + ((3 * pl.np + 1) & ~1)) +
                      sizeof(double) * pl.np;
 #define ZPM_REC(NP_)                                                                           \
   case NP_:                                                                                    \

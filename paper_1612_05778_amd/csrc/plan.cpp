@@ -95,11 +95,13 @@ static bool finish(Plan &pl) {
   const int wa = (pl.Na + 63) / 64, wb = (pl.Nb + 63) / 64;
   const int wmax = std::max(wa, wb);
   // convert-in: stage TI coefficients (2w+1 words each) in LDS; the smallest tile whose
-  // K TI limbs still give every thread of the workgroup one
+  // K TI limbs still give every thread of the workgroup one, but not below 16
+  // coefficients where LDS allows: each residue row gets TI consecutive words per
+  // workgroup, and shorter runs than 64 bytes slow the writes down (large K)
   const int pw_words = 2 * ((pl.M + 31) / 32) * pl.np + 2;   // staged 2^(32t) mod p table
   int lt = 6;
   while (lt > 0 && ((((2 * wmax + 1) << lt) + pw_words > LDS_WORDS) ||
-                    ((int64_t)pl.K << (lt - 1)) >= BLOCK))
+                    (lt > 4 && ((int64_t)pl.K << (lt - 1)) >= BLOCK)))
     --lt;
   if (((2 * wmax + 1) << lt) + pw_words > LDS_WORDS) return false;
   pl.log_ti_in = lt;

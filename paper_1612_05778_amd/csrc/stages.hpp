@@ -908,24 +908,25 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
                              const PlanDev *__restrict__ pd, uint64_t *__restrict__ out) {
   // S: TI x nw32 partial sums, then the CRT constants
   constexpr int W = NP;
-  constexpr int NPE = (NP + 1) & ~1;  // primes padded to a pair
+  constexpr int NT = NP + 1;          // terms of each word: the np residues, then t
+  constexpr int NPE = (NT + 1) & ~1;  // terms padded to a pair
   const int TI = 1 << logTI;
   const int J = 2 * K - 1;            // c_{i,2K-1} = 0
   const int64_t twoK = 2 * (int64_t)K;
   const int64_t i0 = tile_id << logTI;
   if (i0 >= nout) return;
   const int ti = (int)min<int64_t>(TI, nout - i0);
-  // CRT constants, read by every lane: P/p_k as [u][k] (W x NPE words), P (W words),
+  // CRT constants, read by every lane: as [u][k] (W x NPE words) P/p_k for k < np and,
+  // at k = np, 2^(32 W) - P (P is odd, so its negation is ~P + 1 = -P[0], ~P[1], ...);
   // per prime (c_k Shoup pair, p_k), and 1/p_k
   uint32_t *cq = reinterpret_cast<uint32_t *>(S + ((int64_t)nw32 << logTI));
-  uint32_t *cp = cq + NPE * W;
-  uint32_t *ci = cp + W;
+  uint32_t *ci = cq + NPE * W;
   double *cr = reinterpret_cast<double *>(ci + ((3 * NP + 1) & ~1));
   for (int idx = threadIdx.x; idx < NPE * W; idx += BLOCK) {
     const int u = idx / NPE, kk = idx - u * NPE;
-    cq[idx] = kk < NP ? pd->crt_q[kk][u] : 0u;
+    cq[idx] = kk < NP ? pd->crt_q[kk][u]
+                      : kk == NP ? (u == 0 ? 0u - pd->crt_p[0] : ~pd->crt_p[u]) : 0u;
   }
-  for (int idx = threadIdx.x; idx < W; idx += BLOCK) cp[idx] = pd->crt_p[idx];
   for (int idx = threadIdx.x; idx < NP; idx += BLOCK) {
     ci[3 * idx] = pd->crt_inv[idx].x;
     ci[3 * idx + 1] = pd->crt_inv[idx].y;
@@ -942,7 +943,6 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
     uint32_t cc[NPE];
 #pragma unroll
     for (int k = 0; k < NP; ++k) cc[k] = X[((int64_t)k * twoK + j) * L + i];
-    if (NPE > NP) cc[NPE - 1] = 0;
     double f = 0.0;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
@@ -950,34 +950,31 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
       f += (double)cc[k] * cr[k];
     }
     // c_{i,j} = sum_k c_k (P/p_k) - t P, where sum_k c_k P/p_k = c + t P with |c| < P/4,
-    // so t = round(sum_k c_k / p_k).  The value is produced one 32-bit word u at a time
-    // (column sums of the products over 64 bits, with the carries out of bit 63 counted
-    // in a third word, and a signed carry between words) and its shifted digits are
-    // added into the output words at once.
-    const uint32_t tq = (uint32_t)__double2int_rn(f);
+    // so t = round(sum_k c_k / p_k).  Adding t (2^(32 W) - P) instead of subtracting t P
+    // gives c + t 2^(32 W), whose low W words are c in two's complement: every term is
+    // an unsigned product.  The value is produced one 32-bit word u at a time (column
+    // sums of the products over 64 bits, the carries out of bit 63 counted in a third
+    // word, the bits above the word carried into the next one) and its shifted digits
+    // are added into the output words at once.
+    cc[NP] = (uint32_t)__double2int_rn(f);
+    if (NPE > NT) cc[NPE - 1] = 0;
     const int64_t bit = (int64_t)M * j;
     const int64_t q0 = bit >> 5;
     const int sh = (int)(bit & 31);
     uint64_t *Si = S + (int64_t)il * nw32;
-    int64_t carry = 0;
+    uint64_t lo = 0;
     uint32_t prev = 0;
 #pragma unroll
     for (int u = 0; u < W; ++u) {
-      uint64_t lo = 0;
       uint32_t hi = 0;
 #pragma unroll
       for (int k = 0; k < NPE; k += 2) {
         const uint2 qq = *reinterpret_cast<const uint2 *>(cq + u * NPE + k);
         mac_carry(lo, hi, cc[k], qq.x);
-        mac_carry(lo, hi, cc[k + 1], qq.y);
+        if (k + 1 < NT) mac_carry(lo, hi, cc[k + 1], qq.y);
       }
-      const uint64_t tp = (uint64_t)tq * cp[u];
-      const uint64_t D = lo - tp;
-      int64_t H = (int64_t)hi - (lo < tp ? 1 : 0);
-      const uint64_t D2 = D + (uint64_t)carry;
-      H += (D2 < D ? 1 : 0) - (carry < 0 ? 1 : 0);
-      const uint32_t wd = (uint32_t)D2;                 // word u of c_{i,j}, two's complement
-      carry = (int64_t)((uint64_t)H << 32) + (int64_t)(D2 >> 32);
+      const uint32_t wd = (uint32_t)lo;                 // word u of c_{i,j}, two's complement
+      lo = (lo >> 32) | ((uint64_t)hi << 32);           // carry into word u + 1
       const uint32_t dgt = sh ? ((wd << sh) | (prev >> (32 - sh))) : wd;
       prev = wd;
       if (q0 + u < nw32 && dgt) atomicAdd((unsigned long long *)&Si[q0 + u], (unsigned long long)dgt);
