@@ -9,6 +9,15 @@
 
 namespace zpm {
 
+// Read-only tables (twiddle heaps, 2^(32 t) tables) live in device memory.  Pointers
+// read from a structure are generic to the compiler, which then emits flat loads; these
+// go through the global address space instead, so that the loads are plain global (or,
+// where the index is uniform, scalar) reads that do not wait on LDS traffic.
+__device__ __forceinline__ uint2 ld_tab(const uint2 *__restrict__ tab, int64_t i) {
+  const uint64_t v = ((const __attribute__((address_space(1))) uint64_t *)tab)[i];
+  return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+
 // ------------------------------------------------------------------------------------
 // modular arithmetic on 32-bit words, p < 2^31
 // ------------------------------------------------------------------------------------
@@ -39,8 +48,8 @@ __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t p,
 // w_m^e from a heap table (tab[m/2 + e] = w_m^e for e < m/2), any e in [0, m).
 __device__ __forceinline__ uint2 heap_root(const uint2 *__restrict__ tab, int64_t m, int64_t e, uint32_t p) {
   const int64_t half = m >> 1;
-  if (e < half) return tab[half + e];
-  uint2 w = tab[e];            // w_m^(e - m/2) = -w_m^e
+  if (e < half) return ld_tab(tab, half + e);
+  uint2 w = ld_tab(tab, e);    // w_m^(e - m/2) = -w_m^e
   return make_uint2(p - w.x, ~w.y);
 }
 
@@ -103,7 +112,7 @@ __device__ void dif_group(uint32_t *s, const SH &sh, int logh0_rt, const uint2 *
 #pragma unroll
       for (int m = 0; m < NR; ++m) {
         if (m & half) continue;
-        const uint2 w = tw[hsz + j + (m & (half - 1)) * hl];
+        const uint2 w = ld_tab(tw, hsz + j + (m & (half - 1)) * hl);
         const uint32_t u = x[m], v = x[m + half];
         x[m] = add_mod(u, v, p);
         x[m + half] = mul_shoup(u - v + p, w, p);
@@ -149,7 +158,7 @@ __device__ void dit_group(uint32_t *s, const SH &sh, int logh0_rt, const uint2 *
 #pragma unroll
       for (int m = 0; m < NR; ++m) {
         if (m & half) continue;
-        const uint2 w = tw[hsz + j + (m & (half - 1)) * h0];
+        const uint2 w = ld_tab(tw, hsz + j + (m & (half - 1)) * h0);
         const uint32_t u = x[m];
         const uint32_t v = mul_shoup(x[m + half], w, p);
         x[m] = add_mod(u, v, p);
@@ -316,7 +325,7 @@ __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__
   uint32_t *pw = s + (((ti * stride) + 1) & ~1);
   for (int idx = threadIdx.x; idx < nchunks * np; idx += BLOCK) {
     const int t = idx / np, k = idx - t * np;
-    pw[idx] = primes[k].pow32[t].x;
+    pw[idx] = ld_tab(primes[k].pow32, t).x;
   }
   __syncthreads();
   uint32_t pk[NP];
@@ -351,7 +360,7 @@ __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__
       const uint2 c32 = make_uint2(primes[k].c32, primes[k].c32s);
       uint32_t r = add_mod(mul_shoup((uint32_t)lo[k], one, p),
                            mul_shoup((uint32_t)(lo[k] >> 32), c32, p), p);
-      r = add_mod(r, mul_shoup(hi[k], primes[k].pow32[2], p), p);   // 2^64 mod p
+      r = add_mod(r, mul_shoup(hi[k], ld_tab(primes[k].pow32, 2), p), p);   // 2^64 mod p
       if (neg_top) r = sub_mod(r, pd->pow2M[k], p);
       X[((int64_t)k * twoK + col_off + j) * L + i0 + il] = r;
     }
@@ -554,7 +563,7 @@ __device__ __forceinline__ void reg_dif(uint32_t (&x)[2 << LOGK], const uint2 *_
   constexpr int N2 = 2 << LOGK;
   // first stage: the upper half is zero, so x[j + K] = x[j] theta^j (the twist)
 #pragma unroll
-  for (int j = 0; j < N2 / 2; ++j) x[j + N2 / 2] = j ? mul_shoup(x[j], tw[N2 / 2 + j], p) : x[j];
+  for (int j = 0; j < N2 / 2; ++j) x[j + N2 / 2] = j ? mul_shoup(x[j], ld_tab(tw, N2 / 2 + j), p) : x[j];
 #pragma unroll
   for (int h = N2 / 4; h >= 1; h >>= 1) {
 #pragma unroll
@@ -563,7 +572,7 @@ __device__ __forceinline__ void reg_dif(uint32_t (&x)[2 << LOGK], const uint2 *_
       for (int j = 0; j < h; ++j) {
         const uint32_t u = x[blk + j], v = x[blk + j + h];
         x[blk + j] = add_mod(u, v, p);
-        x[blk + j + h] = j ? mul_shoup(u - v + p, tw[h + j], p) : sub_mod(u, v, p);
+        x[blk + j + h] = j ? mul_shoup(u - v + p, ld_tab(tw, h + j), p) : sub_mod(u, v, p);
       }
     }
   }
@@ -580,7 +589,7 @@ __device__ __forceinline__ void reg_dit(uint32_t (&x)[2 << LOGK], const uint2 *_
 #pragma unroll
       for (int j = 0; j < h; ++j) {
         const uint32_t u = x[blk + j];
-        const uint32_t v = j ? mul_shoup(x[blk + j + h], tw[h + j], p) : x[blk + j + h];
+        const uint32_t v = j ? mul_shoup(x[blk + j + h], ld_tab(tw, h + j), p) : x[blk + j + h];
         x[blk + j] = add_mod(u, v, p);
         x[blk + j + h] = sub_mod(u, v, p);
       }
