@@ -253,11 +253,19 @@ __device__ __forceinline__ uint64_t mont64(uint64_t a, uint64_t b, uint64_t p, u
   const uint64_t mp = __umul64hi(m, p);   // m p = lo mod 2^64, so no borrow below
   return hi >= mp ? hi - mp : hi - mp + p;
 }
+// Twiddle heaps live in device memory; their pointers come from the per-prime constants
+// and are generic to the compiler, so they are read through the global address space
+// (global or scalar loads instead of flat ones).
+__device__ __forceinline__ W64 ld_tab64(const W64 *__restrict__ tab, int64_t i) {
+  const auto *g = (const __attribute__((address_space(1))) uint64_t *)tab;
+  return W64{g[2 * i], g[2 * i + 1]};
+}
+
 // w_m^e from a heap table (tab[m/2 + e] = w_m^e for e < m/2), e in [0, m), m >= 2
 __device__ __forceinline__ W64 heap_root64(const W64 *__restrict__ tab, int64_t m, int64_t e, uint64_t p) {
   const int64_t half = m >> 1;
-  if (e < half) return tab[half + e];
-  const W64 w = tab[e];        // w_m^(e - m/2) = -w_m^e
+  if (e < half) return ld_tab64(tab, half + e);
+  const W64 w = ld_tab64(tab, e);   // w_m^(e - m/2) = -w_m^e
   return W64{p - w.w, ~w.s};
 }
 
@@ -296,7 +304,7 @@ __device__ void dif64_group(uint64_t *s, const SH &sh, int logh0_rt, const W64 *
 #pragma unroll
       for (int m = 0; m < NR; ++m) {
         if (m & half) continue;
-        const W64 w = tw[hsz + j + (m & (half - 1)) * hl];
+        const W64 w = ld_tab64(tw, hsz + j + (m & (half - 1)) * hl);
         const uint64_t u = x[m], v = x[m + half];
         x[m] = add64(u, v, p);
         x[m + half] = mulsh64(u - v + p, w, p);
@@ -340,7 +348,7 @@ __device__ void dit64_group(uint64_t *s, const SH &sh, int logh0_rt, const W64 *
 #pragma unroll
       for (int m = 0; m < NR; ++m) {
         if (m & half) continue;
-        const W64 w = tw[hsz + j + (m & (half - 1)) * h0];
+        const W64 w = ld_tab64(tw, hsz + j + (m & (half - 1)) * h0);
         const uint64_t u = x[m];
         const uint64_t v = mulsh64(x[m + half], w, p);
         x[m] = add64(u, v, p);
