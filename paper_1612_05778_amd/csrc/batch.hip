@@ -148,9 +148,9 @@ hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *seg
       // factor; LDS kernel: 0 (any K), or 64 + log2 K with its full inner factor
       if (gr.variant >= 64) {
         switch (gr.variant - 64) {
-          case 6: hipLaunchKernelGGL((kg_convolve<6, 6>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
-          case 7: hipLaunchKernelGGL((kg_convolve<7, 5>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
-          case 8: hipLaunchKernelGGL((kg_convolve<8, 4>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+          case 6: hipLaunchKernelGGL((kg_convolve<6, 5>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+          case 7: hipLaunchKernelGGL((kg_convolve<7, 4>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
+          case 8: hipLaunchKernelGGL((kg_convolve<8, 3>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
           default: return hipErrorInvalidValue;
         }
         break;

@@ -215,15 +215,16 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
     return hipGetLastError();
   }
   const size_t lds = sizeof(uint32_t) * (size_t)4 * pl.K << pl.logL1;
-  // K = 64, 128, 256 with their full inner factor (4 K L1 = LDS_WORDS) fixed at compile time
+  // K = 64, 128, 256 with the planner's inner factor (4 K L1 = LDS_WORDS / 2) fixed at
+  // compile time
   const int lk = ilog2(pl.K);
 #define ZPM_CONV_LDS(LK_, LL1_)                                                                \
   hipLaunchKernelGGL((k_convolve_rows<LK_, LL1_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, \
                      ds.X, L, pl.K, lk, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, mode, spec)
   if (!fixed_lds_kl1(lk, pl.logL1)) ZPM_CONV_LDS(-1, -1);
-  else if (lk == 6) ZPM_CONV_LDS(6, 6);
-  else if (lk == 7) ZPM_CONV_LDS(7, 5);
-  else ZPM_CONV_LDS(8, 4);
+  else if (lk == 6) ZPM_CONV_LDS(6, 5);
+  else if (lk == 7) ZPM_CONV_LDS(7, 4);
+  else ZPM_CONV_LDS(8, 3);
 #undef ZPM_CONV_LDS
   return hipGetLastError();
 }

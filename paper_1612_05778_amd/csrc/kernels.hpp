@@ -16,9 +16,9 @@ inline int fixed_col_index(int logn, int logT) {
   return 0;
 }
 // Register row kernels have a compile-time kernel for their full inner factor
-// 2^(12 - log2 K); the LDS row kernel for K = 64, 128, 256 with 4 K L1 = 16384 words.
+// 2^(12 - log2 K); the LDS row kernel for K = 64, 128, 256 with 4 K L1 = 8192 words.
 inline bool fixed_reg_l1(int logK, int logL1) { return logL1 == 12 - logK; }
-inline bool fixed_lds_kl1(int logK, int logL1) { return logK >= 6 && logK <= 8 && logL1 == 12 - logK; }
+inline bool fixed_lds_kl1(int logK, int logL1) { return logK >= 6 && logK <= 8 && logL1 == 11 - logK; }
 
 // Device pointers a launch needs.
 struct DevState {

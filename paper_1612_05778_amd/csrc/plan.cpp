@@ -64,6 +64,9 @@ static bool split_y(Plan &pl, int reg_k_max, int col_tile) {
     // two 2K x L1 tiles: 4 K L1 <= LDS_WORDS
     while ((4ll << (logK + logcap + 1)) <= LDS_WORDS) ++logcap;
     if ((4ll << (logK + logcap)) > LDS_WORDS) return false;     // K too large even for L1 = 1
+    // tiles of half that (32 KiB) where L1 allows: five workgroups share a CU's LDS
+    // instead of two, which hides the LDS latency of the x-transforms
+    if (logcap >= 1) --logcap;
   }
   pl.logL1 = std::min(pl.logL, logcap);
   int rest = pl.logL - pl.logL1;

@@ -62,13 +62,13 @@ def test_fixed_shapes(ctx, K, logn):
     torch.cuda.empty_cache()
 
 
-# the LDS row kernel (K >= 64) with its full inner factor: 4 K L1 = 16384 words
+# the LDS row kernel (K >= 64) with the planner's inner factor: 4 K L1 = 8192 words
 LDS_CASES = [(K, logn) for K in (64, 128, 256) for logn in (5, 7, 9)]
 
 
 @pytest.mark.parametrize("K,logn", LDS_CASES)
 def test_fixed_shapes_lds_kernel(ctx, K, logn):
-    logL1 = 14 - 2 - (K.bit_length() - 1)
+    logL1 = 13 - 2 - (K.bit_length() - 1)
     logL = logL1 + logn
     d = (1 << (logL - 2)) + 1
     N = 3 * K                                  # M = 3
