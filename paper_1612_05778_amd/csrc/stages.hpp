@@ -992,7 +992,32 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
     if (q0 + W < nw32 && top) atomicAdd((unsigned long long *)&Si[q0 + W], (unsigned long long)top);
   }
   __syncthreads();
-  // ---- carries, one wave per coefficient ----
+  // ---- carries ----
+  if (nw32 <= 8 * TI) {
+    // short outputs: one lane per coefficient, its words in order (eight LDS reads in
+    // flight ahead of the carry chain)
+    for (int il = threadIdx.x; il < ti; il += BLOCK) {
+      uint64_t *Si = S + (int64_t)il * nw32;
+      int64_t carry = 0;
+      for (int w0 = 0; w0 < nw32; w0 += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = w0 + u < nw32 ? Si[w0 + u] : 0ull;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t tsum = (int64_t)v[u] + carry;
+          if (w0 + u < nw32) Si[w0 + u] = (uint32_t)tsum;
+          carry = tsum >> 32;
+        }
+      }
+      const uint64_t fill = ((int32_t)(uint32_t)Si[nw32 - 1] < 0) ? ~0ull : 0ull;
+      uint64_t *o = out + (i0 + il) * (int64_t)wc;
+      for (int u = 0; u < wc; ++u)
+        o[u] = (2 * u + 1 < nw32) ? ((Si[2 * u] & 0xFFFFFFFFull) | (Si[2 * u + 1] << 32)) : fill;
+    }
+    return;
+  }
+  // long outputs: one wave per coefficient
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int per = (nw32 + 63) >> 6;
   const int w_lo = min(lane * per, nw32), w_hi = min(w_lo + per, nw32);
