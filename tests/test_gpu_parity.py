@@ -103,6 +103,20 @@ def test_binomial(ctx):
     assert pyint.decode(got, 64 * got.shape[1]) == [math.comb(2 * n, i) for i in range(2 * n + 1)]
 
 
+# The recovery normalises carries either one lane per coefficient (outputs of at most
+# 8 * TI 32-bit words, TI coefficients per workgroup) or one wave per coefficient with a
+# scan.  With K = 16 the tile is 8 coefficients, so 50 x 1021-bit operands (outputs of
+# 64 words) take the first branch and 50 x 1022-bit ones (66 words) the second; the rest
+# reach each branch with long serial chains (K = 2, tiles of 64) or tiles of 4.
+@pytest.mark.parametrize("d,N,K", [(50, 1021, 16), (50, 1022, 16), (100, 1000, 2),
+                                   (200, 64, 0), (40, 6000, 0), (30, 24000, 0)])
+def test_carry_branches(ctx, d, N, K):
+    r = synth.rng_for(7 * d + N)
+    A, _ = synth.signed_words(r, d, N - 1)
+    B, _ = synth.signed_words(r, d + 3, N - 1)
+    check(ctx, A, d, N, B, d + 3, N, K=K)
+
+
 def test_plans_agree(ctx):
     p = synth.dense(21, 777, 900)
     ref = None
