@@ -417,10 +417,15 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   const int S32 = (int)S;
   const int lim_store = (int)std::min<int64_t>(std::max<int64_t>(nlimit - first, 0), L);
   if (!inverse) {
+    // every load of this thread is in its own column t (BLOCK is a multiple of T): row e
+    // is below nz iff e < e_lim.  S is a power of two.
+    const int logS = __builtin_ctzll((unsigned long long)S);
+    const int64_t rem = nz - first - t;
+    const int e_lim = rem <= 0 ? 0 : (int)min<int64_t>((rem + S - 1) >> logS, n);
+    const uint32_t *bt = base + t;
     staged<8, uint32_t>(n << logT, [&](int idx) {
-      const int tt = idx & (T - 1), e = idx >> logT;
-      const int64_t off = tt + S * (int64_t)e;
-      return (first + off < nz) ? base[off] : 0u;
+      const int e = idx >> logT;
+      return e < e_lim ? bt[(int64_t)e << logS] : 0u;
     }, [&](int idx, uint32_t v) { s[idx] = v; });
     __syncthreads();
     if constexpr (fixed) lds_dif_c<CSH>(s, pr.hf, p);
