@@ -497,17 +497,21 @@ __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   uint32_t *B = s + twoK * L1;          // 2K rows x L1
   uint32_t *base = X + (int64_t)k * twoK * L + rb * L1;
   const int64_t y0 = rb * L1;
+  const int logL = __builtin_ctzll((unsigned long long)L);
+  // rows are read below nz_a / nz_b and written below nlimit: as positions in the block
+  const int lim_b = (int)max<int64_t>(0, min<int64_t>(nz_b - y0, L1));
+  const int lim_o = (int)max<int64_t>(0, min<int64_t>(nlimit - y0, L1));
   // A: a's limb rows (b's for CM_SPECTRUM); the upper K rows are the zero padding
   const int src_a = mode == CM_SPECTRUM ? K : 0;
-  const int64_t nz_first = mode == CM_SPECTRUM ? nz_b : nz_a;
+  const int lim_first = mode == CM_SPECTRUM ? lim_b : (int)max<int64_t>(0, min<int64_t>(nz_a - y0, L1));
   staged<8, uint32_t>(K << logL1, [&](int idx) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
-    return (y0 + e < nz_first) ? base[(int64_t)(src_a + j) * L + e] : 0u;
+    return e < lim_first ? base[((int64_t)(src_a + j) << logL) + e] : 0u;
   }, [&](int idx, uint32_t v) { A[idx] = v; A[(K << logL1) + idx] = 0u; });
   if (mode == CM_PRODUCT) {
     staged<8, uint32_t>(K << logL1, [&](int idx) {
       const int j = idx >> logL1, e = idx & (L1 - 1);
-      return (y0 + e < nz_b) ? base[(int64_t)(K + j) * L + e] : 0u;
+      return e < lim_b ? base[((int64_t)(K + j) << logL) + e] : 0u;
     }, [&](int idx, uint32_t v) { B[idx] = v; B[(K << logL1) + idx] = 0u; });
   } else if (mode == CM_WITH_SPECTRUM) {
     // b's spectra, in the order the forward transforms below leave A in
@@ -553,7 +557,7 @@ __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   }
   staged<8, uint32_t>(twoK << logL1, [&](int idx) { return A[idx]; }, [&](int idx, uint32_t v) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
-    if (y0 + e < nlimit) base[(int64_t)j * L + e] = v;
+    if (e < lim_o) base[((int64_t)j << logL) + e] = v;
   });
 }
 
@@ -622,6 +626,11 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
   uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
   const int64_t y0 = rb * L1;
   const int L32 = (int)L;   // 2K rows of at most 2^21 words: 32-bit row offsets
+  const int logL = __builtin_ctzll((unsigned long long)L);
+  // rows are read below nz_a / nz_b and written below nlimit: as positions in the block
+  const int lim_a = (int)max<int64_t>(0, min<int64_t>(nz_a - y0, L1));
+  const int lim_b = (int)max<int64_t>(0, min<int64_t>(nz_b - y0, L1));
+  const int lim_o = (int)max<int64_t>(0, min<int64_t>(nlimit - y0, L1));
   // LDS rows 0..K-1: limbs of a (of b for CM_SPECTRUM); rows K..2K-1: limbs of b
   // (CM_PRODUCT only)
   constexpr bool one = MODE != CM_PRODUCT;
@@ -629,8 +638,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
   constexpr int src0 = MODE == CM_SPECTRUM ? K : 0;
   staged<8, uint32_t>(rows << logL1, [&](int idx) {
     const int j = src0 + (idx >> logL1), e = idx & (L1 - 1);
-    const int64_t nz = j < K ? nz_a : nz_b;
-    return (y0 + e < nz) ? base[j * L32 + e] : 0u;
+    return e < (j < K ? lim_a : lim_b) ? base[(j << logL) + e] : 0u;
   }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
   __syncthreads();
   if constexpr (CLOGL1 >= 0)
@@ -703,7 +711,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
     return s[(idx >> logL1) * RS + (idx & (L1 - 1))];
   }, [&](int idx, uint32_t v) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
-    if (y0 + e < nlimit) base[j * L32 + e] = v;
+    if (e < lim_o) base[(j << logL) + e] = v;
   });
 }
 
@@ -776,13 +784,17 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
   uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
   const int64_t y0 = rb * L1;
   const int L32 = (int)L;   // 2K rows of at most 2^21 words: 32-bit row offsets
+  const int logL = __builtin_ctzll((unsigned long long)L);
+  // rows are read below nz_a / nz_b and written below nlimit: as positions in the block
+  const int lim_a = (int)max<int64_t>(0, min<int64_t>(nz_a - y0, L1));
+  const int lim_b = (int)max<int64_t>(0, min<int64_t>(nz_b - y0, L1));
+  const int lim_o = (int)max<int64_t>(0, min<int64_t>(nlimit - y0, L1));
   constexpr bool one = MODE != CM_PRODUCT;
   constexpr int rows = one ? K : K2;
   constexpr int src0 = MODE == CM_SPECTRUM ? K : 0;
   staged<8, uint32_t>(rows << logL1, [&](int idx) {
     const int j = src0 + (idx >> logL1), e = idx & (L1 - 1);
-    const int64_t nz = j < K ? nz_a : nz_b;
-    return (y0 + e < nz) ? base[j * L32 + e] : 0u;
+    return e < (j < K ? lim_a : lim_b) ? base[(j << logL) + e] : 0u;
   }, [&](int idx, uint32_t v) { s[(idx >> logL1) * RS + (idx & (L1 - 1))] = v; });
   __syncthreads();
   if constexpr (CLOGL1 >= 0)
@@ -893,7 +905,7 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
     return s[(idx >> logL1) * RS + (idx & (L1 - 1))];
   }, [&](int idx, uint32_t v) {
     const int j = idx >> logL1, e = idx & (L1 - 1);
-    if (y0 + e < nlimit) base[j * L32 + e] = v;
+    if (e < lim_o) base[(j << logL) + e] = v;
   });
 }
 
