@@ -414,18 +414,18 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   uint32_t cur = mul_shoup(R, heap_root(tab, m, (inner * e0) & (m - 1), p), p);
   const uint32_t step = mul_shoup(R, heap_root(tab, m, (inner * de) & (m - 1), p), p);
   // offsets inside the column stay below L <= 2^21: 32-bit index arithmetic
-  const int S32 = (int)S;
   const int lim_store = (int)std::min<int64_t>(std::max<int64_t>(nlimit - first, 0), L);
+  // every global access of this thread is in its own column t (BLOCK is a multiple of
+  // T), at row offsets e S with S a power of two (e S < L <= 2^21)
+  const int logS = __builtin_ctzll((unsigned long long)S);
+  uint32_t *bt = base + t;
   if (!inverse) {
-    // every load of this thread is in its own column t (BLOCK is a multiple of T): row e
-    // is below nz iff e < e_lim.  S is a power of two.
-    const int logS = __builtin_ctzll((unsigned long long)S);
+    // row e is below nz iff e < e_lim
     const int64_t rem = nz - first - t;
     const int e_lim = rem <= 0 ? 0 : (int)min<int64_t>((rem + S - 1) >> logS, n);
-    const uint32_t *bt = base + t;
     staged<8, uint32_t>(n << logT, [&](int idx) {
       const int e = idx >> logT;
-      return e < e_lim ? bt[(int64_t)e << logS] : 0u;
+      return e < e_lim ? bt[e << logS] : 0u;
     }, [&](int idx, uint32_t v) { s[idx] = v; });
     __syncthreads();
     if constexpr (fixed) lds_dif_c<CSH>(s, pr.hf, p);
@@ -433,7 +433,7 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     for (int e = e0; e < n; e += de) {
       const uint32_t v = mont_mul(s[(bitrev(e, logn) << logT) + t], cur, p, pr.pinv);
       cur = mont_mul(cur, step, p, pr.pinv);
-      base[t + S32 * e] = v;
+      bt[e << logS] = v;
     }
   } else {
     // eight independent loads in flight per thread, then the twiddle progression
@@ -442,7 +442,7 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int ee = e + u * de;
-        v[u] = ee < n ? base[t + S32 * ee] : 0u;
+        v[u] = ee < n ? bt[ee << logS] : 0u;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -456,9 +456,12 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     __syncthreads();
     if constexpr (fixed) lds_dit_c<CSH>(s, pr.hi, p);
     else lds_dit(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hi, p);
+    // row e is stored iff t + e S < lim_store
+    const int rem = lim_store - t;
+    const int e_lim = rem <= 0 ? 0 : min((rem + (int)S - 1) >> logS, n);
     staged<8, uint32_t>(n << logT, [&](int idx) { return s[idx]; }, [&](int idx, uint32_t v) {
-      const int off = (idx & (T - 1)) + S32 * (idx >> logT);
-      if (off < lim_store) base[off] = v;
+      const int e = idx >> logT;
+      if (e < e_lim) bt[e << logS] = v;
     });
   }
 }
@@ -985,7 +988,8 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
     cc[NP] = (uint32_t)__double2int_rn(f);
     if (NPE > NT) cc[NPE - 1] = 0;
     const int64_t bit = (int64_t)M * j;
-    const int64_t q0 = bit >> 5;
+    // M j < 2 N, and convert-in's LDS tile keeps N below 2^19 bits: a 32-bit word index
+    const int q0 = (int)(bit >> 5);
     const int sh = (int)(bit & 31);
     uint64_t *Si = S + (int64_t)il * nw32;
     uint64_t lo = 0;
