@@ -390,15 +390,18 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   using CSH = CShape<(CLOGT >= 0 ? CLOGT : 0), (CLOGN >= 0 ? CLOGN : 1), 1,
                      (1 << (CLOGT >= 0 ? CLOGT : 0))>;
   const int n = 1 << logn, T = 1 << logT;
-  const int64_t inner_tiles = S >> logT;
-  const int64_t outers = L / ((int64_t)n * S);
-  const int64_t tiles = inner_tiles * outers;
-  const int64_t cidx = bid / tiles;
-  const int64_t tile = bid - cidx * tiles;
-  const int64_t outer = tile / inner_tiles;
-  const int64_t inner0 = (tile - outer * inner_tiles) << logT;
-  const int k = (int)(cidx / cols);
-  const int jc = col0 + (int)(cidx - (int64_t)k * cols);
+  // L, S, T and cols (K or 2K) are powers of two: the block index splits by shifts
+  const int logS = __builtin_ctzll((unsigned long long)S);
+  const int logL = __builtin_ctzll((unsigned long long)L);
+  const int log_inner = logS - logT;                  // inner tiles per outer index
+  const int log_tiles = logL - logn - logT;           // tiles per column
+  const int64_t cidx = bid >> log_tiles;
+  const int64_t tile = bid & (((int64_t)1 << log_tiles) - 1);
+  const int64_t outer = tile >> log_inner;
+  const int64_t inner0 = (tile & (((int64_t)1 << log_inner) - 1)) << logT;
+  const int log_cols = __builtin_ctz((unsigned)cols);
+  const int k = (int)(cidx >> log_cols);
+  const int jc = col0 + (int)(cidx & (cols - 1));
   const int64_t col = (int64_t)k * twoK + jc;
   const PrimeDev pr = primes[k];
   const uint32_t p = pr.p;
@@ -416,8 +419,7 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   // offsets inside the column stay below L <= 2^21: 32-bit index arithmetic
   const int lim_store = (int)std::min<int64_t>(std::max<int64_t>(nlimit - first, 0), L);
   // every global access of this thread is in its own column t (BLOCK is a multiple of
-  // T), at row offsets e S with S a power of two (e S < L <= 2^21)
-  const int logS = __builtin_ctzll((unsigned long long)S);
+  // T), at row offsets e S (e S < L <= 2^21)
   uint32_t *bt = base + t;
   if (!inverse) {
     // row e is below nz iff e < e_lim
@@ -490,9 +492,9 @@ __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   const int logK = fixed ? CLOGK : logK_rt, logL1 = fixed ? CLOGL1 : logL1_rt;
   const int K = fixed ? (1 << CLOGK) : K_rt;
   const int L1 = 1 << logL1;
-  const int64_t nrb = L >> logL1;
-  const int k = (int)(bid / nrb);
-  const int64_t rb = bid - (int64_t)k * nrb;
+  const int64_t nrb = L >> logL1;   // a power of two: the block index splits by shifts
+  const int k = (int)(bid >> __builtin_ctzll((unsigned long long)nrb));
+  const int64_t rb = bid & (nrb - 1);
   const PrimeDev pr = primes[k];
   const uint32_t p = pr.p;
   const int twoK = 2 * K;
@@ -621,9 +623,9 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
   constexpr int K = 1 << LOGK, K2 = 2 * K;
   const int logL1 = CLOGL1 >= 0 ? CLOGL1 : logL1_rt;
   const int L1 = 1 << logL1, RS = L1 + 1;      // odd row stride: rows fall on distinct banks
-  const int64_t nrb = L >> logL1;
-  const int k = (int)(bid / nrb);
-  const int64_t rb = bid - (int64_t)k * nrb;
+  const int64_t nrb = L >> logL1;   // a power of two: the block index splits by shifts
+  const int k = (int)(bid >> __builtin_ctzll((unsigned long long)nrb));
+  const int64_t rb = bid & (nrb - 1);
   const PrimeDev pr = primes[k];
   const uint32_t p = pr.p;
   uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
@@ -779,9 +781,9 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
   constexpr int K = 1 << LOGK, K2 = 2 * K;
   const int logL1 = CLOGL1 >= 0 ? CLOGL1 : logL1_rt;
   const int L1 = 1 << logL1, RS = L1 + 1;
-  const int64_t nrb = L >> logL1;
-  const int k = (int)(bid / nrb);
-  const int64_t rb = bid - (int64_t)k * nrb;
+  const int64_t nrb = L >> logL1;   // a power of two: the block index splits by shifts
+  const int k = (int)(bid >> __builtin_ctzll((unsigned long long)nrb));
+  const int64_t rb = bid & (nrb - 1);
   const PrimeDev pr = primes[k];
   const uint32_t p = pr.p;
   uint32_t *base = X + (int64_t)k * K2 * L + rb * L1;
