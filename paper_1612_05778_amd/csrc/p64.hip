@@ -496,10 +496,11 @@ __global__ __launch_bounds__(BLOCK) void k64_ypass(uint64_t *__restrict__ X, int
   const int64_t inner_tiles = S >> logT;
   const int64_t tiles = inner_tiles * ((L >> (logn + logS)) >> logG);
   const int64_t bid = blockIdx.x;
-  const int64_t cidx = bid / tiles, tile = bid - cidx * tiles;
-  const int k = (int)(cidx / cols), jc = (int)(cidx - (int64_t)k * cols);
-  const int64_t inner0 = (tile % inner_tiles) << logT;
-  const int64_t outer0 = (tile / inner_tiles) << logG;
+  // tiles, inner_tiles and cols (K or 2K) are powers of two: split by shifts
+  const int64_t cidx = bid >> __builtin_ctzll((unsigned long long)tiles), tile = bid & (tiles - 1);
+  const int k = (int)(cidx >> __builtin_ctz((unsigned)cols)), jc = (int)(cidx & (cols - 1));
+  const int64_t inner0 = (tile & (inner_tiles - 1)) << logT;
+  const int64_t outer0 = (tile >> (logS - logT)) << logG;
   const Prime64Dev pr = primes[k];
   const uint64_t p = pr.p;
   uint64_t *base = X + ((int64_t)k * twoK + jc) * L;
@@ -570,8 +571,8 @@ __global__ __launch_bounds__(BLOCK) void k64_xconv(uint64_t *__restrict__ X, int
   const int logK = fixed ? CLOGK : logK_rt, logTX = fixed ? CLOGTX : logTX_rt;
   const int K = 1 << logK, twoK = 2 * K, TX = 1 << logTX;
   const int64_t tiles = L >> logTX;
-  const int k = (int)(blockIdx.x / tiles);
-  const int64_t y0 = ((int64_t)blockIdx.x - (int64_t)k * tiles) << logTX;
+  const int k = (int)((int64_t)blockIdx.x >> __builtin_ctzll((unsigned long long)tiles));
+  const int64_t y0 = ((int64_t)blockIdx.x & (tiles - 1)) << logTX;
   const Prime64Dev pr = primes[k];
   const uint64_t p = pr.p;
   uint64_t *base = X + (int64_t)k * twoK * L + y0;
