@@ -1002,7 +1002,10 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
 #pragma unroll
       for (int k = 0; k < NPE; k += 2) {
         const uint2 qq = *reinterpret_cast<const uint2 *>(cq + u * NPE + k);
-        mac_carry(lo, hi, cc[k], qq.x);
+        // the first term cannot carry out of 64 bits: lo holds below 2^37 (the carry
+        // from word u - 1) and the product is below 2^63
+        if (k == 0) lo += (uint64_t)cc[0] * qq.x;
+        else mac_carry(lo, hi, cc[k], qq.x);
         if (k + 1 < NT) mac_carry(lo, hi, cc[k + 1], qq.y);
       }
       const uint32_t wd = (uint32_t)lo;                 // word u of c_{i,j}, two's complement
