@@ -165,6 +165,7 @@ hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, h
   case I: hipLaunchKernelGGL((k_col_pass<LN, LT>), ZPM_COL_ARGS); break;
     ZPM_COL_FIXED(1, 5, 6) ZPM_COL_FIXED(2, 6, 5) ZPM_COL_FIXED(3, 7, 4)
     ZPM_COL_FIXED(4, 8, 3) ZPM_COL_FIXED(5, 9, 3) ZPM_COL_FIXED(6, 10, 3)
+    ZPM_COL_FIXED(7, 8, 4) ZPM_COL_FIXED(8, 9, 4) ZPM_COL_FIXED(9, 10, 4)
 #undef ZPM_COL_FIXED
     default: hipLaunchKernelGGL((k_col_pass<-1, -1>), ZPM_COL_ARGS); break;
   }

@@ -41,14 +41,14 @@ int32_t out_bits(int64_t da, int32_t Na, int64_t db, int32_t Nb) {
 // Split of the y-transform: innermost factor L1 inside the fused kernel, the rest
 // into strided column passes of length <= 2^10 each.
 // Widest column tile of a strided pass (inner indices per workgroup); ZPM_COL_TILE
-// overrides the default of 8.  Tiles sharing 128-byte lines run next to each other on
-// one XCD, so narrow tiles cost no extra HBM traffic, and more workgroups per CU beat
-// longer runs.
+// overrides the default of 16.  Tiles sharing 128-byte lines run next to each other on
+// one XCD, so narrow tiles cost no extra HBM traffic; 16 columns (64-byte runs) suit the
+// inverse passes, which read every row, better than 8.
 static int64_t col_tile_max() {
   static const int64_t v = [] {
     const char *e = std::getenv("ZPM_COL_TILE");
     const long x = e ? std::atol(e) : 0;
-    return (int64_t)(x >= 1 && x <= 64 && !(x & (x - 1)) ? x : 8);
+    return (int64_t)(x >= 1 && x <= 64 && !(x & (x - 1)) ? x : 16);
   }();
   return v;
 }
