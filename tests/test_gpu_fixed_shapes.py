@@ -88,3 +88,36 @@ def test_fixed_shapes_lds_kernel(ctx, K, logn):
         op.close()
     del A, B
     torch.cuda.empty_cache()
+
+
+def _ceil_log2(x):
+    return (x - 1).bit_length()
+
+
+# Single products now take 16-column tiles; the 8-column compiled passes of 2^8 to 2^10
+# points are reached by batches whose tuned tile is 8.  A tuning table that sets (K, 8)
+# for the product's size class is loaded, and the batch must give the same words as the
+# single product (16-column passes) and the oracle at sampled rows.
+@pytest.mark.parametrize("K,logn", [(16, 8), (16, 9), (8, 10)])
+def test_batch_eight_column_passes(ctx, K, logn, tmp_path):
+    from paper_1612_05778_amd import _native as nat
+    logL1 = 12 - (K.bit_length() - 1)
+    logL = logL1 + logn
+    d = (1 << (logL - 2)) + 1
+    N = 17 * K
+    r = np.random.default_rng(K * 31 + logn)
+    a, _ = synth.signed_words(r, d, N - 1)
+    b, _ = synth.signed_words(r, d, N - 1)
+    cls = (_ceil_log2(2 * d - 1) << 8) | _ceil_log2((N + 31) // 32)
+    path = tmp_path / "tune.json"
+    path.write_text('{"version": %d, "classes": {"%d": [%d, 8]}}' % (nat.zpm_version(), cls, K))
+    ctx.tune_load(str(path))
+    assert ctx.tune_table()[cls] == (K, 8)
+    print(f"[batch tile 8] K={K} pass=2^{logn} d={d} class={cls}", flush=True)
+    A, B = dev(a), dev(b)
+    got = host(ctx.mul_batch([(A, N, B, N)])[0])
+    single = host(ctx.mul(A, N, B, N, K=K))
+    assert np.array_equal(got, single), "8-column batch passes differ from the single product"
+    sampled(synth.Product(a, N, b, N), got, logn + 5)
+    del A, B
+    torch.cuda.empty_cache()
