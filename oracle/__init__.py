@@ -9,8 +9,11 @@ problem statement; Section 2, c_i = sum_{l+m=i} a_l b_m), by schoolbook:
 * ``polymul`` / ``polymul_rows``: the C schoolbook in ``schoolbook.c`` (OpenMP
   over output coefficients, 64x64->128-bit word products), reading and writing
   the fixed-width two's complement layout of Section 2.3.
-* ``pyint``: a pure-Python integer version for small cases plus an independent
-  Kronecker-substitution product used to pin the C code.
+* ``polymul_mod``: every c_i mod q (q odd, below 2^61) by the same definition
+  over Z/qZ, for checking all coefficients of products too large for the exact
+  schoolbook.
+* ``pyint``: pure-Python integer helpers (encoding, evaluation mod q) and an
+  independent Kronecker-substitution product used to pin the C code.
 
 It shares no code with the GPU path (no limbs, primes or transforms here).
 """
@@ -50,6 +53,10 @@ def _load():
             u64p, ctypes.c_int64, ctypes.c_int32, u64p, ctypes.c_int64, ctypes.c_int32,
             u64p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, ctypes.c_int]
         lib.oracle_polymul_rows.restype = ctypes.c_int
+        lib.oracle_polymul_mod.argtypes = [
+            u64p, ctypes.c_int64, ctypes.c_int32, u64p, ctypes.c_int64, ctypes.c_int32,
+            ctypes.c_uint64, u64p, ctypes.c_int]
+        lib.oracle_polymul_mod.restype = ctypes.c_int
         lib.oracle_threads.argtypes = [ctypes.c_int]
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
@@ -106,6 +113,24 @@ def polymul_rows(a, da: int, Na: int, b, db: int, Nb: int, rows, wc: int | None 
     rc = lib.oracle_polymul_rows(_ptr(A), da, Na, _ptr(B), db, Nb, _ptr(C), wc, rp, nr, nthreads)
     if rc != 0:
         raise ValueError("oracle_polymul_rows failed")
+    return C
+
+
+def polymul_mod(a, da: int, Na: int, b, db: int, Nb: int, q: int,
+                nthreads: int = 0) -> np.ndarray:
+    """c_i mod q for all da+db-1 coefficients of a*b (residues in [0, q)), by the
+    schoolbook convolution of the operands' residues; q odd, below 2^61."""
+    lib = _load()
+    wa, wb = (Na + 63) // 64, (Nb + 63) // 64
+    A = _words(a, wa)
+    B = _words(b, wb)
+    assert A.shape[0] == da and B.shape[0] == db
+    n = da + db - 1 if (da and db) else 0
+    C = np.zeros(n, dtype=np.uint64)
+    if n == 0:
+        return C
+    if lib.oracle_polymul_mod(_ptr(A), da, Na, _ptr(B), db, Nb, q, _ptr(C), nthreads) != 0:
+        raise ValueError("oracle_polymul_mod failed")
     return C
 
 

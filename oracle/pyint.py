@@ -3,8 +3,6 @@
 * ``decode`` / ``encode``: the coefficient layout of Section 2.3 (ceil(N/w)
   words per coefficient, two's complement, Relation (definingN) for the range),
   written independently of the GPU library and of ``schoolbook.c``.
-* ``schoolbook``: c_i = sum_{l+m=i} a_l b_m with Python ints (Section 1/2
-  definition of the product), for small cases only.
 * ``kronecker``: the same product by Kronecker substitution, a(2^s) * b(2^s) as
   one Python big-integer product, then unpacking signed base-2^s digits.  It is
   a different algorithm from the schoolbook (Python's big-integer multiply),
@@ -46,19 +44,6 @@ def encode(vals: Sequence[int], nwords: int) -> np.ndarray:
         for k in range(nwords):
             out[i, k] = (u >> (64 * k)) & 0xFFFFFFFFFFFFFFFF
     return out
-
-
-def schoolbook(a: Sequence[int], b: Sequence[int]) -> list[int]:
-    """c_i = sum_{l+m=i} a_l b_m."""
-    if not a or not b:
-        return []
-    c = [0] * (len(a) + len(b) - 1)
-    for l, x in enumerate(a):
-        if x == 0:
-            continue
-        for m, y in enumerate(b):
-            c[l + m] += x * y
-    return c
 
 
 def kronecker(a: Sequence[int], b: Sequence[int]) -> list[int]:

@@ -171,6 +171,63 @@ int oracle_polymul(const uint64_t *a, int64_t da, int32_t Na,
     return oracle_polymul_rows(a, da, Na, b, db, Nb, c, wc, NULL, 0, nthreads);
 }
 
+/*
+ * The same product reduced modulo q: c_i mod q = sum_{l+m=i} (a_l mod q)(b_m mod q)
+ * mod q, for every i in [0, da+db-1), written as residues in [0, q) to c[i].
+ * This is the definition of the product (Section 1, Section 2's c_i) taken in
+ * Z/qZ; it serves to check every coefficient of a product far too large for the
+ * exact schoolbook (its cost is d^2 word products instead of d^2 N^2 / 64^2).
+ * q must be odd and below 2^61, so that 32 products of residues fit in 128 bits.
+ */
+static uint64_t reduce_coeff(const uint64_t *mag, int32_t w, int neg, uint64_t q)
+{
+    u128 r = 0;
+    for (int32_t k = w - 1; k >= 0; --k) r = ((r << 64) | mag[k]) % q;
+    uint64_t v = (uint64_t)r;
+    return (neg && v) ? q - v : v;
+}
+
+int oracle_polymul_mod(const uint64_t *a, int64_t da, int32_t Na,
+                       const uint64_t *b, int64_t db, int32_t Nb,
+                       uint64_t q, uint64_t *c, int nthreads)
+{
+    if (da < 0 || db < 0 || Na < 1 || Nb < 1 || q < 3 || !(q & 1) || (q >> 61)) return -1;
+    if (da == 0 || db == 0) return 0;
+    int32_t wa = (Na + 63) / 64, wb = (Nb + 63) / 64;
+    int64_t nout = da + db - 1;
+    uint64_t *amag, *bmag;
+    unsigned char *aneg, *bneg;
+    if (prepare(a, da, Na, wa, &amag, &aneg) || prepare(b, db, Nb, wb, &bmag, &bneg)) return -1;
+    uint64_t *ar = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)da);
+    uint64_t *br = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)db);
+    if (!ar || !br) { free(ar); free(br); free(amag); free(aneg); free(bmag); free(bneg); return -1; }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t l = 0; l < da; ++l) ar[l] = reduce_coeff(amag + (size_t)l * wa, wa, aneg[l], q);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t m = 0; m < db; ++m) br[m] = reduce_coeff(bmag + (size_t)m * wb, wb, bneg[m], q);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < nout; ++i) {
+        int64_t lo = i - (db - 1) > 0 ? i - (db - 1) : 0;
+        int64_t hi = i < da - 1 ? i : da - 1;
+        u128 acc = 0;
+        int n = 0;
+        for (int64_t l = lo; l <= hi; ++l) {
+            acc += (u128)ar[l] * br[i - l];      /* each product is below 2^122 */
+            if (++n == 32) { acc %= q; n = 0; }
+        }
+        c[i] = (uint64_t)(acc % q);
+    }
+    free(ar); free(br); free(amag); free(aneg); free(bmag); free(bneg);
+    return 0;
+}
+
 /* Number of threads an OpenMP region actually gets with the given request. */
 int oracle_threads(int nthreads)
 {

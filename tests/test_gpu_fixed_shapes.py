@@ -99,8 +99,10 @@ def _ceil_log2(x):
 # for the product's size class is loaded, and the batch must give the same words as the
 # single product (16-column passes) and the oracle at sampled rows.
 @pytest.mark.parametrize("K,logn", [(16, 8), (16, 9), (8, 10)])
-def test_batch_eight_column_passes(ctx, K, logn, tmp_path):
+def test_batch_eight_column_passes(K, logn, tmp_path):
     from paper_1612_05778_amd import _native as nat
+    from paper_1612_05778_amd.api import Context
+    ctx = Context(0)    # its own context: the loaded tuning table must not leak
     logL1 = 12 - (K.bit_length() - 1)
     logL = logL1 + logn
     d = (1 << (logL - 2)) + 1
@@ -119,5 +121,6 @@ def test_batch_eight_column_passes(ctx, K, logn, tmp_path):
     single = host(ctx.mul(A, N, B, N, K=K))
     assert np.array_equal(got, single), "8-column batch passes differ from the single product"
     sampled(synth.Product(a, N, b, N), got, logn + 5)
+    ctx.close()
     del A, B
     torch.cuda.empty_cache()

@@ -10,10 +10,13 @@ The oracle cannot redo a whole 2^16 x 4096-bit product in test time, so:
   probability about (da + db) / q);
 * every coefficient satisfies |c_i| <= min(da, db) 2^(Na+Nb-2) and its words
   above Nout bits are pure sign extension;
-* where tests/golden/digests.json holds the SHA-256 of the oracle's complete output
-  for the workload (written by tests/golden/make_digests.py from the generators and
-  the oracle alone), the whole device output must have that digest: every
-  coefficient bit for bit.
+* tests/golden/digests.json (written by tests/golden/make_digests.py from the
+  generators and the oracle alone) holds, for bits4096_64k, the SHA-256 of the
+  oracle's complete output: the whole device output must have that digest, every
+  coefficient bit for bit.  For bits16384_256k it holds the SHA-256 of c_i mod q for
+  every coefficient and two primes q below 2^61 (the oracle's modular schoolbook),
+  which the device output reduced mod q must reproduce, and the digests of 256 exact
+  oracle rows, which the device's rows must reproduce.  A missing entry fails.
 """
 import hashlib
 import json
@@ -46,12 +49,17 @@ def eval_mod(vals, r, q):
 DIGESTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")
 
 
-def check_digest(name, got):
+def digest_entry(name):
     if not os.path.exists(DIGESTS):
-        return False
+        pytest.fail(f"{DIGESTS} is missing")
     ref = json.load(open(DIGESTS)).get(name)
     if ref is None:
-        return False
+        pytest.fail(f"{DIGESTS} has no entry for {name}")
+    return ref
+
+
+def check_digest(name, got):
+    ref = digest_entry(name)
     assert got.shape[1] == ref["wc"], "output width differs from the digested one"
     assert hashlib.sha256(got.tobytes()).hexdigest() == ref["sha256"], \
         f"{name}: device output differs from the oracle's full output"
@@ -59,7 +67,26 @@ def check_digest(name, got):
     return True
 
 
-def full_checks(prod, got, nsample, seed):
+def check_residues_and_rows(name, prod, got, c):
+    """Every coefficient mod two primes against the oracle's modular schoolbook, and the
+    stored exact rows, both from the digest file."""
+    ref = digest_entry(name)
+    assert got.shape[1] == ref["wc"], "output width differs from the digested one"
+    assert (ref["da"], ref["Na"], ref["db"], ref["Nb"]) == (prod.da, prod.Na, prod.db, prod.Nb)
+    for q, want in ref["residue_sha256"].items():
+        res = np.array([x % int(q) for x in c], dtype=np.uint64)
+        assert hashlib.sha256(res.tobytes()).hexdigest() == want, \
+            f"{name}: some coefficient differs from the oracle mod {q}"
+    rows = ref["rows"]
+    assert len(rows) >= 256
+    bad = [r for r, h in zip(rows, ref["row_sha256"])
+           if hashlib.sha256(got[r].tobytes()).hexdigest() != h]
+    assert not bad, f"{name}: rows {bad[:8]} differ from the stored oracle rows"
+    print(f"[fullsize] {name}: all {len(c)} coefficients match the oracle mod "
+          f"{len(ref['residue_sha256'])} primes; {len(rows)} stored oracle rows exact", flush=True)
+
+
+def full_checks(prod, got, nsample, seed, name=None):
     da, db = prod.da, prod.db
     nout = da + db - 1
     rng = np.random.default_rng(seed)
@@ -73,6 +100,8 @@ def full_checks(prod, got, nsample, seed):
     b = to_ints(prod.b)
     # inputs are sign-extended encodings, so from_bytes(signed) gives their values
     c = to_ints(got)
+    if name is not None:
+        check_residues_and_rows(name, prod, got, c)
     bound = min(da, db) << (prod.Na + prod.Nb - 2)
     nb = oracle.out_bits(da, prod.Na, db, prod.Nb)
     assert all(-bound <= x <= bound for x in c)
@@ -100,7 +129,7 @@ def test_bits4096_64k(ctx):
     torch.cuda.synchronize()
     got = host(out)
     del out
-    check_digest("bits4096_64k", got)
+    assert check_digest("bits4096_64k", got)
     full_checks(prod, got, 40, 7)
 
 
@@ -112,4 +141,4 @@ def test_bits16384_256k(ctx):
     got = host(out)
     del out
     torch.cuda.empty_cache()
-    full_checks(prod, got, 8, 8)
+    full_checks(prod, got, 8, 8, name="bits16384_256k")

@@ -207,3 +207,68 @@ def test_stored_digest_matches_oracle():
     p = synth.int64_1k(1)
     c = oracle.polymul(p.a, p.da, p.Na, p.b, p.db, p.Nb, wc=ref["wc"])
     assert hashlib.sha256(c.tobytes()).hexdigest() == ref["sha256"]
+
+
+# ---- the residue oracle (every c_i mod q, for products too large for the exact one) ----
+QS = [2305843009213693951, 2305843009213693921]   # primes below 2^61
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_polymul_mod_against_exact(seed):
+    """Residues equal the exact product reduced mod q (the exact oracle is pinned above),
+    over ragged sizes, edge widths, negative values and bits above N."""
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(12):
+        da, db = int(rng.integers(1, 90)), int(rng.integers(1, 90))
+        Na = int(rng.choice([1, 2, 63, 64, 65, 130, 1000, int(rng.integers(1, 700))]))
+        Nb = int(rng.choice([1, 3, 64, 129, 257, int(rng.integers(1, 700))]))
+        a = rng.integers(0, 2**64, size=(da, (Na + 63) // 64), dtype=np.uint64)
+        b = rng.integers(0, 2**64, size=(db, (Nb + 63) // 64), dtype=np.uint64)
+        C = oracle.polymul(a, da, Na, b, db, Nb)
+        c = pyint.decode(C, 64 * C.shape[1])
+        for q in QS + [3, 1000003]:
+            got = oracle.polymul_mod(a, da, Na, b, db, Nb, q)
+            assert got.tolist() == [x % q for x in c]
+
+
+def test_polymul_mod_closed_forms():
+    # (y+1)^n squared: binomials C(2n, i) mod q, with n past the 32-term reduction period
+    n = 700
+    row = [math.comb(n, i) for i in range(n + 1)]
+    N = max(x.bit_length() for x in row) + 1
+    A = pyint.encode(row, (N + 63) // 64)
+    for q in QS:
+        got = oracle.polymul_mod(A, n + 1, N, A, n + 1, N, q)
+        assert got.tolist() == [math.comb(2 * n, i) % q for i in range(2 * n + 1)]
+    # extreme constants: all -2^(N-1) gives c_i = t_i 2^(2N-2); 2^(N-1)-1 against -1
+    da, db, N = 300, 170, 4097
+    t = [min(i + 1, da + db - 1 - i, da, db) for i in range(da + db - 1)]
+    lo = pyint.encode([-(1 << (N - 1))] * da, 65)
+    lo_b = pyint.encode([-(1 << (N - 1))] * db, 65)
+    hi = pyint.encode([(1 << (N - 1)) - 1] * da, 65)
+    m1 = pyint.encode([-1] * db, 65)
+    for q in QS:
+        assert oracle.polymul_mod(lo, da, N, lo_b, db, N, q).tolist() == \
+            [(ti << (2 * N - 2)) % q for ti in t]
+        assert oracle.polymul_mod(hi, da, N, m1, db, N, q).tolist() == \
+            [(-ti * ((1 << (N - 1)) - 1)) % q for ti in t]
+
+
+def test_polymul_mod_evaluation_and_planted():
+    """sum_i c_i r^i = a(r) b(r) mod q on a mid-size product; a changed residue, a
+    shifted index or a dropped term fails it."""
+    prod = synth.dense(21, 3000, 2000)
+    a = pyint.decode(prod.a, prod.Na)
+    b = pyint.decode(prod.b, prod.Nb)
+    rng = random.Random(3)
+    for q in QS:
+        c = oracle.polymul_mod(prod.a, prod.da, prod.Na, prod.b, prod.db, prod.Nb, q).tolist()
+        r = rng.randrange(2, q - 1)
+        lhs = pyint.eval_mod(a, r, q) * pyint.eval_mod(b, r, q) % q
+        assert pyint.eval_mod(c, r, q) == lhs
+        bad = [list(c) for _ in range(3)]
+        bad[0][1234] = (bad[0][1234] + 1) % q
+        bad[1] = c[1:] + [0]
+        bad[2][2999] = (bad[2][2999] - a[2999] * b[0]) % q
+        for x in bad:
+            assert pyint.eval_mod(x, r, q) != lhs
