@@ -42,7 +42,11 @@ extern "C" {
 #define ZPM_EINVAL (-1)      /* bad argument (null pointer, size, output width) */
 #define ZPM_ENOMEM (-2)      /* device allocation failed; the context stays usable */
 #define ZPM_EDEVICE (-3)     /* HIP runtime or kernel error */
+#define ZPM_ERANGE (-4)      /* checked-input mode: an input coefficient has bits at or above
+                                N that are not copies of bit N-1, i.e. it is outside the range
+                                -2^(N-1) <= a_i <= 2^(N-1) - 1 of Relation (definingN) */
 #define ZPM_EUNSUPPORTED (-5) /* sizes beyond what the prime table supports */
+#define ZPM_ENOTIMPL (-6)    /* a valid request for a feature this library does not provide */
 #define ZPM_EBUSY (-7)       /* server: no capacity for the request right now */
 #define ZPM_ENOTFOUND (-8)   /* server: unknown ticket */
 
@@ -91,9 +95,48 @@ int zpm_prime(int32_t k, uint32_t *p, uint32_t *root);
 int zpm_device_limits(int device, int32_t *ncu, int64_t *lds_per_block, int64_t *lds_per_cu);
 
 /* Create a context on HIP device `device`.  Tables and workspace are allocated
- * on first use and grown as needed. */
+ * on first use and grown as needed (growth waits for the device to be idle), until
+ * zpm_reserve fixes them.  The environment variable ZPM_CHECK_INPUTS=1 turns the
+ * checked-input mode (zpm_set_option) on for every context created afterwards. */
 int zpm_create(zpm_ctx **out, int device);
 void zpm_destroy(zpm_ctx *ctx);
+
+/* Pre-size a context so that later products allocate nothing and never wait for
+ * the device (the plan's resources of Section 2.3: DetermineBase / RecoveryPrime's
+ * prime tables and the workspace of the two-dimensional transforms of Section 2.1).
+ *   workspace_bytes  the residue workspace: at least zpm_plan_info.workspace_bytes
+ *                    of the largest product to come (0 keeps the current one);
+ *   max_len          the largest da + db - 1 to come: twiddle tables of every prime
+ *                    of the table are built for transforms of that length
+ *                    (48 primes x 16 bytes x the next power of two; 100 MB for 2^17);
+ *   max_bits         the largest Na or Nb to come (tables of 2^(32 t) mod p);
+ *   max_plans        distinct plans (prime count, K, M, L) whose constants are kept,
+ *                    about 11 KB of device memory each (0 = 256).
+ * Waits for the device, allocates, and returns ZPM_ENOMEM if that fails.  From then
+ * on zpm_mul, zpm_mul_ex and zpm_mul_operand call no hipMalloc, hipFree,
+ * hipDeviceSynchronize or synchronous copy: a new plan's constants go to a reserved
+ * slot by an asynchronous copy on the call's stream.  A product that needs more than
+ * was reserved (a larger workspace or table, a plan slot beyond max_plans, or a
+ * Kronecker-reshaped product whose buffer is not yet large enough) returns ZPM_ENOMEM
+ * before anything is enqueued; calling zpm_reserve again with larger sizes grows the
+ * reservation.  Batches, servers and the 64-bit prime variant keep their own buffers
+ * and are not covered. */
+int zpm_reserve(zpm_ctx *ctx, size_t workspace_bytes, int64_t max_len, int32_t max_bits,
+                int32_t max_plans);
+
+/* Context options.
+ *   ZPM_OPT_CHECK_INPUTS: 1 = checked-input mode.  Every product call (zpm_mul,
+ *     zpm_mul_ex, zpm_mul_kronecker, zpm_mul_p64, zpm_mul_batch, zpm_mul_batch_ex,
+ *     zpm_operand_create, zpm_mul_operand) first checks on its stream that in every
+ *     input coefficient the bits from N up to the end of its top word are copies of
+ *     bit N-1 (the coefficient lies in the range of Relation (definingN) as the caller
+ *     declared it), waits for that check, and returns ZPM_ERANGE without enqueuing the
+ *     product (c untouched) when one is not.  The call then blocks on its stream.
+ *     0 (default) = bits at and above N are ignored and the value is sign-extended
+ *     from bit N-1.  Servers do not check their requests.
+ * ZPM_EINVAL for an unknown option or value. */
+#define ZPM_OPT_CHECK_INPUTS 1
+int zpm_set_option(zpm_ctx *ctx, int32_t option, int64_t value);
 
 /* c = a * b (the algorithm of Section 2.3).  `stream` is a hipStream_t (NULL =
  * default stream).  da or db == 0 gives an empty product (nothing written).
@@ -125,7 +168,7 @@ int zpm_mul_ex(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const ui
  * like zpm_mul.  ZPM_BATCH_GRAPH captures the whole sequence (descriptor upload and
  * launches) in a HIP graph and replays it when the same job array is passed again.
  * ZPM_BATCH_PERSISTENT (all levels in one persistent launch) is not available:
- * the call returns ZPM_EUNSUPPORTED. */
+ * the call returns ZPM_ENOTIMPL. */
 typedef struct zpm_job {
   const uint64_t *a;
   int64_t da;

@@ -31,7 +31,9 @@ ZPM_OK = 0
 ZPM_EINVAL = -1
 ZPM_ENOMEM = -2
 ZPM_EDEVICE = -3
+ZPM_ERANGE = -4
 ZPM_EUNSUPPORTED = -5
+ZPM_ENOTIMPL = -6
 ZPM_EBUSY = -7
 ZPM_ENOTFOUND = -8
 
@@ -74,6 +76,9 @@ zpm_mul_ex = _sig("zpm_mul_ex", ctypes.c_int,
                   [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32,
                    c_i32, c_i32, c_i32, c_vp, c_vp])
 zpm_sync = _sig("zpm_sync", ctypes.c_int, [c_vp, c_vp])
+zpm_reserve = _sig("zpm_reserve", ctypes.c_int, [c_vp, ctypes.c_size_t, c_i64, c_i32, c_i32])
+ZPM_OPT_CHECK_INPUTS = 1
+zpm_set_option = _sig("zpm_set_option", ctypes.c_int, [c_vp, c_i32, c_i64])
 
 
 class Job(ctypes.Structure):
@@ -196,7 +201,8 @@ zpm_mul_p64 = _sig("zpm_mul_p64", ctypes.c_int,
                    [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp])
 
 EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
-           "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync",
+           "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync", "zpm_reserve",
+           "zpm_set_option",
            "zpm_profile_begin", "zpm_profile_begin_kinds", "zpm_profile_end", "zpm_mul_batch", "zpm_mul_batch_ex",
            "zpm_device_limits", "zpm_batch_schedule", "zpm_tune", "zpm_tune_load",
            "zpm_tune_get", "zpm_server_create", "zpm_server_create_ex",

@@ -132,6 +132,18 @@ class Context:
     def handle(self):
         return self._h
 
+    def reserve(self, workspace_bytes: int, max_len: int, max_bits: int, max_plans: int = 0) -> None:
+        """Fix tables, workspace and plan slots (zpm_reserve): later products of at most
+        these sizes allocate nothing and never wait for the device."""
+        nat.check(nat.zpm_reserve(self._h, workspace_bytes, max_len, max_bits, max_plans),
+                  "zpm_reserve")
+
+    def set_check_inputs(self, on: bool) -> None:
+        """Checked-input mode (ZPM_OPT_CHECK_INPUTS): products fail with ZPM_ERANGE when an
+        input coefficient has bits at or above N that are not sign copies."""
+        nat.check(nat.zpm_set_option(self._h, nat.ZPM_OPT_CHECK_INPUTS, 1 if on else 0),
+                  "zpm_set_option")
+
     def mul(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int, wc: int | None = None,
             out: torch.Tensor | None = None, stream=None, K: int = 0, np: int = 0) -> torch.Tensor:
         """Exact product: (da+db-1, wc) int64 tensor of two's complement words."""
@@ -206,7 +218,8 @@ class Context:
 
         items: list of (a, Na, b, Nb) with a, b int64 CUDA tensors as for mul.
         Returns the list of output tensors (allocated unless ``outs`` is given).
-        The Job array is kept on the context so that a graph replay sees the same bytes.
+        The library copies the Job array during the call; the last one is kept on the
+        context only for inspection.
         """
         n = len(items)
         jobs = (nat.Job * max(n, 1))()
@@ -224,7 +237,7 @@ class Context:
             jobs[i].a, jobs[i].da, jobs[i].Na = a.data_ptr(), da, Na
             jobs[i].b, jobs[i].db, jobs[i].Nb = b.data_ptr(), db, Nb
             jobs[i].c, jobs[i].wc = (o.data_ptr() if nout else None), wc
-        self._jobs = jobs
+        self._batch_jobs = jobs
         flags = nat.ZPM_BATCH_GRAPH if graph else 0
         st = _stream_handle(stream)
         if K:

@@ -324,15 +324,25 @@ int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_forc
   int rc;
   const bool graph = (flags & ZPM_BATCH_GRAPH) != 0;
   BatchState &bs = graph ? batch_graph : batch_eager;
+  if (!bs.upload_done && hipEventCreateWithFlags(&bs.upload_done, hipEventDisableTiming) != hipSuccess)
+    return ZPM_EDEVICE;
   if (graph) {
+    // every launch of the graph is followed by upload_done on the caller's stream: the
+    // graph reads the pinned descriptors (its copy nodes), the device descriptors and
+    // the workspace until then, so none of them is rewritten, freed or destroyed before
     const uint64_t h = BatchState::hash(jobs, n, K_force, T_force);
     if (bs.exec && bs.key == h) {
       prof.begin(KK_BATCH, st);
       const hipError_t e = hipGraphLaunch(bs.exec, st);
       prof.end(st);
-      return e == hipSuccess ? ZPM_OK : ZPM_EDEVICE;
+      if (e != hipSuccess || hipEventRecord(bs.upload_done, st) != hipSuccess) return ZPM_EDEVICE;
+      return ZPM_OK;
     }
-    if (bs.exec) { (void)hipGraphExecDestroy(bs.exec); bs.exec = nullptr; }
+    if (bs.exec) {
+      if (hipEventSynchronize(bs.upload_done) != hipSuccess) return ZPM_EDEVICE;
+      (void)hipGraphExecDestroy(bs.exec);
+      bs.exec = nullptr;
+    }
     if ((rc = build_batch(jobs, n, K_force, bs, nullptr, nullptr, 0, T_force)) != ZPM_OK) return rc;
     if (bs.host.groups.empty()) return ZPM_OK;
     // capture on a stream of our own (the caller's may be the legacy default stream,
@@ -362,14 +372,14 @@ int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_forc
     prof.begin(KK_BATCH, st);
     const hipError_t e = hipGraphLaunch(bs.exec, st);
     prof.end(st);
-    return e == hipSuccess ? ZPM_OK : ZPM_EDEVICE;
+    if (e != hipSuccess || hipEventRecord(bs.upload_done, st) != hipSuccess) return ZPM_EDEVICE;
+    return ZPM_OK;
   }
   if ((rc = build_batch(jobs, n, K_force, bs, nullptr, nullptr, 0, T_force)) != ZPM_OK) return rc;
-  if ((rc = enqueue_batch(bs, st)) != ZPM_OK) return rc;
-  if (!bs.upload_done && hipEventCreateWithFlags(&bs.upload_done, hipEventDisableTiming) != hipSuccess)
-    return ZPM_EDEVICE;
-  (void)hipEventRecord(bs.upload_done, st);
-  return ZPM_OK;
+  rc = enqueue_batch(bs, st);
+  // recorded even after a failed enqueue: what was enqueued may still read the buffers
+  if (hipEventRecord(bs.upload_done, st) != hipSuccess && rc == ZPM_OK) rc = ZPM_EDEVICE;
+  return rc;
 }
 
 int Ctx::reserve_batch(BatchState &bs, int64_t jobs, int64_t segs) {
@@ -420,10 +430,19 @@ extern "C" int zpm_mul_batch(zpm_ctx *ctx, const zpm_job *jobs, int64_t n, int32
 extern "C" int zpm_mul_batch_ex(zpm_ctx *ctx, const zpm_job *jobs, int64_t n, int32_t flags,
                                 int32_t K, void *stream) {
   if (!ctx || n < 0 || (n > 0 && !jobs) || K < 0) return ZPM_EINVAL;
-  if (flags & ZPM_BATCH_PERSISTENT) return ZPM_EUNSUPPORTED;
+  if (flags & ZPM_BATCH_PERSISTENT) return ZPM_ENOTIMPL;
   if (flags & ~ZPM_BATCH_GRAPH) return ZPM_EINVAL;
   zpm::Ctx *cx = reinterpret_cast<zpm::Ctx *>(ctx);
   std::lock_guard<std::mutex> lock(cx->mu);
   if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
-  return cx->mul_batch(jobs, n, flags, K, reinterpret_cast<hipStream_t>(stream));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (int64_t i = 0; cx->check_inputs && i < n; ++i) {
+    const zpm_job &j = jobs[i];
+    if (j.da <= 0 || j.db <= 0) continue;
+    if (!j.a || !j.b || j.Na < 1 || j.Nb < 1) return ZPM_EINVAL;
+    int rc = cx->check_range(j.a, j.da, j.Na, st);
+    if (rc == ZPM_OK) rc = cx->check_range(j.b, j.db, j.Nb, st);
+    if (rc != ZPM_OK) return rc;
+  }
+  return cx->mul_batch(jobs, n, flags, K, st);
 }

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -36,6 +37,7 @@ int Ctx::ensure_tables(int np, int64_t H, int64_t TP) {
   H = std::max<int64_t>(H, 2);
   TP = std::max<int64_t>(TP, 64);
   if (np <= np_built && H <= H_built && TP <= TP_built) return ZPM_OK;
+  if (reserved) return ZPM_ENOMEM;   // beyond the reservation: no reallocation
   const int np2 = std::max(np, np_built);
   const int64_t H2 = std::max(H, H_built);
   const int64_t TP2 = std::max(TP, TP_built);
@@ -84,7 +86,7 @@ int Ctx::ensure_tables(int np, int64_t H, int64_t TP) {
   return ZPM_OK;
 }
 
-int Ctx::plan_consts(const Plan &pl, PlanDev **out) {
+int Ctx::plan_consts(const Plan &pl, PlanDev **out, hipStream_t st) {
   auto key = std::make_tuple(pl.np, pl.K, pl.M, pl.logL);
   auto it = consts.find(key);
   if (it != consts.end()) { *out = it->second; return ZPM_OK; }
@@ -92,6 +94,20 @@ int Ctx::plan_consts(const Plan &pl, PlanDev **out) {
   std::memset(&h, 0, sizeof(h));
   crt_constants(pl.np, h);
   scale_constants(pl.np, pl.K, pl.M, pl.logL, h);
+  if (reserved) {
+    // a reserved slot: its pinned copy is written once and uploaded on the caller's
+    // stream, ahead of the kernels that read it
+    if (pool_used >= pool_cap) return ZPM_ENOMEM;
+    const int slot = pool_used;
+    pool_h[slot] = h;
+    if (hipMemcpyAsync(pool_d + slot, pool_h + slot, sizeof(PlanDev), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return ZPM_EDEVICE;
+    ++pool_used;
+    consts[key] = pool_d + slot;
+    *out = pool_d + slot;
+    return ZPM_OK;
+  }
   PlanDev *d = nullptr;
   if (hipMalloc(&d, sizeof(PlanDev)) != hipSuccess) return ZPM_ENOMEM;
   if (hipMemcpy(d, &h, sizeof(PlanDev), hipMemcpyHostToDevice) != hipSuccess) {
@@ -99,12 +115,14 @@ int Ctx::plan_consts(const Plan &pl, PlanDev **out) {
     return ZPM_EDEVICE;
   }
   consts[key] = d;
+  consts_owned.push_back(d);
   *out = d;
   return ZPM_OK;
 }
 
 int Ctx::ensure_ws(int64_t words) {
   if (words <= ws_words) return ZPM_OK;
+  if (reserved) return ZPM_ENOMEM;
   if (hipDeviceSynchronize() != hipSuccess) return ZPM_EDEVICE;
   if (ws) (void)hipFree(ws);
   ws = nullptr;
@@ -128,17 +146,61 @@ int Ctx::get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int
   return ZPM_OK;
 }
 
-int Ctx::prepare(const Plan &pl, DevState *ds) {
+int Ctx::prepare(const Plan &pl, DevState *ds, hipStream_t st) {
   int rc;
   const int64_t H = std::max<int64_t>((int64_t)1 << pl.logL, 2 * (int64_t)pl.K);
   if ((rc = ensure_tables(pl.np, H, (pl.M + 31) / 32 + 1)) != ZPM_OK) return rc;
   PlanDev *pd = nullptr;
-  if ((rc = plan_consts(pl, &pd)) != ZPM_OK) return rc;
+  if ((rc = plan_consts(pl, &pd, st)) != ZPM_OK) return rc;
   if ((rc = ensure_ws(pl.ws_words)) != ZPM_OK) return rc;
   ds->X = ws;
   ds->primes = primes;
   ds->plan = pd;
   return ZPM_OK;
+}
+
+int Ctx::reserve(size_t ws_bytes, int64_t max_len, int32_t max_bits, int32_t max_plans) {
+  int rc;
+  if (hipDeviceSynchronize() != hipSuccess) return ZPM_EDEVICE;
+  reserved = false;   // growth below is allowed
+  // twiddle heaps of every prime for transforms up to the next power of two of max_len
+  // and for every 2K-point x-transform (K <= 2 max_bits, K <= 1024), and the 2^(32 t)
+  // tables for limbs of up to max_bits / 2 bits
+  int64_t H = 2;
+  while (H < max_len) H <<= 1;
+  int64_t twoK = 4;
+  while (twoK < 4 * (int64_t)max_bits && twoK < 2048) twoK <<= 1;
+  H = std::max(H, twoK);
+  const int64_t TP = ((int64_t)max_bits / 2 + 1 + 31) / 32 + 2;
+  if ((rc = ensure_tables(MAXNP, H, TP)) != ZPM_OK) return rc;
+  if ((rc = ensure_ws((int64_t)((ws_bytes + 3) / 4))) != ZPM_OK) return rc;
+  const int cap = max_plans > 0 ? max_plans : 256;
+  if (cap > pool_cap - pool_used) {
+    // a new pool; slots handed out earlier stay where they are (kept until destruction)
+    PlanDev *d = nullptr, *h = nullptr;
+    if (hipMalloc(&d, sizeof(PlanDev) * (size_t)cap) != hipSuccess) return ZPM_ENOMEM;
+    if (hipHostMalloc(&h, sizeof(PlanDev) * (size_t)cap, hipHostMallocDefault) != hipSuccess) {
+      (void)hipFree(d);
+      return ZPM_ENOMEM;
+    }
+    if (pool_d) pool_old.emplace_back(pool_d, pool_h);
+    pool_d = d;
+    pool_h = h;
+    pool_cap = cap;
+    pool_used = 0;
+  }
+  reserved = true;
+  return ZPM_OK;
+}
+
+int Ctx::check_range(const uint64_t *src, int64_t d, int32_t N, hipStream_t st) {
+  if (!check_inputs || d <= 0 || ((N - 1) & 63) == 63) return ZPM_OK;
+  if (hipMemsetAsync(flag_d, 0, sizeof(uint32_t), st) != hipSuccess) return ZPM_EDEVICE;
+  if (launch_check_range(src, d, N, flag_d, st) != hipSuccess) return ZPM_EDEVICE;
+  if (hipMemcpyAsync(flag_h, flag_d, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return ZPM_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return ZPM_EDEVICE;
+  return *flag_h ? ZPM_ERANGE : ZPM_OK;
 }
 
 Ctx::~Ctx() {
@@ -153,7 +215,14 @@ Ctx::~Ctx() {
   if (kbuf) (void)hipFree(kbuf);
   if (heaps) (void)hipFree(heaps);
   if (primes) (void)hipFree(primes);
-  for (auto &kv : consts) (void)hipFree(kv.second);
+  for (PlanDev *d : consts_owned) (void)hipFree(d);
+  pool_old.emplace_back(pool_d, pool_h);
+  for (auto &ph : pool_old) {
+    if (ph.first) (void)hipFree(ph.first);
+    if (ph.second) (void)hipHostFree(ph.second);
+  }
+  if (flag_d) (void)hipFree(flag_d);
+  if (flag_h) (void)hipHostFree(flag_h);
 }
 
 }  // namespace zpm
@@ -168,7 +237,9 @@ const char *zpm_strerror(int err) {
     case ZPM_EINVAL: return "invalid argument";
     case ZPM_ENOMEM: return "device allocation failed";
     case ZPM_EDEVICE: return "HIP device or runtime error";
+    case ZPM_ERANGE: return "input coefficient outside the declared N-bit range";
     case ZPM_EUNSUPPORTED: return "sizes not supported by the prime table";
+    case ZPM_ENOTIMPL: return "not implemented by this library";
     case ZPM_EBUSY: return "no capacity right now";
     case ZPM_ENOTFOUND: return "unknown ticket";
     default: return "unknown error";
@@ -226,11 +297,41 @@ int zpm_create(zpm_ctx **out, int device) {
   c->device = device;
   if (prime_table().size() < (size_t)MAXNP) { delete c; return ZPM_EUNSUPPORTED; }
   if (hipMalloc(&c->primes, sizeof(PrimeDev) * MAXNP) != hipSuccess) { delete c; return ZPM_ENOMEM; }
+  if (hipMalloc(&c->flag_d, sizeof(uint32_t)) != hipSuccess ||
+      hipHostMalloc(&c->flag_h, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return ZPM_ENOMEM;
+  }
+  const char *chk = std::getenv("ZPM_CHECK_INPUTS");
+  c->check_inputs = (chk && chk[0] == '1') ? 1 : 0;
   *out = reinterpret_cast<zpm_ctx *>(c);
   return ZPM_OK;
 }
 
 void zpm_destroy(zpm_ctx *ctx) { delete reinterpret_cast<Ctx *>(ctx); }
+
+int zpm_reserve(zpm_ctx *ctx, size_t workspace_bytes, int64_t max_len, int32_t max_bits,
+                int32_t max_plans) {
+  if (!ctx || max_len < 1 || max_bits < 1 || max_plans < 0) return ZPM_EINVAL;
+  if (max_len > ((int64_t)1 << LOG2_ROOT_ORDER)) return ZPM_EUNSUPPORTED;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  std::lock_guard<std::mutex> lock(cx->mu);
+  if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  return cx->reserve(workspace_bytes, max_len, max_bits, max_plans);
+}
+
+int zpm_set_option(zpm_ctx *ctx, int32_t option, int64_t value) {
+  if (!ctx) return ZPM_EINVAL;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  std::lock_guard<std::mutex> lock(cx->mu);
+  switch (option) {
+    case ZPM_OPT_CHECK_INPUTS:
+      if (value != 0 && value != 1) return ZPM_EINVAL;
+      cx->check_inputs = (int)value;
+      return ZPM_OK;
+    default: return ZPM_EINVAL;
+  }
+}
 
 static int check_mul_args(const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b, int64_t db,
                           int32_t Nb, uint64_t *c, int32_t wc) {
@@ -259,18 +360,20 @@ int zpm_mul_ex(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const ui
   Ctx *cx = reinterpret_cast<Ctx *>(ctx);
   std::lock_guard<std::mutex> lock(cx->mu);
   if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = cx->check_range(a, da, Na, st)) != ZPM_OK) return rc;
+  if ((rc = cx->check_range(b, db, Nb, st)) != ZPM_OK) return rc;
   Plan pl;
   if ((rc = cx->get_plan(da, Na, db, Nb, K, np, &pl)) != ZPM_OK) {
     // coefficients too wide for one product: Kronecker reshaping, when nothing is forced
     if (rc != ZPM_EUNSUPPORTED || K || np || stop_after) return rc;
-    return cx->mul_kronecker(a, da, Na, b, db, Nb, c, wc, 0, reinterpret_cast<hipStream_t>(stream));
+    return cx->mul_kronecker(a, da, Na, b, db, Nb, c, wc, 0, st);
   }
   // c = a^2 when one operand is passed twice: it is converted and transformed once
   // (stage dumps keep the documented layout with both operands' rows)
   pl.square = (a == b && da == db && Na == Nb && !stop_after) ? 1 : 0;
   DevState ds;
-  if ((rc = cx->prepare(pl, &ds)) != ZPM_OK) return rc;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = cx->prepare(pl, &ds, st)) != ZPM_OK) return rc;
   if (launch_mul(pl, ds, a, b, c, wc, stop_after, st, &cx->prof) != hipSuccess) return ZPM_EDEVICE;
   if (stop_after) {
     if (hipMemcpyAsync(ws_out, ds.X, (size_t)pl.ws_words * 4, hipMemcpyDeviceToDevice, st) !=
@@ -343,8 +446,10 @@ int zpm_mul_kronecker(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, c
   Ctx *cx = reinterpret_cast<Ctx *>(ctx);
   std::lock_guard<std::mutex> lock(cx->mu);
   if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
-  return cx->mul_kronecker(a, da, Na, b, db, Nb, c, wc, chunk_bits,
-                           reinterpret_cast<hipStream_t>(stream));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = cx->check_range(a, da, Na, st)) != ZPM_OK) return rc;
+  if ((rc = cx->check_range(b, db, Nb, st)) != ZPM_OK) return rc;
+  return cx->mul_kronecker(a, da, Na, b, db, Nb, c, wc, chunk_bits, st);
 }
 
 int zpm_kronecker_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t chunk_bits,
@@ -412,7 +517,10 @@ int zpm_mul_p64(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const u
   Ctx *cx = reinterpret_cast<Ctx *>(ctx);
   std::lock_guard<std::mutex> lock(cx->mu);
   if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
-  return mul_p64(*cx, pl, a, b, c, wc, reinterpret_cast<hipStream_t>(stream));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = cx->check_range(a, da, Na, st)) != ZPM_OK) return rc;
+  if ((rc = cx->check_range(b, db, Nb, st)) != ZPM_OK) return rc;
+  return mul_p64(*cx, pl, a, b, c, wc, st);
 }
 
 // A resident operand: b's spectra under a plan sized for products with any a of at
@@ -435,12 +543,14 @@ int zpm_operand_create(zpm_ctx *ctx, const uint64_t *b, int64_t db, int32_t Nb, 
   std::lock_guard<std::mutex> lock(cx->mu);
   if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
   int rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = cx->check_range(b, db, Nb, st)) != ZPM_OK) return rc;
   Plan pl;
   if ((rc = cx->get_plan(da_max, Na_max, db, Nb, K, 0, &pl)) != ZPM_OK) return rc;
   const int64_t H = std::max<int64_t>((int64_t)1 << pl.logL, 2 * (int64_t)pl.K);
   if ((rc = cx->ensure_tables(pl.np, H, (pl.M + 31) / 32 + 1)) != ZPM_OK) return rc;
   PlanDev *pd = nullptr;
-  if ((rc = cx->plan_consts(pl, &pd)) != ZPM_OK) return rc;
+  if ((rc = cx->plan_consts(pl, &pd, st)) != ZPM_OK) return rc;
   zpm_operand *op = new zpm_operand();
   op->cx = cx;
   op->pl = pl;
@@ -457,7 +567,6 @@ int zpm_operand_create(zpm_ctx *ctx, const uint64_t *b, int64_t db, int32_t Nb, 
   ds.X = op->spec;
   ds.primes = cx->primes;
   ds.plan = pd;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   // b's limbs into rows K..2K-1, their forward column passes, then the spectra
   bool ok = launch_convert_in(pl, ds, b, db, Nb, pl.K, st) == hipSuccess;
   for (int c = 0; ok && c < pl.ncol; ++c) ok = launch_col(pl, ds, c, false, st, pl.K, pl.K) == hipSuccess;
@@ -482,6 +591,8 @@ int zpm_mul_operand(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, con
   Ctx *cx = op->cx;
   std::lock_guard<std::mutex> lock(cx->mu);
   if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = cx->check_range(a, da, Na, st)) != ZPM_OK) return rc;
   // the operand's plan, for this a: K, M, np and L are fixed by the bounds
   Plan pl = op->pl;
   pl.da = da;
@@ -490,13 +601,12 @@ int zpm_mul_operand(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, con
   pl.nout_bits = out_bits(da, Na, op->db, op->Nb);
   pl.square = 0;
   PlanDev *pd = nullptr;
-  if ((rc = cx->plan_consts(pl, &pd)) != ZPM_OK) return rc;
+  if ((rc = cx->plan_consts(pl, &pd, st)) != ZPM_OK) return rc;
   if ((rc = cx->ensure_ws(pl.ws_words)) != ZPM_OK) return rc;
   DevState ds;
   ds.X = cx->ws;
   ds.primes = cx->primes;
   ds.plan = pd;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   bool ok = launch_convert_in(pl, ds, a, da, Na, 0, st) == hipSuccess;
   for (int k = 0; ok && k < pl.ncol; ++k) ok = launch_col(pl, ds, k, false, st, pl.K, 0) == hipSuccess;
   ok = ok && launch_convolve(pl, ds, st, CM_WITH_SPECTRUM, op->spec) == hipSuccess;

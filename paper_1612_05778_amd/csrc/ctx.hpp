@@ -77,6 +77,16 @@ struct Ctx {
   int64_t H_built = 0;
   int64_t TP_built = 0;         // entries of each prime's 2^(32 t) table
   std::map<std::tuple<int, int, int, int>, PlanDev *> consts;
+  std::vector<PlanDev *> consts_owned;          // allocated one by one (before zpm_reserve)
+  // zpm_reserve: tables, workspace and plan-constant slots are fixed; products that
+  // need more get ZPM_ENOMEM instead of a reallocation
+  bool reserved = false;
+  PlanDev *pool_d = nullptr, *pool_h = nullptr; // plan-constant slots and their pinned copies
+  int pool_cap = 0, pool_used = 0;
+  std::vector<std::pair<PlanDev *, PlanDev *>> pool_old;   // earlier, smaller pools
+  // checked-input mode (ZPM_OPT_CHECK_INPUTS)
+  int check_inputs = 0;
+  uint32_t *flag_d = nullptr, *flag_h = nullptr;
   std::map<std::tuple<int64_t, int32_t, int64_t, int32_t, int32_t, int32_t, int32_t>, Plan> plans;
   uint32_t *ws = nullptr;
   int64_t ws_words = 0;
@@ -89,13 +99,18 @@ struct Ctx {
   hipStream_t capture_stream = nullptr;        // graph capture only (default priority)
 
   int ensure_tables(int np, int64_t H, int64_t TP);
-  int plan_consts(const Plan &pl, PlanDev **out);
+  // st: stream of the call that needs the constants (a reserved slot is uploaded there)
+  int plan_consts(const Plan &pl, PlanDev **out, hipStream_t st = nullptr);
+  int reserve(size_t ws_bytes, int64_t max_len, int32_t max_bits, int32_t max_plans);
+  // checked-input mode: ZPM_ERANGE if a coefficient of src has bits >= N that are not
+  // copies of bit N-1 (waits for the check on st); ZPM_OK when the mode is off
+  int check_range(const uint64_t *src, int64_t d, int32_t N, hipStream_t st);
   int ensure_ws(int64_t words);
   int ensure_kbuf(int64_t words);
   int mul_kronecker(const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b, int64_t db,
                     int32_t Nb, uint64_t *c, int32_t wc, int32_t chunk_bits, hipStream_t st);
   int get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np, Plan *out);
-  int prepare(const Plan &pl, DevState *ds);
+  int prepare(const Plan &pl, DevState *ds, hipStream_t st = nullptr);
   int get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force,
                      int32_t T_force, Plan *out);
   // given: plans per job (from plan_for_batch) instead of the context's choice

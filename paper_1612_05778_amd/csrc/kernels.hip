@@ -103,6 +103,19 @@ __global__ __launch_bounds__(BLOCK) void k_recovering_product(
                    logTI, primes, pd, out);
 }
 
+// Range check of the inputs (checked-input mode): in the top word of each coefficient the
+// bits above bit N-1 must repeat it, i.e. -2^(N-1) <= a_i < 2^(N-1) (Relation
+// (definingN)).  One thread per coefficient; any violation sets *flag.
+__global__ __launch_bounds__(BLOCK) void k_check_range(const uint64_t *__restrict__ src, int64_t d,
+                                                       int32_t w, int32_t tb, uint32_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= d) return;
+  const uint64_t top = src[i * w + (w - 1)];
+  const int sh = 63 - tb;          // bits above bit tb of the top word
+  const uint64_t ext = (uint64_t)((int64_t)(top << sh) >> sh);
+  if (ext != top) atomicOr(flag, 1u);
+}
+
 // ------------------------------------------------------------------------------------
 // host launchers
 // ------------------------------------------------------------------------------------
@@ -249,6 +262,17 @@ hipError_t launch_recover(const Plan &pl, const DevState &ds, uint64_t *out, int
     default: return hipErrorInvalidValue;
   }
 #undef ZPM_REC
+  return hipGetLastError();
+}
+
+hipError_t launch_check_range(const uint64_t *src, int64_t d, int32_t N, uint32_t *flag,
+                              hipStream_t st) {
+  if (d <= 0) return hipSuccess;
+  const int w = (N + 63) / 64;
+  const int tb = (N - 1) & 63;
+  if (tb == 63) return hipSuccess;   // N fills the top word: nothing above bit N-1
+  const int64_t blocks = (d + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(k_check_range, dim3((unsigned)blocks), dim3(BLOCK), 0, st, src, d, w, tb, flag);
   return hipGetLastError();
 }
 

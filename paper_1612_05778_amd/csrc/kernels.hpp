@@ -40,6 +40,10 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
                            const uint32_t *spec = nullptr);
 hipError_t launch_recover(const Plan &pl, const DevState &ds, uint64_t *out, int32_t wc,
                           hipStream_t st);
+// Sets *flag to 1 if some coefficient of src (d coefficients of N bits, ceil(N/64) words
+// each) has a bit at or above N that differs from bit N-1.
+hipError_t launch_check_range(const uint64_t *src, int64_t d, int32_t N, uint32_t *flag,
+                              hipStream_t st);
 // stop_after: 0 = everything; 1..4 = stop after convert-in / forward column passes /
 // row convolutions / inverse column passes (the workspace then holds that stage).
 hipError_t launch_mul(const Plan &pl, const DevState &ds, const uint64_t *a, const uint64_t *b,

@@ -170,6 +170,7 @@ static hipError_t launch_split(const uint64_t *x, int64_t d, int32_t N, int32_t 
 
 int Ctx::ensure_kbuf(int64_t words) {
   if (words <= kbuf_words) return ZPM_OK;
+  if (reserved) return ZPM_ENOMEM;   // beyond the reservation: no reallocation
   if (hipDeviceSynchronize() != hipSuccess) return ZPM_EDEVICE;
   if (kbuf) (void)hipFree(kbuf);
   kbuf = nullptr;
@@ -192,7 +193,7 @@ int Ctx::mul_kronecker(const uint64_t *a, int64_t da, int32_t Na, const uint64_t
   Plan pl = kp.inner;
   pl.square = square ? 1 : 0;
   DevState ds;
-  if ((rc = prepare(pl, &ds)) != ZPM_OK) return rc;
+  if ((rc = prepare(pl, &ds, st)) != ZPM_OK) return rc;
   if (launch_split(a, da, Na, kp.sa, kp, ap, kp.da2, st) != hipSuccess) return ZPM_EDEVICE;
   if (!square && launch_split(b, db, Nb, kp.sb, kp, bp, kp.db2, st) != hipSuccess) return ZPM_EDEVICE;
   if (launch_mul(pl, ds, ap, bp, cpp, kp.wc2, 0, st, &prof) != hipSuccess) return ZPM_EDEVICE;

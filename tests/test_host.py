@@ -32,6 +32,20 @@ def test_exports_match_header(nat):
     assert nat.zpm_version() >= 100
 
 
+def test_error_codes_and_host_argument_checks(nat):
+    """The boundary's error codes have their own texts, and calls with a null context
+    or bad sizes are refused on the host, before any device is touched."""
+    texts = {c: nat.zpm_strerror(c).decode() for c in
+             (nat.ZPM_OK, nat.ZPM_EINVAL, nat.ZPM_ENOMEM, nat.ZPM_EDEVICE, nat.ZPM_ERANGE,
+              nat.ZPM_EUNSUPPORTED, nat.ZPM_ENOTIMPL, nat.ZPM_EBUSY, nat.ZPM_ENOTFOUND)}
+    assert len(set(texts.values())) == len(texts), texts
+    assert "range" in texts[nat.ZPM_ERANGE] and "not implemented" in texts[nat.ZPM_ENOTIMPL]
+    assert nat.zpm_reserve(None, 1 << 20, 1 << 10, 64, 0) == nat.ZPM_EINVAL
+    assert nat.zpm_set_option(None, nat.ZPM_OPT_CHECK_INPUTS, 1) == nat.ZPM_EINVAL
+    assert nat.zpm_mul(None, None, 1, 64, None, 1, 64, None, 3, None) == nat.ZPM_EINVAL
+    assert nat.zpm_mul_batch_ex(None, None, 0, 0, 0, None) == nat.ZPM_EINVAL
+
+
 def test_prime_table(nat):
     from paper_1612_05778_amd import api
     ps = []
