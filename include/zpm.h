@@ -49,6 +49,8 @@ extern "C" {
 #define ZPM_ENOTIMPL (-6)    /* a valid request for a feature this library does not provide */
 #define ZPM_EBUSY (-7)       /* server: no capacity for the request right now */
 #define ZPM_ENOTFOUND (-8)   /* server: unknown ticket */
+#define ZPM_ETOOBIG (-9)     /* zpm_mul_noalloc: the product's workspace exceeds the fixed
+                                scratch array (zpm_noalloc_max_bytes) */
 
 typedef struct zpm_ctx zpm_ctx;
 
@@ -383,6 +385,29 @@ int zpm_prime64(int32_t k, uint64_t *p, uint64_t *root);
 int zpm_mul_p64(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
                 int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t K, int32_t np,
                 void *stream);
+
+/* c = a * b without allocating (for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, encodings, ownership, result and stream rules as zpm_mul.  The
+ * residue workspace is a fixed device array of zpm_noalloc_max_bytes() bytes (64 MiB)
+ * that the library holds on every device it runs on until the process ends; its
+ * address is taken once per device by zpm_create.  The call makes no hipMalloc,
+ * hipFree, device-wide synchronization or synchronous copy.
+ *   ZPM_ETOOBIG  the plan's workspace (zpm_plan_info.workspace_bytes) exceeds the array;
+ *   ZPM_ENOMEM   the context's twiddle tables do not cover the plan, or its constants
+ *                are not resident and the context is not reserved: call zpm_reserve
+ *                (max_len, max_bits, max_plans; workspace_bytes may be 0) or run one
+ *                zpm_mul of the same sizes first;
+ *   ZPM_EUNSUPPORTED  no direct plan (no Kronecker reshaping on this path).
+ * Every such error returns before anything is enqueued, with c untouched.  All calls on
+ * one device share the one array: calls whose work overlaps on the device (other
+ * streams, other contexts, other host threads) race and give wrong results; order them
+ * on one stream.  The array keeps the last call's residues; every word a product reads
+ * is written by that product first.  The checked-input mode is not applied here (it
+ * waits for the device). */
+int64_t zpm_noalloc_max_bytes(void);
+int zpm_mul_noalloc(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
+                    int64_t db, int32_t Nb, uint64_t *c, int32_t wc, void *stream);
 
 /* Wait for the stream and report any device error raised by earlier calls. */
 int zpm_sync(zpm_ctx *ctx, void *stream);

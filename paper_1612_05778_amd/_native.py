@@ -36,6 +36,7 @@ ZPM_EUNSUPPORTED = -5
 ZPM_ENOTIMPL = -6
 ZPM_EBUSY = -7
 ZPM_ENOTFOUND = -8
+ZPM_ETOOBIG = -9
 
 
 class PlanInfo(ctypes.Structure):
@@ -200,6 +201,10 @@ zpm_prime64 = _sig("zpm_prime64", ctypes.c_int,
 zpm_mul_p64 = _sig("zpm_mul_p64", ctypes.c_int,
                    [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp])
 
+zpm_noalloc_max_bytes = _sig("zpm_noalloc_max_bytes", c_i64, [])
+zpm_mul_noalloc = _sig("zpm_mul_noalloc", ctypes.c_int,
+                       [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_vp])
+
 EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime",
            "zpm_create", "zpm_destroy", "zpm_mul", "zpm_mul_ex", "zpm_sync", "zpm_reserve",
            "zpm_set_option",
@@ -210,7 +215,8 @@ EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime
            "zpm_server_wait", "zpm_server_completions", "zpm_server_stats",
            "zpm_server_reset_stats", "zpm_server_destroy", "zpm_operand_create",
            "zpm_mul_operand", "zpm_operand_info", "zpm_operand_destroy", "zpm_mul_kronecker",
-           "zpm_kronecker_plan", "zpm_plan_p64", "zpm_prime64", "zpm_mul_p64"]
+           "zpm_kronecker_plan", "zpm_plan_p64", "zpm_prime64", "zpm_mul_p64",
+           "zpm_noalloc_max_bytes", "zpm_mul_noalloc"]
 
 
 class ZpmError(RuntimeError):

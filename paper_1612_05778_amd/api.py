@@ -166,6 +166,22 @@ class Context:
         nat.check(rc, "zpm_mul")
         return out
 
+    def mul_noalloc(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int,
+                    out: torch.Tensor, stream=None) -> torch.Tensor:
+        """c = a * b into the caller's `out` with the library's fixed scratch array as the
+        workspace (zpm_mul_noalloc): nothing is allocated.  The context's tables must cover
+        the sizes (zpm_reserve, or an earlier product of the same sizes)."""
+        da = _check_operand(a, Na, "a")
+        db = _check_operand(b, Nb, "b")
+        n = da + db - 1 if (da and db) else 0
+        if n and (out.dim() != 2 or out.shape[0] != n or out.dtype != torch.int64
+                  or not out.is_contiguous()):
+            raise ValueError("out has the wrong shape or dtype")
+        nat.check(nat.zpm_mul_noalloc(self._h, a.data_ptr(), da, Na, b.data_ptr(), db, Nb,
+                                      out.data_ptr() if n else None, out.shape[1] if n else 1,
+                                      _stream_handle(stream)), "zpm_mul_noalloc")
+        return out
+
     def mul_kronecker(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int,
                       chunk_bits: int = 0, out: torch.Tensor | None = None,
                       stream=None) -> torch.Tensor:

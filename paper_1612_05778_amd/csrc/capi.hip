@@ -242,6 +242,7 @@ const char *zpm_strerror(int err) {
     case ZPM_ENOTIMPL: return "not implemented by this library";
     case ZPM_EBUSY: return "no capacity right now";
     case ZPM_ENOTFOUND: return "unknown ticket";
+    case ZPM_ETOOBIG: return "product exceeds the fixed no-allocation scratch array";
     default: return "unknown error";
   }
 }
@@ -302,6 +303,7 @@ int zpm_create(zpm_ctx **out, int device) {
     delete c;
     return ZPM_ENOMEM;
   }
+  if (noalloc_init(device) != hipSuccess) { delete c; return ZPM_EDEVICE; }
   const char *chk = std::getenv("ZPM_CHECK_INPUTS");
   c->check_inputs = (chk && chk[0] == '1') ? 1 : 0;
   *out = reinterpret_cast<zpm_ctx *>(c);

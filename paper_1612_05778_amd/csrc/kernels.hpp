@@ -50,4 +50,8 @@ hipError_t launch_mul(const Plan &pl, const DevState &ds, const uint64_t *a, con
                       uint64_t *c, int32_t wc, int stop_after, hipStream_t st,
                       Profiler *prof = nullptr);
 
+// Looks up the device address of the no-allocation scratch array on `device` (the
+// current device), once per device.
+hipError_t noalloc_init(int device);
+
 }  // namespace zpm
