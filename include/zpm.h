@@ -226,7 +226,8 @@ int zpm_profile_begin(zpm_ctx *ctx);
  * bracketed (each pair of events adds a few microseconds between kernels).  Kinds:
  * 0 bivariate_representation, 1 col_pass_fwd, 2 convolve_rows, 3 col_pass_inv,
  * 4 recovering_product, 5 batch, 6 p64_convert_in, 7 p64_y_fwd, 8 p64_x_convolve,
- * 9 p64_y_inv, 10 p64_recover. */
+ * 9 p64_y_inv, 10 p64_recover, 11 gfp_convert_in, 12 gfp_y_fwd, 13 gfp_x_convolve,
+ * 14 gfp_y_inv, 15 gfp_recover. */
 int zpm_profile_begin_kinds(zpm_ctx *ctx, uint32_t kinds);
 int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t *n_out);
 
@@ -384,6 +385,51 @@ int zpm_prime64(int32_t k, uint64_t *p, uint64_t *root);
  * keeps this variant's tables and workspace apart from zpm_mul's. */
 int zpm_mul_p64(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
                 int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t K, int32_t np,
+                void *stream);
+
+/* One big generalized Fermat prime (Section 3.1: a single prime p = r^k + 1 in place of
+ * several machine-word primes and CRT, Relation (FurerHypothesis) and the table of
+ * generalized Fermat primes; Section 5).  Same method and result as zpm_mul: K limbs of
+ * M bits, the 2K x L two-dimensional convolution over Z/pZ, the lift of each c_{i,j}
+ * into (-p/2, p/2) and evaluation at 2^M with carries (Section 2.2).  An element of Z/pZ
+ * is k digits in radix r; r is a primitive 2k-th root of unity, so the x-transforms
+ * (K <= k, root theta = r^(k/K)) and the y-transform passes of up to 2k points multiply
+ * only by powers of r, which are digit rotations.  The primes (k, r, bits of p):
+ *   k = 8:  r = 2^29 - 2^25,        232 bits
+ *   k = 16: r = 2^29 - 2^9 - 2^7,   464 bits
+ *   k = 32: r = 2^29 - 2^14 - 2^13, 928 bits
+ * and the plan needs p > 4 max(da, db) K 2^(2M) (Relation (recoveryModulo)), so
+ * M <= about (log2 p - log2(4 d K)) / 2; larger coefficients return ZPM_EUNSUPPORTED.
+ * da + db - 1 <= 2^21. */
+typedef struct zpm_gfp_info {
+  int64_t da, db;
+  int32_t Na, Nb;
+  int32_t k;              /* digits of the prime */
+  int32_t r;              /* its radix */
+  int32_t K, M;
+  int32_t log2_L;
+  int32_t npass;          /* y-transform passes */
+  int32_t pass_log2n[6];  /* their lengths, outermost first */
+  int32_t log2p;
+  int32_t nout_bits;
+  int64_t workspace_bytes;  /* 2K L k 32-bit digits */
+} zpm_gfp_info;
+
+/* Host only.  The radix and the bit length of the prime with k digits (8, 16 or 32);
+ * ZPM_EINVAL for another k. */
+int zpm_gfp_prime(int32_t k, int32_t *r, int32_t *log2p);
+/* Host only.  The root of unity of order L = 2^log2_L that the y-transforms use with
+ * the prime of k digits, as k balanced digits (value sum digits[l] r^l mod p).  It
+ * satisfies omega^(L/2k) = r for L >= 2k, and omega = r^(2k/L) for smaller L. */
+int zpm_gfp_root(int32_t k, int32_t log2_L, int32_t *digits);
+/* Planner (host only).  K, k: 0 = choose (by a work model), otherwise forced. */
+int zpm_plan_gfp(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t k,
+                 zpm_gfp_info *out);
+/* c = a * b with one generalized Fermat prime; arguments, encodings, ownership, errors
+ * and stream rules as for zpm_mul (a square when b is a); K, k as in zpm_plan_gfp.  The
+ * context keeps this variant's twiddle tables and workspace apart from zpm_mul's. */
+int zpm_mul_gfp(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
+                int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t K, int32_t k,
                 void *stream);
 
 /* c = a * b without allocating (for callers that cannot allocate device memory: code

@@ -201,6 +201,26 @@ zpm_prime64 = _sig("zpm_prime64", ctypes.c_int,
 zpm_mul_p64 = _sig("zpm_mul_p64", ctypes.c_int,
                    [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp])
 
+class GfpInfo(ctypes.Structure):
+    _fields_ = [("da", c_i64), ("db", c_i64), ("Na", c_i32), ("Nb", c_i32), ("k", c_i32),
+                ("r", c_i32), ("K", c_i32), ("M", c_i32), ("log2_L", c_i32), ("npass", c_i32),
+                ("pass_log2n", c_i32 * 6), ("log2p", c_i32), ("nout_bits", c_i32),
+                ("workspace_bytes", c_i64)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["pass_log2n"] = list(self.pass_log2n)[: self.npass]
+        return d
+
+
+zpm_gfp_prime = _sig("zpm_gfp_prime", ctypes.c_int,
+                     [c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)])
+zpm_gfp_root = _sig("zpm_gfp_root", ctypes.c_int, [c_i32, c_i32, ctypes.POINTER(c_i32)])
+zpm_plan_gfp = _sig("zpm_plan_gfp", ctypes.c_int,
+                    [c_i64, c_i32, c_i64, c_i32, c_i32, c_i32, ctypes.POINTER(GfpInfo)])
+zpm_mul_gfp = _sig("zpm_mul_gfp", ctypes.c_int,
+                   [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp])
+
 zpm_noalloc_max_bytes = _sig("zpm_noalloc_max_bytes", c_i64, [])
 zpm_mul_noalloc = _sig("zpm_mul_noalloc", ctypes.c_int,
                        [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_vp])
@@ -216,7 +236,8 @@ EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime
            "zpm_server_reset_stats", "zpm_server_destroy", "zpm_operand_create",
            "zpm_mul_operand", "zpm_operand_info", "zpm_operand_destroy", "zpm_mul_kronecker",
            "zpm_kronecker_plan", "zpm_plan_p64", "zpm_prime64", "zpm_mul_p64",
-           "zpm_noalloc_max_bytes", "zpm_mul_noalloc"]
+           "zpm_noalloc_max_bytes", "zpm_mul_noalloc", "zpm_gfp_prime", "zpm_gfp_root",
+           "zpm_plan_gfp", "zpm_mul_gfp"]
 
 
 class ZpmError(RuntimeError):

@@ -46,6 +46,27 @@ def plan_p64(da: int, Na: int, db: int, Nb: int, K: int = 0, np: int = 0) -> dic
     return info.as_dict()
 
 
+def plan_gfp(da: int, Na: int, db: int, Nb: int, K: int = 0, k: int = 0) -> dict:
+    """Plan of the generalized Fermat prime variant (host only); K, k: 0 = choose."""
+    info = nat.GfpInfo()
+    nat.check(nat.zpm_plan_gfp(da, Na, db, Nb, K, k, ctypes.byref(info)), "zpm_plan_gfp")
+    return info.as_dict()
+
+
+def gfp_prime(k: int) -> tuple[int, int]:
+    """Radix r and bit length of the generalized Fermat prime r^k + 1 of k digits."""
+    r, lp = ctypes.c_int32(), ctypes.c_int32()
+    nat.check(nat.zpm_gfp_prime(k, ctypes.byref(r), ctypes.byref(lp)), "zpm_gfp_prime")
+    return r.value, lp.value
+
+
+def gfp_root(k: int, log2_L: int) -> list[int]:
+    """Balanced radix-r digits of the order-2^log2_L root the y-transforms use."""
+    buf = (ctypes.c_int32 * k)()
+    nat.check(nat.zpm_gfp_root(k, log2_L, buf), "zpm_gfp_root")
+    return list(buf)
+
+
 def prime64(k: int) -> tuple[int, int]:
     """The k-th 64-bit prime (largest first) and a primitive 2^21-th root of unity."""
     p, r = ctypes.c_uint64(), ctypes.c_uint64()
@@ -211,6 +232,22 @@ class Context:
         nat.check(nat.zpm_mul_p64(self._h, a.data_ptr(), da, Na, b.data_ptr(), db, Nb,
                                   out.data_ptr() if n else None, wc, K, np, _stream_handle(stream)),
                   "zpm_mul_p64")
+        return out
+
+    def mul_gfp(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int, K: int = 0, k: int = 0,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """c = a * b with one generalized Fermat prime (zpm_mul_gfp); K, k: 0 = choose."""
+        da = _check_operand(a, Na, "a")
+        db = _check_operand(b, Nb, "b")
+        n = da + db - 1 if (da and db) else 0
+        wc = out_words(da, Na, db, Nb) if n else 1
+        if out is None:
+            out = torch.empty((n, wc), dtype=torch.int64, device=a.device)
+        elif out.shape != (n, wc) or out.dtype != torch.int64 or not out.is_contiguous():
+            raise ValueError("out has the wrong shape or dtype")
+        nat.check(nat.zpm_mul_gfp(self._h, a.data_ptr(), da, Na, b.data_ptr(), db, Nb,
+                                  out.data_ptr() if n else None, wc, K, k, _stream_handle(stream)),
+                  "zpm_mul_gfp")
         return out
 
     def mul_stage(self, a: torch.Tensor, Na: int, b: torch.Tensor, Nb: int, stop_after: int,

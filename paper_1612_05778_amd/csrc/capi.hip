@@ -13,6 +13,7 @@
 #include "ctx.hpp"
 #include "kernels.hpp"
 #include "p64.hpp"
+#include "gfp.hpp"
 #include "nt.hpp"
 #include "plan.hpp"
 
@@ -205,6 +206,7 @@ int Ctx::check_range(const uint64_t *src, int64_t d, int32_t N, hipStream_t st) 
 
 Ctx::~Ctx() {
   p64_release(*this);
+  gfp_release(*this);
   if (!primes) return;   // a host-only context (planning) owns no device resources
   (void)hipSetDevice(device);
   (void)hipDeviceSynchronize();
@@ -410,7 +412,9 @@ int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t
                                         "convolve_rows", "col_pass_inv",
                                         "recovering_product", "batch",
                                         "p64_convert_in", "p64_y_fwd", "p64_x_convolve",
-                                        "p64_y_inv", "p64_recover"};
+                                        "p64_y_inv", "p64_recover", "gfp_convert_in",
+                                        "gfp_y_fwd", "gfp_x_convolve", "gfp_y_inv",
+                                        "gfp_recover"};
   double ms[KK_COUNT] = {0};
   int64_t cnt[KK_COUNT] = {0};
   int rc = ZPM_OK;
@@ -628,6 +632,77 @@ void zpm_operand_destroy(zpm_operand *op) {
   (void)hipSetDevice(op->cx->device);
   if (op->spec) (void)hipFree(op->spec);
   delete op;
+}
+
+static void fill_info_gfp(const PlanGfp &pl, zpm_gfp_info *out) {
+  std::memset(out, 0, sizeof(*out));
+  out->da = pl.da;
+  out->db = pl.db;
+  out->Na = pl.Na;
+  out->Nb = pl.Nb;
+  out->k = pl.k;
+  out->r = gfp_prime_table()[pl.prime].r;
+  out->K = pl.K;
+  out->M = pl.M;
+  out->log2_L = pl.logL;
+  out->npass = pl.npass;
+  for (int q = 0; q < pl.npass && q < 6; ++q) out->pass_log2n[q] = pl.pass_logn[q];
+  out->log2p = gfp_prime_table()[pl.prime].log2p;
+  out->nout_bits = pl.nout_bits;
+  out->workspace_bytes = pl.ws_words * 4;
+}
+
+static int gfp_prime_index(int32_t k) {
+  if (k == 0) return -1;
+  for (int i = 0; i < GFP_NPRIMES; ++i)
+    if (gfp_prime_table()[i].k == k) return i;
+  return -2;
+}
+
+int zpm_gfp_prime(int32_t k, int32_t *r, int32_t *log2p) {
+  const int i = gfp_prime_index(k);
+  if (i < 0 || !r || !log2p) return ZPM_EINVAL;
+  *r = gfp_prime_table()[i].r;
+  *log2p = gfp_prime_table()[i].log2p;
+  return ZPM_OK;
+}
+
+int zpm_gfp_root(int32_t k, int32_t log2_L, int32_t *digits) {
+  const int i = gfp_prime_index(k);
+  if (i < 0 || !digits || log2_L < 0 || log2_L > GFP_LOG2_LMAX) return ZPM_EINVAL;
+  return gfp_root(i, log2_L, digits) ? ZPM_OK : ZPM_EUNSUPPORTED;
+}
+
+int zpm_plan_gfp(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t k,
+                 zpm_gfp_info *out) {
+  if (!out || K < 0 || da < 1 || db < 1 || Na < 1 || Nb < 1) return ZPM_EINVAL;
+  const int pi = gfp_prime_index(k);
+  if (pi == -2) return ZPM_EINVAL;
+  PlanGfp pl;
+  if (!make_plan_gfp(da, Na, db, Nb, K, pi, pl)) return ZPM_EUNSUPPORTED;
+  fill_info_gfp(pl, out);
+  return ZPM_OK;
+}
+
+int zpm_mul_gfp(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
+                int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t K, int32_t k,
+                void *stream) {
+  if (!ctx || K < 0) return ZPM_EINVAL;
+  const int pi = gfp_prime_index(k);
+  if (pi == -2) return ZPM_EINVAL;
+  int rc = check_mul_args(a, da, Na, b, db, Nb, c, wc);
+  if (rc != ZPM_OK) return rc;
+  if (da == 0 || db == 0) return ZPM_OK;
+  PlanGfp pl;
+  if (!make_plan_gfp(da, Na, db, Nb, K, pi, pl)) return ZPM_EUNSUPPORTED;
+  pl.square = (a == b && da == db && Na == Nb) ? 1 : 0;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  std::lock_guard<std::mutex> lock(cx->mu);
+  if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = cx->check_range(a, da, Na, st)) != ZPM_OK) return rc;
+  if ((rc = cx->check_range(b, db, Nb, st)) != ZPM_OK) return rc;
+  return mul_gfp(*cx, pl, a, b, c, wc, st);
 }
 
 int zpm_sync(zpm_ctx *ctx, void *stream) {

@@ -67,10 +67,12 @@ struct KronPlan {
 bool kron_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t chunk_bits, KronPlan *out);
 
 struct P64State;   // tables and workspace of the 64-bit prime variant
+struct GfpState;   // tables and workspace of the generalized Fermat prime variant
 
 struct Ctx {
   int device = 0;
   P64State *p64 = nullptr;
+  GfpState *gfp = nullptr;
   PrimeDev *primes = nullptr;   // MAXNP entries
   uint2 *heaps = nullptr;       // np_built primes x (forward H, inverse H)
   int np_built = 0;

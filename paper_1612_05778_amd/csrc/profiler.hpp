@@ -18,7 +18,12 @@ enum KernelKind {
   KK_P64_X = 8,
   KK_P64_YINV = 9,
   KK_P64_RECOVER = 10,
-  KK_COUNT = 11
+  KK_GFP_CONVERT = 11,  // single generalized Fermat prime variant
+  KK_GFP_YFWD = 12,
+  KK_GFP_X = 13,
+  KK_GFP_YINV = 14,
+  KK_GFP_RECOVER = 15,
+  KK_COUNT = 16
 };
 
 struct Profiler {
