@@ -12,11 +12,16 @@ The cpu_baseline leg times the oracle (plain schoolbook, all host threads) on a
 bounded sample of output coefficients of the same workload and extrapolates by
 the number of coefficient pairs; it is a reported baseline only.
 
-Two more legs follow the main line's timing: ``batched`` (4096 products of uneven
-size, one at a time through zpm_mul against tuned zpm_mul_batch with graph replay)
-and ``served`` (an open-loop Poisson stream through the continuous-batching server
-at a stated fraction of its saturated throughput, with p50/p99 latency, and the
-same stream through the single-product baseline).
+More legs follow the main line's timing: ``square`` and ``resident_operand`` (the same
+operands), ``p64`` (64-bit machine-word primes) and ``gfp`` (one generalized Fermat
+prime) on the same product, ``latency`` (d = 1024 signed 64-bit coefficients, median and
+p99 per call), ``large`` (d = 2^18, 16384-bit magnitudes), ``batched`` (4096 products of
+uneven size, one at a time through zpm_mul against tuned zpm_mul_batch with graph
+replay) and ``served`` (an open-loop Poisson stream through the continuous-batching
+server at a stated fraction of its saturated throughput, with p50/p99 latency, and the
+same stream through the single-product baseline).  Batched, served and large legs state
+their roofline fraction T*/T, T* being the sum over each product's kernels of
+max(algorithmic bytes / HBM peak, algorithmic ops / ALU peak).
 """
 from __future__ import annotations
 
@@ -164,11 +169,26 @@ def batch_leg(ctx, reps: int) -> dict:
     batch_ms = timed(batched, reps)
     nl = nat.c_i64()
     nat.zpm_batch_schedule(pb.jobs, pb.n, 0, ctypes.byref(nl), None, 0)
+    ts = sum(t_star_of(pb.jobs[i].da, pb.jobs[i].Na, pb.jobs[i].db, pb.jobs[i].Nb)
+             for i in range(pb.n)) * 1e3
     return {"workload": "batch4096", "products": pb.n, "out_bits": bits,
             "value": bits / (batch_ms / 1e3), "ms": batch_ms, "launches": nl.value,
             "plain_value": bits / (plain_ms / 1e3), "plain_ms": plain_ms,
             "speedup": plain_ms / batch_ms, "identical_to_plain": same,
+            "t_star_ms": ts, "roofline_frac": ts / batch_ms, "plain_roofline_frac": ts / plain_ms,
             "tune_s": tune_s, "tuned_classes": len(ctx.tune_table())}
+
+
+def t_star_of(da: int, Na: int, db: int, Nb: int) -> float:
+    """Roofline time (s) of one product under the planner's single-product plan: the sum
+    over its kernels of max(algorithmic bytes / HBM peak, algorithmic ops / ALU peak)."""
+    from paper_1612_05778_amd.api import plan as get_plan
+    from paper_1612_05778_amd.workmodel import t_star
+    try:
+        pl = get_plan(da, Na, db, Nb)
+    except RuntimeError:
+        return 0.0
+    return t_star(pl)
 
 
 def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: int,
@@ -192,6 +212,7 @@ def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: 
     pool = synth.served_pool(5, n_pool)
     pb = PackedBatch(pool)
     bits = [product_bits(p.da, p.Na, p.db, p.Nb) for p in pool]
+    tstar = [t_star_of(p.da, p.Na, p.db, p.Nb) for p in pool]
     mean_bits = float(np.mean(bits))
     big = float(large_bits or (1 << 26))
     h = torch.cuda.current_stream().cuda_stream
@@ -273,6 +294,7 @@ def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: 
         m = lat[warm:]
         rb = np.array([bits[k % n_pool] for k in range(warm, n_total)])
         done_bits = float(rb.sum())
+        done_tstar = float(sum(tstar[k % n_pool] for k in range(warm, n_total)))
 
         def pct(x):
             if not len(x):
@@ -282,6 +304,7 @@ def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: 
         return {"requests": n_total - warm, "warmup_requests": warm,
                 "offered_req_per_s": rate, "offered_bits_per_s": rate * mean_bits,
                 "throughput_bits_per_s": done_bits / span,
+                "roofline_frac": done_tstar / span,
                 "p50_ms": float(np.percentile(m, 50)) * 1e3, "p99_ms": float(np.percentile(m, 99)) * 1e3,
                 "max_ms": float(np.max(m)) * 1e3, "mean_ms": float(np.mean(m)) * 1e3,
                 "small": pct(m[rb < big]), "large": pct(m[rb >= big]),
@@ -311,6 +334,8 @@ def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: 
            "hbm_budget_bytes": budget, "streams": streams, "load": load,
            "large_bits": big, "large_streams": large_streams or max(1, streams // 4),
            "saturated_bits_per_s": cap, "plain_sequential_bits_per_s": sum(bits) / plain_s,
+           "saturated_roofline_frac": cap / sum(bits) * sum(tstar),
+           "plain_sequential_roofline_frac": sum(tstar) / plain_s,
            **res}
     if n_single:
         print(f"[bench] served leg: single-product baseline, {n_single} requests", file=sys.stderr,
@@ -322,10 +347,118 @@ def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: 
         w = max(1, n_single // 10)
         base = stream(srv, n_single + w, w, rate)
         srv.close()
-        out["single_product"] = {"saturated_bits_per_s": cap1, **{k: base[k] for k in (
-            "requests", "throughput_bits_per_s", "p50_ms", "p99_ms", "max_ms", "mean_ms", "small",
-            "large")}}
+        out["single_product"] = {"saturated_bits_per_s": cap1,
+                                 "saturated_roofline_frac": cap1 / sum(bits) * sum(tstar),
+                                 **{k: base[k] for k in (
+            "requests", "throughput_bits_per_s", "roofline_frac", "p50_ms", "p99_ms", "max_ms",
+            "mean_ms", "small", "large")}}
     return out
+
+
+def latency_leg(ctx, n: int = 400) -> dict:
+    """Latency of the small single product (d = 1024 coefficients of signed 64-bit
+    integers each, seed 1): one call at a time, each bracketed by events on its stream."""
+    import torch
+    from paper_1612_05778_amd import synth
+    from paper_1612_05778_amd.workmodel import product_bits
+    prod = synth.int64_1k()
+    a = torch.from_numpy(prod.a.view(np.int64).copy()).cuda()
+    b = torch.from_numpy(prod.b.view(np.int64).copy()).cuda()
+    out = ctx.mul(a, prod.Na, b, prod.Nb)
+    for _ in range(20):
+        ctx.mul(a, prod.Na, b, prod.Nb, out=out)
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev[0].record(st)
+    for i in range(n):
+        ctx.mul(a, prod.Na, b, prod.Nb, out=out)
+        ev[i + 1].record(st)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) / n
+    lat = sorted(ev[i].elapsed_time(ev[i + 1]) * 1e3 for i in range(n))
+    bits = product_bits(prod.da, prod.Na, prod.db, prod.Nb)
+    med = lat[n // 2]
+    return {"workload": "int64_1k", "calls": n, "median_us": med,
+            "p99_us": lat[min(n - 1, int(0.99 * n))], "min_us": lat[0],
+            "host_wall_us_per_call": wall * 1e6, "value": bits / (med / 1e6),
+            "t_star_us": t_star_of(prod.da, prod.Na, prod.db, prod.Nb) * 1e6}
+
+
+def large_leg(ctx, steps: int) -> dict:
+    """The large product (d = 2^18 coefficients of 16384-bit magnitudes, seed 3)."""
+    import torch
+    from paper_1612_05778_amd.api import plan as get_plan
+    from paper_1612_05778_amd.workmodel import product_bits
+    print("[bench] large leg: generating 2^18 x 16385-bit operands", file=sys.stderr, flush=True)
+    prod = make_workload("bits16384_256k")
+    a = torch.from_numpy(prod.a.view(np.int64)).cuda()
+    b = torch.from_numpy(prod.b.view(np.int64)).cuda()
+    da, Na, db, Nb = prod.da, prod.Na, prod.db, prod.Nb
+    del prod
+    pl = get_plan(da, Na, db, Nb)
+    out = ctx.mul(a, Na, b, Nb)
+    ctx.mul(a, Na, b, Nb, out=out)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(steps):
+        ctx.mul(a, Na, b, Nb, out=out)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    bits = product_bits(da, Na, db, Nb)
+    ts = t_star_of(da, Na, db, Nb) * 1e3
+    del a, b, out
+    torch.cuda.empty_cache()
+    return {"workload": "bits16384_256k", "d": da, "N": Na, "steps": steps, "ms": ms,
+            "value": bits / (ms / 1e3), "plan": {k: pl[k] for k in ("K", "M", "np", "log2_L", "col_log2n")},
+            "t_star_ms": ts, "roofline_frac": ts / ms}
+
+
+def gfp_leg(ctx, a, b, prod, steps: int, product_ms: float) -> dict:
+    """The single generalized Fermat prime variant on the same operands."""
+    import torch
+    from paper_1612_05778_amd.api import plan_gfp
+    from paper_1612_05778_amd.workmodel import INT32_PEAK, gfp_work, product_bits
+    info = plan_gfp(prod.da, prod.Na, prod.db, prod.Nb)
+    print(f"[bench] gfp k={info['k']} K={info['K']} M={info['M']} passes={info['pass_log2n']}",
+          file=sys.stderr, flush=True)
+    out = ctx.mul_gfp(a, prod.Na, b, prod.Nb)
+    ctx.mul_gfp(a, prod.Na, b, prod.Nb, out=out)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(steps):
+        ctx.mul_gfp(a, prod.Na, b, prod.Nb, out=out)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ctx.profile_begin()
+    for _ in range(steps):
+        ctx.mul_gfp(a, prod.Na, b, prod.Nb, out=out)
+    torch.cuda.synchronize()
+    kern = ctx.profile_end()
+    k2 = info["k"] ** 2
+    kin = {}
+    for name, (n, t) in kern.items():
+        w = gfp_work(info, name)
+        per = t / steps
+        kin[name] = {"launches_per_step": n / steps, "ms_per_step": per,
+                     "generic_products": w["products"], "algorithmic_bytes": w["bytes"],
+                     "GBps": w["bytes"] / (per / 1e3) / 1e9 if w["bytes"] else None,
+                     "digit_mads_per_s": w["products"] * k2 / (per / 1e3) if w["products"] else None,
+                     "mad_frac_of_int32_peak": (w["products"] * k2 / (per / 1e3) / INT32_PEAK
+                                                if w["products"] else None)}
+    bits = product_bits(prod.da, prod.Na, prod.db, prod.Nb)
+    del out
+    torch.cuda.empty_cache()
+    return {"k": info["k"], "r": info["r"], "log2p": info["log2p"], "K": info["K"], "M": info["M"],
+            "log2_L": info["log2_L"], "y_passes_log2n": info["pass_log2n"], "ms": ms,
+            "value": bits / (ms / 1e3), "vs_product": product_ms / ms, "kernels": kin}
 
 
 P64_CONFIGS = {"default": ((0, 0),), "paper": ((128, 2),), "both": ((0, 0), (128, 2))}
@@ -451,6 +584,12 @@ def main() -> int:
                     help="output bits from which a request runs alone (0 = library default)")
     ap.add_argument("--served-single", type=int, default=3000,
                     help="requests of the single-product baseline (0 = skip)")
+    ap.add_argument("--no-latency", action="store_true", help="skip the int64_1k latency leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the bits16384_256k leg")
+    ap.add_argument("--large-steps", type=int, default=5)
+    ap.add_argument("--no-gfp", action="store_true", help="skip the generalized Fermat prime leg")
+    ap.add_argument("--only-gfp", action="store_true",
+                    help="time the generalized Fermat prime variant alone (for profiling)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -524,10 +663,21 @@ def main() -> int:
                        "share": tot / (ms * args.steps), **work,
                        "timed_in": "timed region" if name == dom else "breakdown run"}
     d = kinfo[dom]
+    from paper_1612_05778_amd import _native as nat
+    from paper_1612_05778_amd.workmodel import OPS_BFLY
+    bfly = ctypes.c_double()
+    nat.check(nat.zpm_butterfly_ceiling(0, 4096, ctypes.byref(bfly)), "zpm_butterfly_ceiling")
+    ceiling = {"kernel": "register-resident forward butterflies (add_mod, mul_shoup), 8 pairs per "
+                         "thread, 8 workgroups of 256 per CU",
+               "butterflies_per_s": bfly.value,
+               "int32_ops_per_s": bfly.value * OPS_BFLY,
+               "vs_derived_peak": bfly.value * OPS_BFLY / INT32_PEAK}
     if d["ops"]:
         achieved = d["ops"] / (d["avg_ms"] / 1e3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_PEAK / 1e12,
                 "unit": "Tops/s (int32 VALU)", "frac": achieved / INT32_PEAK,
+                "peak_measured": bfly.value * OPS_BFLY / 1e12,
+                "frac_measured": achieved / (bfly.value * OPS_BFLY),
                 "traffic": measured_traffic(args.workload, dom), "traffic_unit": "bytes/launch",
                 "algorithmic_bytes": d["bytes"],
                 "kernel": dom}
@@ -593,11 +743,17 @@ def main() -> int:
                    "plan": {k: pl[k] for k in ("K", "M", "np", "log2_L", "log2_L1", "col_log2n", "W")},
                    "wall_ms_per_step": wall * 1e3 / args.steps},
         "roofline": roof,
+        "alu_ceiling": ceiling,
         "path_roofline": path,
         "step_ms": step_stats,
         "transfers": pcie,
         "kernels": kinfo,
     }
+    if args.only_gfp:
+        print(json.dumps({"workload": args.workload,
+                          "gfp": gfp_leg(ctx, a, b, prod, args.steps, ms)}), flush=True)
+        ctx.close()
+        return 0
     if args.only_p64:
         print(json.dumps({"workload": args.workload,
                           "p64": p64_leg(ctx, a, b, prod, args.steps, ms, P64_CONFIGS[args.p64_config])}), flush=True)
@@ -634,6 +790,14 @@ def main() -> int:
     op.close()
     if not args.no_p64:
         line["p64"] = p64_leg(ctx, a, b, prod, args.steps, ms, P64_CONFIGS[args.p64_config])
+    if not args.no_gfp:
+        line["gfp"] = gfp_leg(ctx, a, b, prod, args.steps, ms)
+    if not args.no_latency:
+        line["latency"] = latency_leg(ctx)
+    if not args.no_large:
+        del a, b
+        torch.cuda.empty_cache()
+        line["large"] = large_leg(ctx, args.large_steps)
     if not args.no_batch:
         line["batched"] = batch_leg(ctx, args.batch_reps)
     if not args.no_served:

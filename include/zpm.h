@@ -455,6 +455,13 @@ int64_t zpm_noalloc_max_bytes(void);
 int zpm_mul_noalloc(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
                     int64_t db, int32_t Nb, uint64_t *c, int32_t wc, void *stream);
 
+/* Measurement aid: the attainable rate (butterflies per second) of the transforms' modular
+ * butterfly u, v -> u + v, (u - v) w mod p on HIP device `device`, with every operand in
+ * registers and no memory traffic (eight 256-thread workgroups per compute unit, eight
+ * independent pairs per thread, `iters` butterflies on each).  Allocates a small result
+ * buffer, runs on the null stream and waits for it. */
+int zpm_butterfly_ceiling(int device, int32_t iters, double *bfly_per_s);
+
 /* Wait for the stream and report any device error raised by earlier calls. */
 int zpm_sync(zpm_ctx *ctx, void *stream);
 

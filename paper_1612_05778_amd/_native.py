@@ -221,6 +221,9 @@ zpm_plan_gfp = _sig("zpm_plan_gfp", ctypes.c_int,
 zpm_mul_gfp = _sig("zpm_mul_gfp", ctypes.c_int,
                    [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp])
 
+zpm_butterfly_ceiling = _sig("zpm_butterfly_ceiling", ctypes.c_int,
+                              [ctypes.c_int, c_i32, ctypes.POINTER(ctypes.c_double)])
+
 zpm_noalloc_max_bytes = _sig("zpm_noalloc_max_bytes", c_i64, [])
 zpm_mul_noalloc = _sig("zpm_mul_noalloc", ctypes.c_int,
                        [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_vp])
@@ -237,7 +240,7 @@ EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime
            "zpm_mul_operand", "zpm_operand_info", "zpm_operand_destroy", "zpm_mul_kronecker",
            "zpm_kronecker_plan", "zpm_plan_p64", "zpm_prime64", "zpm_mul_p64",
            "zpm_noalloc_max_bytes", "zpm_mul_noalloc", "zpm_gfp_prime", "zpm_gfp_root",
-           "zpm_plan_gfp", "zpm_mul_gfp"]
+           "zpm_plan_gfp", "zpm_mul_gfp", "zpm_butterfly_ceiling"]
 
 
 class ZpmError(RuntimeError):

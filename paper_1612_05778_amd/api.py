@@ -36,7 +36,8 @@ def kronecker_plan(da: int, Na: int, db: int, Nb: int, chunk_bits: int = 0) -> d
 
 KERNEL_KINDS = ["bivariate_representation", "col_pass_fwd", "convolve_rows", "col_pass_inv",
                 "recovering_product", "batch", "p64_convert_in", "p64_y_fwd", "p64_x_convolve",
-                "p64_y_inv", "p64_recover"]
+                "p64_y_inv", "p64_recover", "gfp_convert_in", "gfp_y_fwd", "gfp_x_convolve",
+                "gfp_y_inv", "gfp_recover"]
 
 
 def plan_p64(da: int, Na: int, db: int, Nb: int, K: int = 0, np: int = 0) -> dict:
@@ -350,10 +351,10 @@ class Context:
 
     def profile_end(self) -> dict:
         """{kernel name: (launches, total GPU ms)} since profile_begin."""
-        buf = (nat.KernelTime * 16)()
+        buf = (nat.KernelTime * 32)()
         n = nat.c_i32()
-        nat.check(nat.zpm_profile_end(self._h, buf, 16, ctypes.byref(n)), "zpm_profile_end")
-        return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(n.value, 16))}
+        nat.check(nat.zpm_profile_end(self._h, buf, 32, ctypes.byref(n)), "zpm_profile_end")
+        return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(n.value, 32))}
 
     def sync(self, stream=None) -> None:
         nat.check(nat.zpm_sync(self._h, _stream_handle(stream)), "zpm_sync")

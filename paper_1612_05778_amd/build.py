@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libzpm.so")
 SOURCES = ["nt.cpp", "plan.cpp", "kernels.hip", "batch.hip", "batch_host.cpp", "capi.hip", "kron.hip",
-           "tune.cpp", "server.cpp", "p64.hip", "noalloc.hip", "gfp.hip"]
+           "tune.cpp", "server.cpp", "p64.hip", "noalloc.hip", "gfp.hip",
+           "ceiling.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("ZPM_ARCH", "gfx950")

@@ -11,7 +11,14 @@ whose first stage is the twist):
 * one radix-2 butterfly = 11 int32 VALU operations (Shoup product: 2 mul_lo,
   1 mul_hi, 1 sub, 2 for the final reduction; modular add 3; modular sub 2);
 * one pointwise product = 13 (Montgomery product 7, Shoup scaling 6);
-* one four-step twiddle product = 6 (Shoup product with reduction).
+* one four-step twiddle product = 6 (Shoup product with reduction);
+* convert-in, per limb residue: 2 per 32-bit word of the limb (a multiply-add with
+  the table entry 2^(32 t) mod p and its carry) plus 6 for the final reduction;
+* CRT of one value c_{i,j} from np residues (Section 2.2, the recovery through
+  the Chinese remaindering of Section 4): 6 per residue (its Shoup product with
+  (P/p_k)^{-1}), 2 per word of each of the np products y_k (P/p_k) summed over W
+  words (multiply-add and carry), and 4 per word for the quotient correction and
+  the shifted accumulation at 2^(Mj).
 
 HBM bytes are the compulsory reads and writes of each launch (every element in
 and out once).
@@ -62,11 +69,72 @@ def kernel_work(plan: dict, name: str) -> dict:
         # per launch = one operand; the mean of the two
         w = ((plan["Na"] + 63) // 64 * da + (plan["Nb"] + 63) // 64 * db) / 2
         d = (da + db) / 2
-        return {"ops": 0, "bytes": 8 * w + 4 * np_ * K * d}
+        words = (plan["M"] + 31) // 32
+        return {"ops": d * K * np_ * (2 * words + 6), "bytes": 8 * w + 4 * np_ * K * d}
     if name == "recovering_product":
         wc = (plan["nout_bits"] + 63) // 64
-        return {"ops": 0, "bytes": 4 * np_ * (2 * K - 1) * nout + 8 * nout * wc}
+        W = plan["W"]
+        nvals = (2 * K - 1) * nout
+        return {"ops": nvals * (6 * np_ + 2 * np_ * W + 4 * W),
+                "bytes": 4 * np_ * (2 * K - 1) * nout + 8 * nout * wc}
     return {"ops": 0, "bytes": 0}
+
+
+KERNELS = ("bivariate_representation", "col_pass_fwd", "convolve_rows", "col_pass_inv",
+           "recovering_product")
+
+
+def launches(plan: dict, name: str, square: bool = False) -> int:
+    """Launches of one kernel kind in one product of this plan."""
+    if name == "bivariate_representation":
+        return 1 if square else 2
+    if name in ("col_pass_fwd", "col_pass_inv"):
+        return len(plan["col_log2n"])
+    return 1
+
+
+def t_star(plan: dict, bw: float = None, alu: float = None, square: bool = False) -> float:
+    """Roofline time (s) of one product: the sum over its launches of
+    max(bytes / bandwidth, ops / ALU rate)."""
+    bw = bw or HBM_PEAK
+    alu = alu or INT32_PEAK
+    t = 0.0
+    for k in KERNELS:
+        n = launches(plan, k, square)
+        if n:
+            w = kernel_work(plan, k)
+            t += n * max(w["bytes"] / bw, w["ops"] / alu)
+    return t
+
+
+def gfp_work(info: dict, name: str) -> dict:
+    """Algorithmic work of the generalized Fermat prime variant per product: generic
+    products in Z/pZ (k^2 digit multiply-adds each) and HBM bytes, per kernel group.
+    Products: the twiddles between y-passes (on every column of each pass but the
+    innermost, both directions) and the 2K L pointwise products."""
+    k, K = info["k"], info["K"]
+    L = 1 << info["log2_L"]
+    da, db = info["da"], info["db"]
+    nout = da + db - 1
+    npass = info["npass"]
+    el = 4 * k                                   # bytes of one element
+    full = el * 2 * K * L
+    wc = (info["nout_bits"] + 63) // 64
+    if name == "gfp_convert_in":
+        words = ((info["Na"] + 63) // 64) * da + ((info["Nb"] + 63) // 64) * db
+        return {"products": 0, "bytes": 8 * words + el * K * (da + db)}
+    if name == "gfp_y_fwd":
+        rows = el * K * (da + db)
+        return {"products": 2 * K * L * max(npass - 1, 0),
+                "bytes": (rows + full + 2 * full * (npass - 1)) if npass else 0}
+    if name == "gfp_x_convolve":
+        return {"products": 2 * K * L, "bytes": 2 * full}
+    if name == "gfp_y_inv":
+        return {"products": 2 * K * L * max(npass - 1, 0),
+                "bytes": (2 * full * (npass - 1) + full + el * 2 * K * nout) if npass else 0}
+    if name == "gfp_recover":
+        return {"products": 0, "bytes": el * 2 * K * nout + 8 * nout * wc}
+    return {"products": 0, "bytes": 0}
 
 
 def product_bits(da: int, Na: int, db: int, Nb: int) -> int:
