@@ -193,7 +193,7 @@ def t_star_of(da: int, Na: int, db: int, Nb: int) -> float:
 
 def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: int,
                n_single: int, large_bits: float = 0.0, large_streams: int = 0,
-               fixed_rate: float = 0.0) -> dict:
+               fixed_rate: float = 0.0, min_batch: int = 0, linger_s: float = 0.0) -> dict:
     """Open-loop Poisson stream of the served distribution (degree log-uniform in
     [15, 65535], magnitude bits log-uniform in [16, 8192], seed 5) through the
     continuous-batching server.  The offered load is ``load`` times the server's
@@ -315,7 +315,7 @@ def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: 
                 "inflight_peak": st["inflight_peak"], "pool_reuse_waits": guard_waits}
 
     srv = api.Server(ctx, hbm_budget=budget, n_streams=streams, large_bits=large_bits,
-                     large_streams=large_streams)
+                     large_streams=large_streams, min_batch=min_batch, linger_s=linger_s)
     print("[bench] served leg: saturated throughput", file=sys.stderr, flush=True)
     saturated(srv)
     cap = saturated(srv)
@@ -332,7 +332,8 @@ def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: 
     res["identical_to_alone"] = same_sat and bool(torch.equal(pb.outputs, ref))
     out = {"workload": "served", "pool_requests": n_pool, "pool_mean_out_bits": mean_bits,
            "hbm_budget_bytes": budget, "streams": streams, "load": load,
-           "large_bits": big, "large_streams": large_streams or max(1, streams // 4),
+           "large_bits": big, "large_streams": large_streams or max(1, streams // 2),
+           "min_batch": min_batch or 4, "linger_us": (linger_s or 150e-6) * 1e6,
            "saturated_bits_per_s": cap, "plain_sequential_bits_per_s": sum(bits) / plain_s,
            "saturated_roofline_frac": cap / sum(bits) * sum(tstar),
            "plain_sequential_roofline_frac": sum(tstar) / plain_s,
@@ -575,7 +576,11 @@ def main() -> int:
     ap.add_argument("--served-load", type=float, default=0.7,
                     help="offered load as a fraction of the server's saturated throughput")
     ap.add_argument("--served-budget-gib", type=float, default=16.0)
-    ap.add_argument("--served-streams", type=int, default=8)
+    ap.add_argument("--served-streams", type=int, default=4)
+    ap.add_argument("--served-min-batch", type=int, default=0,
+                    help="small requests a batch waits for while the device is busy (0 = library default)")
+    ap.add_argument("--served-linger-us", type=float, default=0.0,
+                    help="longest such wait in microseconds (0 = library default, < 0 = none)")
     ap.add_argument("--served-rate", type=float, default=0.0,
                     help="offered requests/s (0 = --served-load times the saturated throughput)")
     ap.add_argument("--served-large-streams", type=int, default=0,
@@ -804,7 +809,8 @@ def main() -> int:
         line["served"] = served_leg(ctx, args.served_requests, args.served_warmup, args.served_load,
                                     int(args.served_budget_gib * (1 << 30)), args.served_streams,
                                     args.served_single, args.served_large_bits,
-                                    args.served_large_streams, args.served_rate)
+                                    args.served_large_streams, args.served_rate,
+                                    args.served_min_batch, args.served_linger_us * 1e-6)
     if not args.no_cpu:
         print("[bench] cpu_baseline: timing the oracle on a sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(prod, args.cpu_seconds)

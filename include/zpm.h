@@ -239,7 +239,8 @@ int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t
  * their workspace (the np * 2K * L residues of their plan) fits in the free part of
  * the pool.  Requests with fewer than large_bits output bits
  * ((da + db - 1) * zpm_out_bits) are batched: as many as fit run together as
- * zpm_mul_batch's grouped launches on that stream.  A larger request keeps the device
+ * zpm_mul_batch's grouped launches on that stream; while other work occupies the
+ * device, a batch of fewer than min_batch requests waits up to linger_s for more.  A larger request keeps the device
  * busy by itself and runs alone, with the zpm_mul plan; large requests hold at most
  * large_streams streams at once, so that small requests do not wait behind them.  Work on different
  * streams overlaps on the device, and requests that arrive while others run join the
@@ -260,13 +261,19 @@ int zpm_profile_end(zpm_ctx *ctx, zpm_kernel_time *out, int32_t max_out, int32_t
 typedef struct zpm_server zpm_server;
 typedef struct zpm_server_config {
   size_t hbm_budget;   /* workspace pool bytes; 0 = half of the free device memory */
-  int32_t n_streams;   /* batches in flight at once, 1..16; 0 = 8 */
+  int32_t n_streams;   /* batches in flight at once, 1..16; 0 = 4 (a process gets four
+                          hardware queues by default) */
   int32_t max_batch;   /* products per batch, 1..4096; 0 = 4096 */
   double large_bits;   /* output bits from which a request is large; 0 = 2^26 */
   int32_t single_product; /* 1: no batching, every request runs alone through the
                              zpm_mul path (a baseline for the batched server) */
   int32_t large_streams;  /* streams large requests may hold at once, 1..n_streams;
-                             0 = max(1, n_streams / 4) */
+                             0 = max(1, n_streams / 2) */
+  int32_t min_batch;      /* while other work occupies the device, a batch of small
+                             requests waits for this many (or for linger_s); 0 = 4,
+                             1 = never wait */
+  double linger_s;        /* the longest a small request waits for companions while the
+                             device is busy, at most 1 s; 0 = 150 us, < 0 = no wait */
 } zpm_server_config;
 int zpm_server_create(zpm_ctx *ctx, size_t hbm_budget, int32_t n_streams, zpm_server **out);
 int zpm_server_create_ex(zpm_ctx *ctx, const zpm_server_config *cfg, zpm_server **out);

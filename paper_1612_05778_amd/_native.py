@@ -117,7 +117,8 @@ zpm_profile_end = _sig("zpm_profile_end", ctypes.c_int,
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("n_streams", c_i32), ("max_batch", c_i32),
-                ("large_bits", ctypes.c_double), ("single_product", c_i32), ("large_streams", c_i32)]
+                ("large_bits", ctypes.c_double), ("single_product", c_i32), ("large_streams", c_i32),
+                ("min_batch", c_i32), ("linger_s", ctypes.c_double)]
 
 
 class ServerReport(ctypes.Structure):

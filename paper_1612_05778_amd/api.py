@@ -414,9 +414,10 @@ class Server:
 
     def __init__(self, ctx: Context | None, hbm_budget: int = 0, n_streams: int = 0,
                  max_batch: int = 0, large_bits: float = 0.0, single_product: bool = False,
-                 large_streams: int = 0, simulate: dict | None = None):
+                 large_streams: int = 0, simulate: dict | None = None, min_batch: int = 0,
+                 linger_s: float = 0.0):
         cfg = nat.ServerConfig(hbm_budget, n_streams, max_batch, large_bits, int(single_product),
-                               large_streams)
+                               large_streams, min_batch, linger_s)
         h = nat.c_vp()
         if simulate is not None:
             rc = nat.zpm_server_create_simulated(ctypes.byref(cfg), simulate["bits_per_s"],

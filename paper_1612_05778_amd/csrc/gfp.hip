@@ -285,8 +285,10 @@ bool make_plan_gfp(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_for
       pl.K = K;
       pl.M = M;
       pl.logL = logL;
-      // y-passes of at most 2k points, as even as possible, outermost first
-      const int maxln = clog2(2 * P.k);
+      // y-passes of at most 2k points (roots r^(2k/n)) and at most 32: a 64-point pass
+      // keeps 64 digit registers per lane across its twiddle products and spills; as even
+      // as possible, outermost first
+      const int maxln = std::min(clog2(2 * P.k), 5);
       pl.npass = (logL + maxln - 1) / maxln;
       if (pl.npass > GFP_MAX_PASS) continue;
       for (int q = 0; q < pl.npass; ++q)

@@ -10,10 +10,13 @@
 // the batch kernels do not cover and every request in single-product mode (the
 // unbatched baseline).  Work on different streams overlaps on the device, and
 // requests that arrive meanwhile wait for the next free stream.  Large requests may
-// occupy at most large_streams streams (a quarter of them by default): while large
+// occupy at most large_streams streams (half of them by default): while large
 // kernels fill the device, small kernels wait for free compute units, so the fewer
 // large requests run at once, the shorter small requests' tail latency, at some cost
-// in throughput.  Twiddle tables and plan constants stay resident in the context.
+// in throughput.  While the device is busy, a small batch of fewer than min_batch
+// requests is held until its oldest request has waited linger_s, so that arrivals
+// coalesce into fewer, larger batches.  Twiddle tables and plan constants stay resident
+// in the context.
 //
 // The executor is an interface so that the admission and batching policy can also run
 // against a simulated device (no computation, a modelled duration per batch).
@@ -284,7 +287,7 @@ struct Server {
 
   int plan_req(SReq &r);
   bool take(int ln, Flight &f);
-  bool form(Flight &f, int busy_large);
+  bool form(Flight &f, int busy_large, int busy_any);
   void retire(Flight &f, int status);
   void fail_queued(int status);
   void run();
@@ -365,10 +368,16 @@ bool Server::take(int ln, Flight &f) {
   return true;
 }
 
-// Picks the lane whose head arrived first among those allowed a stream (under m).
-bool Server::form(Flight &f, int busy_large) {
+// Picks the lane whose head arrived first among those allowed a stream (under m).  While
+// other work occupies the device, a small batch of fewer than min_batch requests waits
+// until its oldest request has waited linger_s, so that requests arriving meanwhile
+// join it (an idle device takes whatever is queued at once).
+bool Server::form(Flight &f, int busy_large, int busy_any) {
   const bool large_ok = !lane[1].empty() && busy_large < cfg.large_streams;
-  const bool small_ok = !lane[0].empty();
+  bool small_ok = !lane[0].empty();
+  if (small_ok && busy_any && (int32_t)lane[0].size() < cfg.min_batch &&
+      seconds(Clock::now() - lane[0].front().t0) < cfg.linger_s)
+    small_ok = false;
   int order[2] = {0, 1};
   if (large_ok && small_ok && lane[1].front().t0 < lane[0].front().t0) std::swap(order[0], order[1]);
   for (int ln : order) {
@@ -451,12 +460,15 @@ void Server::run() {
       int s = 0;
       while (s < S && busy[s]) ++s;
       if (s == S) break;
-      int busy_large = 0;
-      for (int t = 0; t < S; ++t) busy_large += busy[t] && fls[t].large;
+      int busy_large = 0, busy_any = 0;
+      for (int t = 0; t < S; ++t) {
+        busy_large += busy[t] && fls[t].large;
+        busy_any += busy[t];
+      }
       Flight f;
       {
         std::lock_guard<std::mutex> lock(m);
-        if (dead != ZPM_OK || !form(f, busy_large)) break;
+        if (dead != ZPM_OK || !form(f, busy_large, busy_any)) break;
       }
       const int lr = ex->launch(s, f);
       if (lr != ZPM_OK) {
@@ -499,13 +511,17 @@ static int fill_config(const zpm_server_config *in, zpm_server_config *out) {
   zpm_server_config c;
   std::memset(&c, 0, sizeof(c));
   if (in) c = *in;
-  if (c.n_streams == 0) c.n_streams = 8;
+  if (c.n_streams == 0) c.n_streams = 4;
+  if (c.min_batch == 0) c.min_batch = 4;
+  if (c.linger_s == 0) c.linger_s = 150e-6;
+  if (c.linger_s < 0) c.linger_s = 0;
   if (c.max_batch == 0) c.max_batch = kMaxBatch;
   if (c.large_bits == 0) c.large_bits = 67108864.0;
-  if (c.large_streams == 0 && c.n_streams >= 1) c.large_streams = std::max(1, c.n_streams / 4);
+  if (c.large_streams == 0 && c.n_streams >= 1) c.large_streams = std::max(1, c.n_streams / 2);
   if (c.n_streams < 1 || c.n_streams > kMaxStreams || c.max_batch < 1 || c.max_batch > kMaxBatch ||
       !(c.large_bits > 0) || (c.single_product != 0 && c.single_product != 1) ||
-      c.large_streams < 1 || c.large_streams > c.n_streams)
+      c.large_streams < 1 || c.large_streams > c.n_streams || c.min_batch < 1 ||
+      !(c.linger_s <= 1.0))
     return ZPM_EINVAL;
   *out = c;
   return ZPM_OK;

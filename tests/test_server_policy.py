@@ -221,10 +221,50 @@ def test_concurrent_submitters():
 
 def test_config_rejected():
     for cfg in ({"n_streams": 17}, {"max_batch": 5000}, {"large_bits": -1.0}, {"single": 2},
-                {"n_streams": 2, "large_streams": 3}, {"large_streams": -1}):
+                {"n_streams": 2, "large_streams": 3}, {"large_streams": -1}, {"min_batch": -2},
+                {"linger_s": 2.0}):
         c = nat.ServerConfig(1 << 20, cfg.get("n_streams", 0), cfg.get("max_batch", 0),
                              cfg.get("large_bits", 0.0), cfg.get("single", 0),
-                             cfg.get("large_streams", 0))
+                             cfg.get("large_streams", 0), cfg.get("min_batch", 0),
+                             cfg.get("linger_s", 0.0))
         h = nat.c_vp()
         assert nat.zpm_server_create_simulated(ctypes.byref(c), 1e9, 0.0, -1, ctypes.byref(h)) \
             == nat.ZPM_EINVAL
+
+
+def test_small_requests_coalesce_while_busy():
+    # a long request occupies one stream; three small ones arriving meanwhile wait
+    # (min_batch 4) until a fourth joins them, and run as one batch
+    s = api.Server(None, hbm_budget=1 << 30, n_streams=2, min_batch=4, linger_s=0.5,
+                   simulate={"bits_per_s": 1e8, "overhead_s": 1e-3})
+    big = s.submit_job(job(2000, 400))          # about 1.6e6 bits: 16 ms simulated
+    time.sleep(0.002)
+    small = []
+    for _ in range(3):
+        small.append(s.submit_job(job(16, 32)))
+        time.sleep(0.002)
+    time.sleep(0.02)                             # the long one has finished; three wait
+    assert s.stats()["batches"] == 1
+    small.append(s.submit_job(job(16, 32)))
+    drain(s, [big] + small)
+    st = s.stats()
+    assert st["batches"] == 2 and st["mean_batch"] == 2.5
+    s.close()
+
+
+def test_linger_expires_and_idle_device_does_not_wait():
+    s = api.Server(None, hbm_budget=1 << 30, n_streams=2, min_batch=8, linger_s=0.03,
+                   simulate={"bits_per_s": 1e8, "overhead_s": 1e-3})
+    # idle device: a lone small request starts at once
+    t0 = time.time()
+    drain(s, [s.submit_job(job(16, 32))])
+    assert time.time() - t0 < 0.025
+    # busy device: two small requests wait for the linger time, then run together
+    big = s.submit_job(job(4000, 400))          # about 3.2e6 bits: 32 ms simulated
+    time.sleep(0.002)
+    small = [s.submit_job(job(16, 32)) for _ in range(2)]
+    got = drain(s, [big] + small)
+    assert all(v[0] == 0 for v in got.values())
+    st = s.stats()
+    assert st["batches"] == 3 and st["completed"] == 4
+    s.close()
