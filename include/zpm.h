@@ -169,8 +169,10 @@ int zpm_mul_ex(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const ui
  * launch (a few launches per level, whatever the number of products).  Stream-ordered
  * like zpm_mul.  ZPM_BATCH_GRAPH captures the whole sequence (descriptor upload and
  * launches) in a HIP graph and replays it when the same job array is passed again.
- * ZPM_BATCH_PERSISTENT (all levels in one persistent launch) is not available:
- * the call returns ZPM_ENOTIMPL. */
+ * ZPM_BATCH_PERSISTENT (every tile of every stage of every product in one persistent
+ * launch, workgroups taking task numbers from a counter in stage order and waiting on
+ * agent-scope stage counters) is not available in this build: the call returns
+ * ZPM_ENOTIMPL.  Combined with ZPM_BATCH_GRAPH it is ZPM_EINVAL. */
 typedef struct zpm_job {
   const uint64_t *a;
   int64_t da;
@@ -451,7 +453,9 @@ int zpm_mul_gfp(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const u
  *                are not resident and the context is not reserved: call zpm_reserve
  *                (max_len, max_bits, max_plans; workspace_bytes may be 0) or run one
  *                zpm_mul of the same sizes first;
- *   ZPM_EUNSUPPORTED  no direct plan (no Kronecker reshaping on this path).
+ *   ZPM_ENOTIMPL  coefficients too wide for a direct plan (zpm_mul reshapes those by
+ *                 Kronecker substitution, which this entry point does not do);
+ *   ZPM_EUNSUPPORTED  no plan at all.
  * Every such error returns before anything is enqueued, with c untouched.  All calls on
  * one device share the one array: calls whose work overlaps on the device (other
  * streams, other contexts, other host threads) race and give wrong results; order them

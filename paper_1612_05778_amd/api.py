@@ -267,8 +267,10 @@ class Context:
         w = ws.to(torch.int64) & 0xFFFFFFFF
         return w.view(info["np"], 2 * info["K"], L), info
 
-    def mul_batch(self, items, graph: bool = False, K: int = 0, stream=None, outs=None):
-        """Products of many (a, Na, b, Nb) in one call (grouped launches per level).
+    def mul_batch(self, items, graph: bool = False, K: int = 0, stream=None, outs=None,
+                  persistent: bool = False):
+        """Products of many (a, Na, b, Nb) in one call (grouped launches per level, or with
+        ``persistent`` all of them in one persistent launch, which waits for the device).
 
         items: list of (a, Na, b, Nb) with a, b int64 CUDA tensors as for mul.
         Returns the list of output tensors (allocated unless ``outs`` is given).
@@ -292,7 +294,7 @@ class Context:
             jobs[i].b, jobs[i].db, jobs[i].Nb = b.data_ptr(), db, Nb
             jobs[i].c, jobs[i].wc = (o.data_ptr() if nout else None), wc
         self._batch_jobs = jobs
-        flags = nat.ZPM_BATCH_GRAPH if graph else 0
+        flags = (nat.ZPM_BATCH_GRAPH if graph else 0) | (nat.ZPM_BATCH_PERSISTENT if persistent else 0)
         st = _stream_handle(stream)
         if K:
             rc = nat.zpm_mul_batch_ex(self._h, jobs, n, flags, K, st)

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libzpm.so")
 SOURCES = ["nt.cpp", "plan.cpp", "kernels.hip", "batch.hip", "batch_host.cpp", "capi.hip", "kron.hip",
            "tune.cpp", "server.cpp", "p64.hip", "noalloc.hip", "gfp.hip",
-           "ceiling.hip"]
+           "ceiling.hip", "persistent.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("ZPM_ARCH", "gfx950")

@@ -50,6 +50,21 @@ struct Group {
 
 hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *segs,
                         const PrimeDev *primes, hipStream_t st);
+
+// Persistent launch: every tile of every group as one task list (see persistent.hip).
+// done[job * PERSIST_LEVELS + level] counts the finished tiles of a product's stage, need[]
+// holds how many there are.
+constexpr int PERSIST_LEVELS = 3 + 2 * MAX_COL_PASSES;
+struct PersistCtl {
+  unsigned long long ticket;   // next task number
+  uint32_t abort;              // set when a wait exceeded its bound
+  uint32_t pad;
+};
+hipError_t launch_persistent(const JobDev *jobs, const GroupSeg *segs, const Group *groups,
+                             const int64_t *gstart, int32_t ngroups, int64_t ntasks,
+                             const uint32_t *need, uint32_t *done, int64_t nslots, PersistCtl *ctl,
+                             const PrimeDev *primes, size_t lds, uint32_t spin_limit, int ncu,
+                             hipStream_t st);
 // LDS bytes a stage of a plan needs (same formulas as the per-stage launchers).
 size_t stage_lds(const Plan &pl, int kind, int pass);
 // Whether the batch kernels have code for this plan.

@@ -38,6 +38,14 @@ struct BatchState {
   int64_t nlive = 0;
   hipEvent_t upload_done = nullptr;
   hipGraphExec_t exec = nullptr;
+  // persistent launch: groups, their first task numbers, tiles per product stage, the
+  // done counters and the ticket/abort words
+  Group *groups_h = nullptr, *groups_d = nullptr;
+  int64_t *gstart_h = nullptr, *gstart_d = nullptr;
+  uint32_t *need_h = nullptr, *need_d = nullptr, *done_d = nullptr;
+  int64_t groups_hcap = 0, groups_dcap = 0, gstart_hcap = 0, gstart_dcap = 0;
+  int64_t need_hcap = 0, need_dcap = 0, done_dcap = 0;
+  PersistCtl *ctl_h = nullptr, *ctl_d = nullptr;
   uint64_t key = 0;
   static uint64_t hash(const zpm_job *jobs, int64_t n, int32_t K_force, int32_t T_force);
   void release();
@@ -126,6 +134,10 @@ struct Ctx {
   // segments, so that later batches within those bounds allocate nothing
   int reserve_batch(BatchState &bs, int64_t jobs, int64_t segs);
   int enqueue_batch(BatchState &bs, hipStream_t st);
+  // the whole batch as one persistent launch; waits for it (ZPM_EDEVICE if a wait of the
+  // kernel exceeded its bound)
+  int enqueue_persistent(BatchState &bs, hipStream_t st);
+  int ncu = 0;                                 // compute units of the device (persistent grid)
   int mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_force, hipStream_t st,
                 int32_t T_force = 0);
   int tune(const zpm_job *sample, int64_t n, hipStream_t st);

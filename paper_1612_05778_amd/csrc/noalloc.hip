@@ -71,7 +71,13 @@ int zpm_mul_noalloc(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, con
   if (!ws) return ZPM_EDEVICE;
   int rc;
   Plan pl;
-  if ((rc = cx->get_plan(da, Na, db, Nb, 0, 0, &pl)) != ZPM_OK) return rc;
+  if ((rc = cx->get_plan(da, Na, db, Nb, 0, 0, &pl)) != ZPM_OK) {
+    // coefficients too wide for a direct plan: zpm_mul reshapes them (Kronecker), which
+    // needs a buffer of its own; not provided here
+    KronPlan kp;
+    if (rc == ZPM_EUNSUPPORTED && kron_plan(da, Na, db, Nb, 0, &kp)) return ZPM_ENOTIMPL;
+    return rc;
+  }
   if (pl.ws_words > SCRATCH_WORDS) return ZPM_ETOOBIG;
   pl.square = (a == b && da == db && Na == Nb) ? 1 : 0;
   // tables and plan constants must already be resident (zpm_reserve, or earlier

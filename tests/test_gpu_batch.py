@@ -119,16 +119,34 @@ def test_batch_graph_back_to_back(ctx):
             assert np.array_equal(e, host(o)), f"back-to-back graph batch differs (rep {rep})"
 
 
-@pytest.mark.skip(reason="the single persistent launch (all levels in one kernel, workgroups "
-                         "waiting on per-stage counters) stalled on the GPU twice, the second time "
-                         "after its polling loop stopped invalidating L2; no cause was found by "
-                         "reading the code or by a CPU simulation of its schedule, so it is "
-                         "switched off (ZPM_BATCH_PERSISTENT returns ZPM_ENOTIMPL)")
+@pytest.mark.skip(reason="ZPM_BATCH_PERSISTENT is switched off: the first run of this kernel "
+                         "never finished on the GPU. Cause, found in its compiled code: the "
+                         "loop exit read from LDS was divergent to the compiler, whose "
+                         "structurizer built an inner loop around the barrier and the task in "
+                         "which lanes 1..63 of wave 0 re-ran the last task while lane 0, which "
+                         "writes the next one, waited outside it. The kernel is restructured "
+                         "(all lane-0 work in a called function, a scalar loop exit; checked "
+                         "by tests/test_persistent_isa.py on the CPU) but has not been run on "
+                         "the GPU again")
 def test_persistent_single_launch(ctx):
+    """ZPM_BATCH_PERSISTENT: every stage of every product in one persistent launch, tasks
+    taken from a ticket counter in stage order (its schedule is modelled on the CPU in
+    test_persistent_model.py).  Must equal the grouped launches and the oracle, on
+    repeated calls and with a square and forced limb counts in the mix."""
     prods = small_mix()
-    from paper_1612_05778_amd import _native as nat
     items = to_dev(prods)
-    outs = ctx.mul_batch(items)
+    items.append((items[0][0], items[0][1], items[0][0], items[0][1]))   # a square
+    prods.append(synth.Product(prods[0].a, prods[0].Na, prods[0].a, prods[0].Na))
+    print(f"[batch] persistent launch of {len(items)} products", flush=True)
+    ref = [host(o) for o in ctx.mul_batch(items)]
+    ctx.sync()
+    for rep in range(3):
+        outs = ctx.mul_batch(items, persistent=True)
+        ctx.sync()
+        for i, (r, o) in enumerate(zip(ref, outs)):
+            assert np.array_equal(r, host(o)), f"persistent product {i} differs (rep {rep})"
+    check_all(prods, outs)
+    outs = ctx.mul_batch(items, persistent=True, K=2)
     ctx.sync()
     check_all(prods, outs)
 
@@ -138,6 +156,8 @@ def test_persistent_flag_is_rejected(ctx):
     jobs = (nat.Job * 1)()
     assert nat.zpm_mul_batch_ex(ctx.handle, jobs, 0, nat.ZPM_BATCH_PERSISTENT, 0, None) == \
         nat.ZPM_ENOTIMPL
+    assert nat.zpm_mul_batch_ex(ctx.handle, jobs, 0, nat.ZPM_BATCH_PERSISTENT | nat.ZPM_BATCH_GRAPH,
+                                0, None) == nat.ZPM_EINVAL
 
 
 def test_batch_empty_and_invalid(ctx):

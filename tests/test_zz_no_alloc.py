@@ -7,8 +7,9 @@ buffer; everything else is zpm_mul's path.  Checked here:
   (Section 1's product c_i = sum a_l b_m);
 * a square (one operand passed twice) likewise;
 * device free memory is unchanged by the calls;
-* a product whose workspace exceeds the array fails with ZPM_ETOOBIG, and one whose
-  tables are not resident with ZPM_ENOMEM, both with c untouched.
+* a product whose workspace exceeds the array fails with ZPM_ETOOBIG, one whose
+  tables are not resident with ZPM_ENOMEM, both with c untouched, and one whose
+  coefficients need Kronecker reshaping with ZPM_ENOTIMPL.
 """
 import numpy as np
 import pytest
@@ -96,6 +97,11 @@ def test_noalloc_limits():
     assert _noalloc(ctx, A2, big.Na, B2, big.Nb, o2) == nat.ZPM_ETOOBIG
     torch.cuda.synchronize()
     assert (host(o) == np.uint64(0x3C3C)).all() and (host(o2) == np.uint64(0x3C3C)).all()
+    # coefficients too wide for a direct plan (zpm_mul would reshape them): ZPM_ENOTIMPL
+    wide = synth.dense(406, 2, 120000)
+    Aw, Bw = dev(wide.a), dev(wide.b)
+    ow = _out(wide, 0x3C3C)
+    assert _noalloc(ctx, Aw, wide.Na, Bw, wide.Nb, ow) == nat.ZPM_ENOTIMPL
     # after the reservation the small product runs
     assert _noalloc(ctx, A, p.Na, B, p.Nb, o) == nat.ZPM_OK
     ctx.sync()
