@@ -98,7 +98,9 @@ def test_noalloc_limits():
     torch.cuda.synchronize()
     assert (host(o) == np.uint64(0x3C3C)).all() and (host(o2) == np.uint64(0x3C3C)).all()
     # coefficients too wide for a direct plan (zpm_mul would reshape them): ZPM_ENOTIMPL
-    wide = synth.dense(406, 2, 120000)
+    wide = synth.dense(406, 2, 300000)
+    with pytest.raises(RuntimeError):
+        api.plan(wide.da, wide.Na, wide.db, wide.Nb)
     Aw, Bw = dev(wide.a), dev(wide.b)
     ow = _out(wide, 0x3C3C)
     assert _noalloc(ctx, Aw, wide.Na, Bw, wide.Nb, ow) == nat.ZPM_ENOTIMPL
