@@ -1067,26 +1067,33 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
       allz = allz && (uint32_t)tsum == 0u;
       allo = allo && (uint32_t)tsum == 0xFFFFFFFFu;
     }
-    int code;
-    if (w_lo >= w_hi) {
-      code = (0) | (1 << 2) | (2 << 4);                 // identity
-    } else {
-      const int g = (int)x;                             // in {-1, 0, 1}
-      const int fm = g + (allz ? -1 : 0), f0 = g, fp = g + (allo ? 1 : 0);
-      code = (fm + 1) | ((f0 + 1) << 2) | ((fp + 1) << 4);
-    }
-    // inclusive scan of carry-transfer functions across the wave
+    // x is this lane's carry out in {-1, 0, 1} once its carry in is the lane below's
+    // first-level carry.  When every lane that has a lane above it gives 0, no carry
+    // moves further and the words are final (the top lane's carry out is the sign and
+    // leaves the output).  Otherwise the carries ripple through runs of all-zero or
+    // all-one lanes, which the scan resolves.
+    if (__any(w_lo < w_hi && w_hi < nw32 && x != 0)) {
+      int code;
+      if (w_lo >= w_hi) {
+        code = (0) | (1 << 2) | (2 << 4);               // identity
+      } else {
+        const int g = (int)x;                           // in {-1, 0, 1}
+        const int fm = g + (allz ? -1 : 0), f0 = g, fp = g + (allo ? 1 : 0);
+        code = (fm + 1) | ((f0 + 1) << 2) | ((fp + 1) << 4);
+      }
+      // inclusive scan of carry-transfer functions across the wave
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int other = __shfl_up(code, off, 64);
-      if (lane >= off) code = fcompose(code, other);
-    }
-    const int prevc = __shfl_up(code, 1, 64);
-    int y = lane == 0 ? 0 : fapply(prevc, 0);
-    for (int w = w_lo; w < w_hi && y != 0; ++w) {
-      const int64_t tsum = (int64_t)Si[w] + y;
-      Si[w] = (uint32_t)tsum;
-      y = (int)(tsum >> 32);
+      for (int off = 1; off < 64; off <<= 1) {
+        const int other = __shfl_up(code, off, 64);
+        if (lane >= off) code = fcompose(code, other);
+      }
+      const int prevc = __shfl_up(code, 1, 64);
+      int y = lane == 0 ? 0 : fapply(prevc, 0);
+      for (int w = w_lo; w < w_hi && y != 0; ++w) {
+        const int64_t tsum = (int64_t)Si[w] + y;
+        Si[w] = (uint32_t)tsum;
+        y = (int)(tsum >> 32);
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
