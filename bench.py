@@ -606,7 +606,8 @@ def main() -> int:
 
     import torch
     from paper_1612_05778_amd.api import Context, plan as get_plan
-    from paper_1612_05778_amd.workmodel import INT32_PEAK, HBM_PEAK, kernel_work, product_bits
+    from paper_1612_05778_amd.workmodel import (INT32_PEAK, HBM_PEAK, MFMA_I8_PEAK, kernel_time,
+                                                kernel_work, product_bits)
 
     print(f"[bench] workload {args.workload}: generating", file=sys.stderr, flush=True)
     if args.copy_mib:
@@ -694,7 +695,11 @@ def main() -> int:
     for v in kinfo.values():
         if v["ops"]:
             v["int32_Tops"] = v["ops"] / (v["avg_ms"] / 1e3) / 1e12
+        if v.get("mfma_ops"):
+            v["int8_mfma_Tops"] = v["mfma_ops"] / (v["avg_ms"] / 1e3) / 1e12
+            v["int8_mfma_frac"] = v["mfma_ops"] / (v["avg_ms"] / 1e3) / MFMA_I8_PEAK
         v["GBps"] = v["bytes"] / (v["avg_ms"] / 1e3) / 1e9
+        v["roofline_frac"] = kernel_time(v) / (v["avg_ms"] / 1e3)
 
     # per-step distribution (a second run of the same steps, one event pair per step)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
@@ -712,8 +717,7 @@ def main() -> int:
     copy_bw = copy_bandwidth()
 
     def t_star(bw):
-        return 1e3 * sum(v["launches_per_step"] * max(v["bytes"] / bw, (v["ops"] or 0) / INT32_PEAK)
-                         for v in kinfo.values())
+        return 1e3 * sum(v["launches_per_step"] * kernel_time(v, bw) for v in kinfo.values())
     path = {"t_star_ms": t_star(HBM_PEAK), "frac": t_star(HBM_PEAK) / ms,
             "t_star_measured_copy_ms": t_star(copy_bw), "frac_measured_copy": t_star(copy_bw) / ms,
             "copy_GBps": copy_bw / 1e9, "alu_peak_Tops": INT32_PEAK / 1e12}

@@ -69,6 +69,8 @@ zpm_plan = _sig("zpm_plan", ctypes.c_int,
                 [c_i64, c_i32, c_i64, c_i32, c_i32, c_i32, ctypes.POINTER(PlanInfo)])
 zpm_prime = _sig("zpm_prime", ctypes.c_int,
                  [c_i32, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)])
+zpm_crt_matrix = _sig("zpm_crt_matrix", ctypes.c_int,
+                      [c_i32, ctypes.POINTER(ctypes.c_int8), c_i64, ctypes.POINTER(c_i32)])
 zpm_create = _sig("zpm_create", ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.c_int])
 zpm_destroy = _sig("zpm_destroy", None, [c_vp])
 zpm_mul = _sig("zpm_mul", ctypes.c_int,
@@ -241,7 +243,7 @@ EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime
            "zpm_mul_operand", "zpm_operand_info", "zpm_operand_destroy", "zpm_mul_kronecker",
            "zpm_kronecker_plan", "zpm_plan_p64", "zpm_prime64", "zpm_mul_p64",
            "zpm_noalloc_max_bytes", "zpm_mul_noalloc", "zpm_gfp_prime", "zpm_gfp_root",
-           "zpm_plan_gfp", "zpm_mul_gfp", "zpm_butterfly_ceiling"]
+           "zpm_plan_gfp", "zpm_mul_gfp", "zpm_butterfly_ceiling", "zpm_crt_matrix"]
 
 
 class ZpmError(RuntimeError):

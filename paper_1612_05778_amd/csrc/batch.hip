@@ -194,9 +194,7 @@ size_t stage_lds(const Plan &pl, int kind, int pass) {
                          : sizeof(uint32_t) * (size_t)4 * pl.K << pl.logL1;
     case SK_RECOVER: {
       const int nw32 = 2 * ((pl.nout_bits + 63) / 64);
-      return sizeof(uint64_t) * ((size_t)nw32 << pl.log_ti_out) +
-             sizeof(uint32_t) * ((size_t)((pl.np + 2) & ~1) * pl.np + ((3 * pl.np + 1) & ~1)) +
-             sizeof(double) * pl.np;
+      return recover_lds_bytes(pl.np, pl.K, pl.M, nw32, pl.log_ti_out);
     }
     default:
       return 0;

@@ -273,6 +273,19 @@ int zpm_prime(int32_t k, uint32_t *p, uint32_t *root) {
   return ZPM_OK;
 }
 
+int zpm_crt_matrix(int32_t np, int8_t *out, int64_t cap, int32_t *tiles) {
+  if (np < 1 || np > CRT_MFMA_NP || !out || !tiles) return ZPM_EINVAL;
+  const int TN = crt_tiles(np);
+  const int64_t bytes = (int64_t)TN * CRT_STEPS * 64 * 16;
+  if (cap < bytes) return ZPM_EINVAL;
+  PlanDev h;
+  std::memset(&h, 0, sizeof(h));
+  crt_constants(np, h);
+  std::memcpy(out, h.crt_afrag, (size_t)bytes);   // tiles are the array's leading index
+  *tiles = TN;
+  return ZPM_OK;
+}
+
 int zpm_device_limits(int device, int32_t *ncu, int64_t *lds_per_block, int64_t *lds_per_cu) {
   if (!ncu || !lds_per_block || !lds_per_cu) return ZPM_EINVAL;
   int v = 0;

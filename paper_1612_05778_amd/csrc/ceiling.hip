@@ -52,7 +52,7 @@ extern "C" int zpm_butterfly_ceiling(int device, int32_t iters, double *bfly_per
   const uint32_t p = T[0].p;
   const uint32_t wv = T[0].root % p;
   const uint2 w = make_uint2(wv, shoup(wv, p));
-  hipEvent_t e0, e1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = ZPM_OK;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = ZPM_EDEVICE;
   float ms = 0;
@@ -65,8 +65,8 @@ extern "C" int zpm_butterfly_ceiling(int device, int32_t iters, double *bfly_per
         hipGetLastError() != hipSuccess)
       rc = ZPM_EDEVICE;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(sink);
   if (rc != ZPM_OK) return rc;
   *bfly_per_s = (double)blocks * BLOCK * 8.0 * iters / (ms / 1e3);

@@ -249,9 +249,7 @@ hipError_t launch_recover(const Plan &pl, const DevState &ds, uint64_t *out, int
   const int nw32 = 2 * ((pl.nout_bits + 63) / 64);
   const int logTI = pl.log_ti_out;
   const int64_t blocks = xcd_grid((pl.nout + (1 << logTI) - 1) >> logTI);
-  const size_t lds = sizeof(uint64_t) * ((size_t)nw32 << logTI) +
-                     sizeof(uint32_t) * ((size_t)((pl.np + 2) & ~1) * pl.np + ((3 * pl.np + 1) & ~1)) +
-                     sizeof(double) * pl.np;
+  const size_t lds = recover_lds_bytes(pl.np, pl.K, pl.M, nw32, logTI);
 #define ZPM_REC(NP_)                                                                           \
   case NP_:                                                                                    \
     hipLaunchKernelGGL(k_recovering_product<NP_>, dim3((unsigned)blocks), dim3(BLOCK), lds, st, \

@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <vector>
+#include <cstdlib>
 
 namespace zpm {
 
@@ -180,6 +182,62 @@ bool primes_cover(int np, int64_t d, int64_t K, int64_t M) {
   return false;   // strict inequality required
 }
 
+// Balanced base-256 digits d_n in [-128, 127] of x = sign * |x| (|x| little-endian 32-bit
+// words), nd of them; false if x does not fit.  For x < 0 the digits of |x| are taken in
+// [-127, 128] and negated.
+static bool balanced_bytes(const uint32_t *mag, int nw, int sign, int nd, int8_t *out) {
+  int carry = 0;
+  for (int n = 0; n < nd; ++n) {
+    const int byte = n < 4 * nw ? (int)((mag[n >> 2] >> (8 * (n & 3))) & 255u) : 0;
+    int v = byte + carry;
+    const bool wrap = sign > 0 ? v >= 128 : v > 128;
+    carry = wrap ? 1 : 0;
+    if (wrap) v -= 256;
+    out[n] = (int8_t)(sign > 0 ? v : -v);
+  }
+  if (carry) return false;
+  for (int n = nd; n < 4 * nw; ++n)
+    if ((mag[n >> 2] >> (8 * (n & 3))) & 255u) return false;
+  return true;
+}
+
+// The CRT sum c = sum_k y_k (P / p_k) - t P as an int8 matrix product.  Each term (y_k
+// centred in (-p_k/2, p_k/2), and t, |t| <= np/2) is split into balanced signed bytes,
+// the slots (term, a) with a < 4 (t uses a = 0 only); each constant P/p_k and -P is
+// written in balanced bytes too, and A[n][(term, a)] = digit n - a of the term's
+// constant, so that c = sum_n 2^(8n) sum_slot A[n][slot] y_slot.  Rows are placed so that
+// lane group g of the product's output holds digits 4 TN g + 4 T + i (tile T, row i),
+// i.e. the consecutive words TN g .. TN g + TN - 1 of the value.
+static void crt_matrix_constants(int np, const uint32_t *P, const uint32_t (*Q)[MAXW],
+                                 PlanDev &pd) {
+  static_assert(crt_tiles(CRT_MFMA_NP) <= CRT_TILES, "CRT tiles");
+  static_assert((CRT_MFMA_NP + 1 + 15) / 16 <= CRT_STEPS, "CRT steps");
+  std::memset(pd.crt_afrag, 0, sizeof(pd.crt_afrag));
+  if (np > CRT_MFMA_NP) return;
+  const int TN = crt_tiles(np), ND = 16 * TN;
+  std::vector<int8_t> dig((size_t)(np + 1) * ND, 0);
+  // a constant's digit b meets byte a < 4 at row b + a: its digits must end 3 rows early
+  for (int k = 0; k < np; ++k)
+    if (!balanced_bytes(Q[k], MAXW, 1, ND - 3, &dig[(size_t)k * ND])) std::abort();
+  if (!balanced_bytes(P, MAXW, -1, ND, &dig[(size_t)np * ND])) std::abort();
+  auto A = [&](int n, int slot) -> int {
+    const int term = slot >> 2, a = slot & 3;
+    if (term > np || (term == np && a != 0) || n - a < 0) return 0;
+    return dig[(size_t)term * ND + (n - a)];
+  };
+  auto row_digit = [&](int T, int m) { return 4 * TN * (m >> 2) + 4 * T + (m & 3); };
+  for (int T = 0; T < TN; ++T)
+    for (int st = 0; st < CRT_STEPS; ++st)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int n = row_digit(T, lane & 15);
+        for (int b = 0; b < 16; ++b) {
+          const int slot = 64 * st + 16 * (lane >> 4) + b;
+          pd.crt_afrag[T][st][lane][b >> 2] |= (uint32_t)(uint8_t)(int8_t)A(n, slot)
+                                               << (8 * (b & 3));
+        }
+      }
+}
+
 void crt_constants(int np, PlanDev &pd) {
   const auto &T = prime_table();
   uint32_t P[MAXW];
@@ -199,6 +257,7 @@ void crt_constants(int np, PlanDev &pd) {
     pd.crt_inv[k] = make_uint2(inv, shoup(inv, T[k].p));
     pd.crt_rcp[k] = 1.0 / (double)T[k].p;
   }
+  crt_matrix_constants(np, pd.crt_p, pd.crt_q, pd);
 }
 
 void scale_constants(int np, int K, int M, int logL, PlanDev &pd) {

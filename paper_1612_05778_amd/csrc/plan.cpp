@@ -116,10 +116,13 @@ static bool finish(Plan &pl) {
   const int64_t J = 2 * (int64_t)pl.K - 1;
   const int64_t nw32 = 2 * (int64_t)((pl.nout_bits + 63) / 64);
   lt = 6;
-  const int64_t crt_words = (int64_t)(pl.np + 1) * pl.W + pl.W + 5 * pl.np + 2;
   while (lt > 0 && ((nw32 << lt) * 2 > 12288 || (J << lt) > 1024)) --lt;
   while (lt > 2 && (J << (lt - 1)) >= 192) --lt;
-  if ((nw32 << lt) * 2 + crt_words > LDS_WORDS) return false;
+  // the CRT's matrix form stages each value's terms in LDS (20 KiB at most) and may touch
+  // 4 TN + 1 words past a row: such a recovery may take up to 96 of the 160 KiB a gfx950
+  // workgroup can address
+  const size_t lds_cap = pl.np <= CRT_MFMA_NP ? 96 * 1024 : 4 * (size_t)LDS_WORDS;
+  if (recover_lds_bytes(pl.np, pl.K, pl.M, (int)nw32, lt) > lds_cap) return false;
   pl.log_ti_out = lt;
   pl.ws_words = (int64_t)pl.np * 2 * pl.K << pl.logL;
   return true;

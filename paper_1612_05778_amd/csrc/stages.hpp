@@ -929,6 +929,156 @@ __device__ __forceinline__ int fcompose(int g, int f) {   // g after f
   return r;
 }
 
+typedef int crt_i32x4 __attribute__((ext_vector_type(4)));
+
+// The CRT of each c_{i,j} on the int8 matrix cores, added at bit M j into S (np <=
+// CRT_MFMA_NP).  Per wave and 64 values (one per lane): each lane reads its value's np
+// residues, takes y_k = r_k (P/p_k)^{-1} mod p_k centred in (-p_k/2, p_k/2) and
+// t = round(sum_k y_k / p_k), so that c_{i,j} = sum_k y_k (P/p_k) - t P, and stages the
+// terms as balanced signed bytes in LDS.  (|c_{i,j}| < P/4 leaves t a margin of 1/4,
+// far above the error of the single-precision sum.)  Then four products of 16 values
+// each: D = A Y with A the constants' digit matrix (built on the host in fragment order),
+// whose 16-digit tiles T give lane group g the digits 4 TN g + 4 T + i of value
+// v = lane mod 16.  The lane folds its 4 TN digit sums into TN consecutive 32-bit words
+// plus a signed carry, exactly its share of c_{i,j}, and adds them, shifted by M j bits,
+// into its row of S (RS words, with room for every word a lane group touches; S[-1]
+// exists).  Values past the tile's end stage zero terms and add zeros to row 0.
+// The residues of each wave's first 64 values and the A fragments are loaded before the
+// workgroup's set-up (constants to LDS, S cleared, barrier), whose time they overlap.
+// cw: per prime (c_k, its Shoup companion, p_k, 1/p_k as float bits).
+template <int NP>
+struct CrtMatrix {
+  static constexpr int NT = NP + 1;
+  static constexpr int YW = crt_stage_words(NP);
+  static constexpr int NS = (NT + 15) / 16;
+  static constexpr int TN = crt_tiles(NP);
+  static constexpr int CH = 6;        // terms whose constants are read from LDS together
+  static_assert(NS <= CRT_STEPS && TN <= CRT_TILES, "CRT matrix shape");
+  crt_i32x4 af[TN][NS];
+  uint32_t pre[NP];
+
+  __device__ __forceinline__ void prefetch(const uint32_t *__restrict__ X, int64_t L, int32_t K,
+                                           int32_t logTI, int ti, int64_t i0,
+                                           const PlanDev *__restrict__ pd) {
+    const int lane = threadIdx.x & 63;
+    const int TI = 1 << logTI;
+    const int items = (2 * K - 1) << logTI;
+    const int item = (threadIdx.x & ~63) + lane;
+    const int il = item & (TI - 1), j = item >> logTI;
+    const bool ok = item < items && il < ti;
+    const int64_t off = (int64_t)j * L + i0 + il;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) pre[k] = ok ? X[(int64_t)k * 2 * K * L + off] : 0u;
+#pragma unroll
+    for (int T = 0; T < TN; ++T)
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(&pd->crt_afrag[T][st][lane][0]);
+        af[T][st] = crt_i32x4{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+      }
+  }
+
+  __device__ __forceinline__ void run(uint64_t *S, int32_t RS, uint32_t *Y, const uint4 *cw,
+                                      const uint32_t *__restrict__ X, int64_t L, int32_t K,
+                                      int32_t M, int32_t logTI, int ti, int64_t i0) {
+  const int TI = 1 << logTI;
+  const int J = 2 * K - 1;
+  const int64_t twoK = 2 * (int64_t)K;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, v = lane & 15;
+  uint32_t *Yw = Y + wave * 64 * YW;
+  const int items = J << logTI;
+  for (int base = wave * 64; base < items; base += BLOCK) {   // uniform per wave
+    {
+      const int item = base + lane;
+      const int il = item & (TI - 1), j = item >> logTI;
+      const bool ok = item < items && il < ti;
+      const int64_t off = (int64_t)j * L + i0 + il;
+      uint32_t y[YW];
+      if (base == wave * 64) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) y[k] = pre[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) y[k] = ok ? X[(int64_t)k * twoK * L + off] : 0u;
+      }
+      float f = 0.0f;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        if (k % CH == 0) asm volatile("" ::: "memory");   // bounds the constants in flight
+        const uint4 c = cw[k];
+        const uint32_t u = mul_shoup(y[k], make_uint2(c.x, c.y), c.z);
+        const int32_t yc = u > (c.z >> 1) ? (int32_t)(u - c.z) : (int32_t)u;
+        f = fmaf((float)yc, __uint_as_float(c.w), f);
+        // |yc| < 2^30: the bytes of yc + 0x80808080 are its balanced digits plus 128
+        y[k] = ((uint32_t)yc + 0x80808080u) ^ 0x80808080u;
+      }
+      y[NP] = (uint32_t)__float2int_rn(f) & 0xFFu;
+#pragma unroll
+      for (int k = NP + 1; k < YW; ++k) y[k] = 0;
+#pragma unroll
+      for (int q = 0; q < YW / 4; ++q)
+        *reinterpret_cast<uint4 *>(&Yw[lane * YW + 4 * q]) =
+            make_uint4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+      const int vi = 16 * r + v;
+      crt_i32x4 acc[TN];
+#pragma unroll
+      for (int T = 0; T < TN; ++T) acc[T] = crt_i32x4{0, 0, 0, 0};
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+        const int w0 = 16 * st + 4 * g;
+        uint4 q = make_uint4(0u, 0u, 0u, 0u);
+        if (w0 < YW) q = *reinterpret_cast<const uint4 *>(&Yw[vi * YW + w0]);
+        const crt_i32x4 bf{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+#pragma unroll
+        for (int T = 0; T < TN; ++T)
+          acc[T] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[T][st], bf, acc[T], 0, 0, 0);
+      }
+      const int item = base + vi;
+      const bool ok = item < items && (item & (TI - 1)) < ti;
+      const int il = ok ? item & (TI - 1) : 0, j = ok ? item >> logTI : 0;
+      // c_{i,j} 2^(M j) = c_{i,j} 2^s 2^(32 q) with s in 1..32 (q = -1 for j = 0: word -1
+      // of a row is the end of the previous row or, for row 0, a spare word, and only
+      // receives the zero below the value's first word)
+      const int64_t bit = (int64_t)M * j;
+      // M j < 2 N, and convert-in's LDS tile keeps N below 2^19 bits: a 32-bit word index
+      const int q = (int)((bit - 1) >> 5);
+      const uint32_t rsh = (uint32_t)(32 * (q + 1) - bit);  // 32 - s, in 0..31
+      unsigned long long *Sw =
+          reinterpret_cast<unsigned long long *>(S + (int64_t)il * RS + q + TN * g);
+      // the words of sum_i D[4 T + i] 2^(8 i) plus the carry, in 32-bit steps (every
+      // digit sum is below 2^21 in magnitude, so t1, t2, t3 fit 31 bits)
+      int32_t c = 0;
+      uint32_t prev = 0;
+#pragma unroll
+      for (int T = 0; T < TN; ++T) {
+        const int32_t t1 = acc[T][0] + c + (int32_t)((uint32_t)acc[T][1] << 8);
+        const int32_t t2 = (t1 >> 16) + acc[T][2];
+        const int32_t t3 = t2 + (int32_t)((uint32_t)acc[T][3] << 8);
+        const uint32_t wd = __builtin_amdgcn_perm((uint32_t)t3, (uint32_t)t1, 0x05040100u);
+        c = t3 >> 16;
+        // bits 32 - s .. 63 - s of (wd, prev): the word shifted left by s, with the
+        // previous word's top s bits below
+        atomicAdd(&Sw[T], (unsigned long long)__builtin_amdgcn_alignbit(wd, prev, rsh));
+        prev = wd;
+      }
+      // the lane's carry out (a signed multiple of 2^(32 TN)) with the last word's top bits
+      atomicAdd(&Sw[TN],
+                (unsigned long long)((int64_t)(((uint64_t)(int64_t)c << 32) | prev) >> rsh));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+  }
+};
+
 // NP = np exactly and W = NP words per CRT value (32 NP >= log2 P + 1 since every
 // prime is below 2^31).  Per workgroup: TI consecutive coefficients; S holds their
 // output words as 64-bit partial sums.
@@ -937,35 +1087,52 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
                              int64_t L, int32_t K, int32_t M, int64_t nout, int32_t nw32,
                              int32_t wc, int32_t logTI, const PrimeDev *__restrict__ primes,
                              const PlanDev *__restrict__ pd, uint64_t *__restrict__ out) {
-  // S: TI x nw32 partial sums, then the CRT constants
   constexpr int W = NP;
   constexpr int NT = NP + 1;          // terms of each word: the np residues, then t
   constexpr int NPE = (NT + 1) & ~1;  // terms padded to a pair
+  constexpr bool MF = NP <= CRT_MFMA_NP;
   const int TI = 1 << logTI;
   const int J = 2 * K - 1;            // c_{i,2K-1} = 0
   const int64_t twoK = 2 * (int64_t)K;
   const int64_t i0 = tile_id << logTI;
   if (i0 >= nout) return;
   const int ti = (int)min<int64_t>(TI, nout - i0);
-  // CRT constants, read by every lane: as [u][k] (W x NPE words) P/p_k for k < np and,
-  // at k = np, 2^(32 W) - P (P is odd, so its negation is ~P + 1 = -P[0], ~P[1], ...);
-  // per prime (c_k Shoup pair, p_k), and 1/p_k
-  uint32_t *cq = reinterpret_cast<uint32_t *>(S + ((int64_t)nw32 << logTI));
-  uint32_t *ci = cq + NPE * W;
+  // S: TI rows of RS partial sums (nw32 output words and, in the matrix form, room for
+  // every word the CRT's lane groups touch), then either the staged CRT terms and per
+  // prime (c_k Shoup pair, p_k, 1/p_k in single precision) (matrix form), or, as [u][k]
+  // (W x NPE words), P/p_k for k < np and, at k = np, 2^(32 W) - P (P is odd, so its
+  // negation is ~P + 1 = -P[0], ~P[1], ...), then per prime (c_k Shoup pair, p_k) and 1/p_k
+  CrtMatrix<MF ? NP : 1> cm;
+  if constexpr (MF) cm.prefetch(X, L, K, logTI, ti, i0, pd);
+  const int RS = recover_row_words(NP, K, M, nw32);
+  uint64_t *const S0 = S;             // a spare word, then the rows
+  S = S0 + 1;
+  uint32_t *cq = reinterpret_cast<uint32_t *>(S0 + ((((int64_t)RS << logTI) + 2) & ~(int64_t)1));
+  uint32_t *ci = cq + (MF ? BLOCK * crt_stage_words(NP) : NPE * W);
   double *cr = reinterpret_cast<double *>(ci + ((3 * NP + 1) & ~1));
-  for (int idx = threadIdx.x; idx < NPE * W; idx += BLOCK) {
-    const int u = idx / NPE, kk = idx - u * NPE;
-    cq[idx] = kk < NP ? pd->crt_q[kk][u]
-                      : kk == NP ? (u == 0 ? 0u - pd->crt_p[0] : ~pd->crt_p[u]) : 0u;
+  if constexpr (MF) {
+    uint4 *cw = reinterpret_cast<uint4 *>(ci);
+    for (int idx = threadIdx.x; idx < NP; idx += BLOCK)
+      cw[idx] = make_uint4(pd->crt_inv[idx].x, pd->crt_inv[idx].y, primes[idx].p,
+                           __float_as_uint((float)pd->crt_rcp[idx]));
+  } else {
+    for (int idx = threadIdx.x; idx < NPE * W; idx += BLOCK) {
+      const int u = idx / NPE, kk = idx - u * NPE;
+      cq[idx] = kk < NP ? pd->crt_q[kk][u]
+                        : kk == NP ? (u == 0 ? 0u - pd->crt_p[0] : ~pd->crt_p[u]) : 0u;
+    }
+    for (int idx = threadIdx.x; idx < NP; idx += BLOCK) {
+      ci[3 * idx] = pd->crt_inv[idx].x;
+      ci[3 * idx + 1] = pd->crt_inv[idx].y;
+      ci[3 * idx + 2] = primes[idx].p;
+      cr[idx] = pd->crt_rcp[idx];
+    }
   }
-  for (int idx = threadIdx.x; idx < NP; idx += BLOCK) {
-    ci[3 * idx] = pd->crt_inv[idx].x;
-    ci[3 * idx + 1] = pd->crt_inv[idx].y;
-    ci[3 * idx + 2] = primes[idx].p;
-    cr[idx] = pd->crt_rcp[idx];
-  }
-  for (int idx = threadIdx.x; idx < ti * nw32; idx += BLOCK) S[idx] = 0;
+  for (int idx = threadIdx.x; idx < ti * RS; idx += BLOCK) S[idx] = 0;
   __syncthreads();
+  if constexpr (MF) {
+    cm.run(S, RS, cq, reinterpret_cast<const uint4 *>(ci), X, L, K, M, logTI, ti, i0);
+  } else {
   // ---- CRT of each c_{i,j}, then add c_{i,j} 2^(M j) into the output words ----
   for (int idx = threadIdx.x; idx < (J << logTI); idx += BLOCK) {
     const int il = idx & (TI - 1), j = idx >> logTI;
@@ -993,7 +1160,7 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
     // M j < 2 N, and convert-in's LDS tile keeps N below 2^19 bits: a 32-bit word index
     const int q0 = (int)(bit >> 5);
     const int sh = (int)(bit & 31);
-    uint64_t *Si = S + (int64_t)il * nw32;
+    uint64_t *Si = S + (int64_t)il * RS;
     uint64_t lo = 0;
     uint32_t prev = 0;
 #pragma unroll
@@ -1017,13 +1184,14 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
     const int64_t top = sh ? (int64_t)((int32_t)prev >> (32 - sh)) : -(int64_t)(prev >> 31);
     if (q0 + W < nw32 && top) atomicAdd((unsigned long long *)&Si[q0 + W], (unsigned long long)top);
   }
+  }
   __syncthreads();
   // ---- carries ----
   if (nw32 <= 8 * TI) {
     // short outputs: one lane per coefficient, its words in order (eight LDS reads in
     // flight ahead of the carry chain)
     for (int il = threadIdx.x; il < ti; il += BLOCK) {
-      uint64_t *Si = S + (int64_t)il * nw32;
+      uint64_t *Si = S + (int64_t)il * RS;
       int64_t carry = 0;
       for (int w0 = 0; w0 < nw32; w0 += 8) {
         uint64_t v[8];
@@ -1043,12 +1211,87 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
     }
     return;
   }
-  // long outputs: one wave per coefficient
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (nw32 <= 512) {
+    // outputs of at most 512 words: one wave per coefficient, an even number (at most 8)
+    // of consecutive words per lane held in registers, so that each lane also writes its
+    // own output words
+    const int per = 2 * ((nw32 + 127) >> 7);
+    const int w_lo = min(lane * per, nw32), w_hi = min(w_lo + per, nw32);
+    for (int il = wave; il < ti; il += BLOCK / 64) {
+      const uint64_t *Si = S + (int64_t)il * RS;
+      uint32_t wv[8];
+      int64_t carry = 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = u < per && w_lo + u < w_hi;
+        const int64_t tsum = (in ? (int64_t)Si[w_lo + u] : 0) + carry;
+        wv[u] = in ? (uint32_t)tsum : 0u;
+        if (in) carry = tsum >> 32;
+      }
+      // the lane below's carry, then this lane's carry out x in {-1, 0, 1}
+      int64_t x = __shfl_up(carry, 1, 64);
+      if (lane == 0) x = 0;
+      bool allz = true, allo = true;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (u < per && w_lo + u < w_hi) {
+          const int64_t tsum = (int64_t)wv[u] + x;
+          wv[u] = (uint32_t)tsum;
+          x = tsum >> 32;
+          allz = allz && wv[u] == 0u;
+          allo = allo && wv[u] == 0xFFFFFFFFu;
+        }
+      }
+      // as in the general case below: only when some lane passes a carry on does it
+      // ripple through runs of all-zero or all-one lanes
+      if (__any(w_lo < w_hi && w_hi < nw32 && x != 0)) {
+        int code;
+        if (w_lo >= w_hi) {
+          code = (0) | (1 << 2) | (2 << 4);
+        } else {
+          const int gg = (int)x;
+          const int fm = gg + (allz ? -1 : 0), f0 = gg, fp = gg + (allo ? 1 : 0);
+          code = (fm + 1) | ((f0 + 1) << 2) | ((fp + 1) << 4);
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int other = __shfl_up(code, off, 64);
+          if (lane >= off) code = fcompose(code, other);
+        }
+        const int prevc = __shfl_up(code, 1, 64);
+        int y = lane == 0 ? 0 : fapply(prevc, 0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (u < per && w_lo + u < w_hi) {
+            const int64_t tsum = (int64_t)wv[u] + y;
+            wv[u] = (uint32_t)tsum;
+            y = (int)(tsum >> 32);
+          }
+        }
+      }
+      // the top word's sign fills the output words above the product's width
+      const int top_lane = (nw32 - 1) / per;
+      uint32_t topv = 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (w_lo + u == nw32 - 1) topv = wv[u];
+      topv = __shfl(topv, top_lane, 64);
+      const uint64_t fill = (int32_t)topv < 0 ? ~0ull : 0ull;
+      uint64_t *o = out + (i0 + il) * (int64_t)wc;
+#pragma unroll
+      for (int u = 0; u < 8; u += 2)
+        if (u < per && w_lo + u < w_hi && (w_lo >> 1) + (u >> 1) < wc)
+          o[(w_lo >> 1) + (u >> 1)] = (uint64_t)wv[u] | ((uint64_t)wv[u + 1] << 32);
+      for (int u = (nw32 >> 1) + lane; u < wc; u += 64) o[u] = fill;
+    }
+    return;
+  }
+  // long outputs: one wave per coefficient
   const int per = (nw32 + 63) >> 6;
   const int w_lo = min(lane * per, nw32), w_hi = min(w_lo + per, nw32);
   for (int il = wave; il < ti; il += BLOCK / 64) {
-    uint64_t *Si = S + (int64_t)il * nw32;
+    uint64_t *Si = S + (int64_t)il * RS;
     int64_t carry = 0;
     for (int w = w_lo; w < w_hi; ++w) {
       const int64_t tsum = (int64_t)Si[w] + carry;

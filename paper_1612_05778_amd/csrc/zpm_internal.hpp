@@ -1,5 +1,6 @@
 // Internal structures shared by the host planner and the gfx950 kernels.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
 
@@ -14,6 +15,17 @@ constexpr int MAXW = 48;                // 32-bit words of a CRT value (> 31*MAX
 constexpr int BLOCK = 256;              // threads per workgroup of every kernel
 constexpr int LDS_WORDS = 16384;        // 64 KiB of LDS staging per workgroup
 constexpr int MAX_COL_PASSES = 4;
+// The recovery's CRT runs on int8 matrix cores up to this prime count: np + 1 terms of 4
+// bytes in CRT_STEPS steps of 64 slots, values of up to 16 CRT_TILES signed bytes.
+constexpr int CRT_MFMA_NP = 18;
+constexpr int CRT_STEPS = 2;
+constexpr int CRT_TILES = 5;
+// Words each recovery value stages in LDS for the matrix cores: its np terms and t,
+// rounded to a 16-byte fragment.
+constexpr int crt_stage_words(int np) { return 4 * ((np + 4) / 4); }
+// 16-digit tiles of one CRT value, each lane group of the matrix product holding one
+// 32-bit word of each: 4 TN words >= the bytes of P plus the three bytes of the offsets.
+constexpr int crt_tiles(int np) { return (4 * np + 8 + 15) / 16; }
 
 // Prime counts with compiled kernels (per-prime loops are unrolled at compile time);
 // a plan's prime count is rounded up to one of these.
@@ -45,6 +57,10 @@ struct PlanDev {
   double crt_rcp[MAXNP];   // 1/p_k
   uint32_t crt_q[MAXNP][MAXW];  // P/p_k, little-endian 32-bit words
   uint32_t crt_p[MAXW];         // P
+  // The CRT sum as an int8 matrix product (np <= CRT_MFMA_NP): the A operand, digits n
+  // by byte slots (term, a), in each lane's fragment order (tile T of 16 digits, step s
+  // of 64 slots, lane, 16 signed bytes).
+  uint32_t crt_afrag[CRT_TILES][CRT_STEPS][64][4];
 };
 
 // A factor of the y-transform done by a strided column pass: index
@@ -62,6 +78,29 @@ struct ColPass {
 //   CM_WITH_SPECTRUM  a * b from a's rows and b's spectra written earlier by
 //                     CM_SPECTRUM for the same plan.
 enum ConvMode : int32_t { CM_PRODUCT = 0, CM_SQUARE = 1, CM_SPECTRUM = 2, CM_WITH_SPECTRUM = 3 };
+
+// 64-bit partial sums per coefficient row of a recovery workgroup: the nw32 output words
+// and, in the CRT's matrix form, the words past them that its lane groups may touch
+// (value j starts at word floor(M j / 32); lane group 3's carry lands 4 TN words on).
+// Those extra words collect nothing the output needs.
+__host__ __device__ inline int recover_row_words(int np, int K, int M, int nw32) {
+  if (np > CRT_MFMA_NP) return nw32;
+  const int need = (int)(((int64_t)M * (2 * K - 2)) >> 5) + 4 * crt_tiles(np) + 1;
+  return need > nw32 ? need : nw32;
+}
+
+// LDS of one recovery workgroup: a spare word, 2^log_ti coefficient rows of partial sums
+// (rounded to 16 bytes), then either
+// the CRT's staged terms and 4 words of constants per prime (matrix form), or its word
+// table and 3 words and a double per prime.
+inline size_t recover_lds_bytes(int np, int K, int M, int nw32, int log_ti) {
+  // a spare word before the rows, rounded to 16 bytes
+  size_t b = sizeof(uint64_t) * ((((size_t)recover_row_words(np, K, M, nw32) << log_ti) + 2) & ~(size_t)1);
+  if (np <= CRT_MFMA_NP)
+    return b + sizeof(uint32_t) * ((size_t)BLOCK * crt_stage_words(np) + 4 * (size_t)np);
+  b += sizeof(uint32_t) * (size_t)((np + 2) & ~1) * np;
+  return b + sizeof(uint32_t) * ((3 * np + 1) & ~1) + sizeof(double) * np;
+}
 
 struct Plan {
   // caller-visible problem

@@ -18,7 +18,10 @@ whose first stage is the twist):
   the Chinese remaindering of Section 4): 6 per residue (its Shoup product with
   (P/p_k)^{-1}), 2 per word of each of the np products y_k (P/p_k) summed over W
   words (multiply-add and carry), and 4 per word for the quotient correction and
-  the shifted accumulation at 2^(Mj).
+  the shifted accumulation at 2^(Mj).  Up to 18 primes the kernel forms the sum
+  sum_k y_k (P/p_k) - t P on the int8 matrix cores: each 32 x 32-bit word product
+  is 16 byte products, 2 int8 operations each, counted against the int8 matrix
+  peak instead of the int32 one.
 
 HBM bytes are the compulsory reads and writes of each launch (every element in
 and out once).
@@ -32,6 +35,8 @@ OPS_POINTWISE = 13
 OPS_TWIDDLE = 6
 INT32_PEAK = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes x 2.4 GHz: int32 VALU op/s
 HBM_PEAK = 8.0e12                   # bytes/s
+MFMA_I8_PEAK = 5.0e15               # dense int8 matrix operations/s (published)
+CRT_MFMA_NP = 18                    # prime counts whose CRT sum runs on the matrix cores
 
 
 def kernel_work(plan: dict, name: str) -> dict:
@@ -75,9 +80,19 @@ def kernel_work(plan: dict, name: str) -> dict:
         wc = (plan["nout_bits"] + 63) // 64
         W = plan["W"]
         nvals = (2 * K - 1) * nout
-        return {"ops": nvals * (6 * np_ + 2 * np_ * W + 4 * W),
-                "bytes": 4 * np_ * (2 * K - 1) * nout + 8 * nout * wc}
+        byts = 4 * np_ * (2 * K - 1) * nout + 8 * nout * wc
+        if np_ <= CRT_MFMA_NP:
+            return {"ops": nvals * (6 * np_ + 4 * W), "mfma_ops": nvals * np_ * W * 32,
+                    "bytes": byts}
+        return {"ops": nvals * (6 * np_ + 2 * np_ * W + 4 * W), "bytes": byts}
     return {"ops": 0, "bytes": 0}
+
+
+def kernel_time(w: dict, bw: float = None, alu: float = None) -> float:
+    """Roofline time (s) of one launch: the largest of its HBM, int32 VALU and int8
+    matrix times."""
+    return max(w["bytes"] / (bw or HBM_PEAK), (w.get("ops") or 0) / (alu or INT32_PEAK),
+               (w.get("mfma_ops") or 0) / MFMA_I8_PEAK)
 
 
 KERNELS = ("bivariate_representation", "col_pass_fwd", "convolve_rows", "col_pass_inv",
@@ -95,15 +110,14 @@ def launches(plan: dict, name: str, square: bool = False) -> int:
 
 def t_star(plan: dict, bw: float = None, alu: float = None, square: bool = False) -> float:
     """Roofline time (s) of one product: the sum over its launches of
-    max(bytes / bandwidth, ops / ALU rate)."""
+    max(bytes / bandwidth, ops / ALU rate, int8 matrix ops / matrix rate)."""
     bw = bw or HBM_PEAK
     alu = alu or INT32_PEAK
     t = 0.0
     for k in KERNELS:
         n = launches(plan, k, square)
         if n:
-            w = kernel_work(plan, k)
-            t += n * max(w["bytes"] / bw, w["ops"] / alu)
+            t += n * kernel_time(kernel_work(plan, k), bw, alu)
     return t
 
 
