@@ -167,6 +167,17 @@ def batch_leg(ctx, reps: int) -> dict:
     torch.cuda.synchronize()
     same = bool(torch.equal(pb.outputs, ref))
     batch_ms = timed(batched, reps)
+    print("[bench] batch leg: timing the persistent launch", file=sys.stderr, flush=True)
+    pb.outputs.zero_()
+
+    def persistent():
+        nat.check(nat.zpm_mul_batch(ctx.handle, pb.jobs, pb.n, nat.ZPM_BATCH_PERSISTENT, h),
+                  "zpm_mul_batch")
+
+    persistent()
+    torch.cuda.synchronize()
+    same_persistent = bool(torch.equal(pb.outputs, ref))
+    persistent_ms = timed(persistent, reps)
     nl = nat.c_i64()
     nat.zpm_batch_schedule(pb.jobs, pb.n, 0, ctypes.byref(nl), None, 0)
     ts = sum(t_star_of(pb.jobs[i].da, pb.jobs[i].Na, pb.jobs[i].db, pb.jobs[i].Nb)
@@ -175,6 +186,8 @@ def batch_leg(ctx, reps: int) -> dict:
             "value": bits / (batch_ms / 1e3), "ms": batch_ms, "launches": nl.value,
             "plain_value": bits / (plain_ms / 1e3), "plain_ms": plain_ms,
             "speedup": plain_ms / batch_ms, "identical_to_plain": same,
+            "persistent_ms": persistent_ms, "persistent_value": bits / (persistent_ms / 1e3),
+            "persistent_identical_to_plain": same_persistent,
             "t_star_ms": ts, "roofline_frac": ts / batch_ms, "plain_roofline_frac": ts / plain_ms,
             "tune_s": tune_s, "tuned_classes": len(ctx.tune_table())}
 

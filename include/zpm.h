@@ -180,10 +180,12 @@ int zpm_mul_ex(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const ui
  * launch (a few launches per level, whatever the number of products).  Stream-ordered
  * like zpm_mul.  ZPM_BATCH_GRAPH captures the whole sequence (descriptor upload and
  * launches) in a HIP graph and replays it when the same job array is passed again.
- * ZPM_BATCH_PERSISTENT (every tile of every stage of every product in one persistent
- * launch, workgroups taking task numbers from a counter in stage order and waiting on
- * agent-scope stage counters) is not available in this build: the call returns
- * ZPM_ENOTIMPL.  Combined with ZPM_BATCH_GRAPH it is ZPM_EINVAL. */
+ * ZPM_BATCH_PERSISTENT runs every tile of every stage of every product in one
+ * persistent launch: a grid of resident workgroups takes task numbers from a counter in
+ * stage order and waits on per-product stage counters (agent-scope loads, bounded waits).
+ * The call waits for the device before it returns; if a wait exceeds its bound the
+ * launch stops and the call returns ZPM_EDEVICE.  Combined with ZPM_BATCH_GRAPH it is
+ * ZPM_EINVAL. */
 typedef struct zpm_job {
   const uint64_t *a;
   int64_t da;

@@ -511,10 +511,6 @@ extern "C" int zpm_mul_batch_ex(zpm_ctx *ctx, const zpm_job *jobs, int64_t n, in
                                 int32_t K, void *stream) {
   if (!ctx || n < 0 || (n > 0 && !jobs) || K < 0) return ZPM_EINVAL;
   if (flags != 0 && flags != ZPM_BATCH_GRAPH && flags != ZPM_BATCH_PERSISTENT) return ZPM_EINVAL;
-  // the persistent launch (Ctx::enqueue_persistent) is switched off: its first version
-  // never finished on the device (a lane-divergent inner loop the compiler built around
-  // its barrier, since restructured) and the restructured kernel has not run there yet
-  if (flags == ZPM_BATCH_PERSISTENT) return ZPM_ENOTIMPL;
   zpm::Ctx *cx = reinterpret_cast<zpm::Ctx *>(ctx);
   std::lock_guard<std::mutex> lock(cx->mu);
   if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;

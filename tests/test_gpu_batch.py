@@ -119,15 +119,6 @@ def test_batch_graph_back_to_back(ctx):
             assert np.array_equal(e, host(o)), f"back-to-back graph batch differs (rep {rep})"
 
 
-@pytest.mark.skip(reason="ZPM_BATCH_PERSISTENT is switched off: the first run of this kernel "
-                         "never finished on the GPU. Cause, found in its compiled code: the "
-                         "loop exit read from LDS was divergent to the compiler, whose "
-                         "structurizer built an inner loop around the barrier and the task in "
-                         "which lanes 1..63 of wave 0 re-ran the last task while lane 0, which "
-                         "writes the next one, waited outside it. The kernel is restructured "
-                         "(all lane-0 work in a called function, a scalar loop exit; checked "
-                         "by tests/test_persistent_isa.py on the CPU) but has not been run on "
-                         "the GPU again")
 def test_persistent_single_launch(ctx):
     """ZPM_BATCH_PERSISTENT: every stage of every product in one persistent launch, tasks
     taken from a ticket counter in stage order (its schedule is modelled on the CPU in
@@ -146,16 +137,14 @@ def test_persistent_single_launch(ctx):
         for i, (r, o) in enumerate(zip(ref, outs)):
             assert np.array_equal(r, host(o)), f"persistent product {i} differs (rep {rep})"
     check_all(prods, outs)
-    outs = ctx.mul_batch(items, persistent=True, K=2)
+    outs = ctx.mul_batch(items, persistent=True, K=4)
     ctx.sync()
     check_all(prods, outs)
 
 
-def test_persistent_flag_is_rejected(ctx):
+def test_persistent_flag_combination_is_rejected(ctx):
     from paper_1612_05778_amd import _native as nat
     jobs = (nat.Job * 1)()
-    assert nat.zpm_mul_batch_ex(ctx.handle, jobs, 0, nat.ZPM_BATCH_PERSISTENT, 0, None) == \
-        nat.ZPM_ENOTIMPL
     assert nat.zpm_mul_batch_ex(ctx.handle, jobs, 0, nat.ZPM_BATCH_PERSISTENT | nat.ZPM_BATCH_GRAPH,
                                 0, None) == nat.ZPM_EINVAL
 

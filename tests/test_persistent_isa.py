@@ -24,7 +24,8 @@ def kernel_asm(tmp_path, name):
     src = os.path.join(ROOT, "paper_1612_05778_amd", "csrc", "persistent.hip")
     out = tmp_path / "persistent.s"
     cmd = [HIPCC, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature",
-           "-Xclang", "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I",
+           "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form=true", "-I",
+           os.path.join(ROOT, "include"), "-I",
            os.path.join(ROOT, "paper_1612_05778_amd", "csrc"), "-x", "hip", "--cuda-device-only",
            "-S", src, "-o", str(out)]
     subprocess.run(cmd, check=True, capture_output=True)
