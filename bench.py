@@ -683,11 +683,11 @@ def main() -> int:
                        "timed_in": "timed region" if name == dom else "breakdown run"}
     d = kinfo[dom]
     from paper_1612_05778_amd import _native as nat
-    from paper_1612_05778_amd.workmodel import OPS_BFLY
+    from paper_1612_05778_amd.workmodel import OPS_BFLY_DIF as OPS_BFLY
     bfly = ctypes.c_double()
     nat.check(nat.zpm_butterfly_ceiling(0, 4096, ctypes.byref(bfly)), "zpm_butterfly_ceiling")
-    ceiling = {"kernel": "register-resident forward butterflies (add_mod, mul_shoup), 8 pairs per "
-                         "thread, 8 workgroups of 256 per CU",
+    ceiling = {"kernel": "register-resident forward butterflies (add_lz, mul_shoup_lz: values "
+                         "in [0, 2p)), 8 pairs per thread, 8 workgroups of 256 per CU",
                "butterflies_per_s": bfly.value,
                "int32_ops_per_s": bfly.value * OPS_BFLY,
                "vs_derived_peak": bfly.value * OPS_BFLY / INT32_PEAK}

@@ -55,9 +55,10 @@ extern "C" {
 typedef struct zpm_ctx zpm_ctx;
 
 /* Parameters the planner chose for a product (Section 2.3, DetermineBase and
- * RecoveryPrime): N padded to K*M, K limbs of M bits, np primes p_k < 2^31 with
- * prod p_k > 4 d K 2^(2M) (Relation (recoveryModulo) with the product of the
- * primes in the role of p), y-transform length L = 2^log2_L >= da + db - 1. */
+ * RecoveryPrime): N padded to K*M, K limbs of M bits, np primes p_k < 2^30 with
+ * P = prod p_k > 2 d K 2^(2M) (1 + 2^-12), d = min(da, db) (Relation (recoveryModulo)
+ * with the product of the primes in the role of p, for c_{i,j} itself, whose magnitude
+ * is below d K 2^(2M)), y-transform length L = 2^log2_L >= da + db - 1. */
 typedef struct zpm_plan_info {
   int64_t da, db;
   int32_t Na, Nb;
@@ -94,14 +95,14 @@ int zpm_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t 
 int zpm_prime(int32_t k, uint32_t *p, uint32_t *root);
 
 /* The recovery's Chinese remaindering in matrix form (host only, for checking): for a
- * plan of np <= 18 primes, c_{i,j} = sum_k y_k (P/p_k) - t P (Section 4, the Chinese
+ * plan of np <= 20 primes, c_{i,j} = sum_k y_k (P/p_k) - t P (Section 4, the Chinese
  * remaindering of each c_{i,j}; y_k the residue times (P/p_k)^{-1} mod p_k, centred) is
  * computed as int8 products on the matrix cores.  Writes the A operand the recovery loads,
  * tiles x 2 steps x 64 lanes x 16 signed bytes in that order (lane l of tile T, step s
  * holds row l mod 16 and the 16 slots 64 s + 16 (l / 16) + b; slot 4 q + a is byte a of
  * staged term q: y_q for q < np, t for q = np), and the tile count in *tiles.  Row m of
  * tile T is the weight-2^(8n) digit n = 4 tiles (m / 4) + 4 T + (m mod 4).  `cap` is the
- * size of `out` in bytes.  ZPM_EINVAL for np outside 1..18 or a short buffer. */
+ * size of `out` in bytes.  ZPM_EINVAL for np outside 1..20 or a short buffer. */
 int zpm_crt_matrix(int32_t np, int8_t *out, int64_t cap, int32_t *tiles);
 
 /* Compute units and LDS limits (bytes per workgroup, per CU) of a HIP device. */

@@ -1,7 +1,7 @@
 // Attainable rate of the transforms' modular butterfly on one device: every thread keeps
-// eight independent (u, v) pairs modulo a 31-bit Fourier prime in registers and applies
-// the forward-transform butterfly u, v -> u + v, (u - v) w (the add_mod / mul_shoup pair
-// of the transform kernels) to each, with no memory traffic.  Reported beside the ALU
+// eight independent (u, v) pairs modulo a 30-bit Fourier prime in registers and applies
+// the forward-transform butterfly u, v -> u + v, (u - v) w (the add_lz / mul_shoup_lz pair
+// of the transform kernels, values in [0, 2p)) to each, with no memory traffic.  Reported beside the ALU
 // peak derived from the chip's lane count and clock.
 #include <hip/hip_runtime.h>
 
@@ -23,8 +23,8 @@ __global__ __launch_bounds__(BLOCK) void k_bfly_ceiling(uint32_t p, uint2 w, int
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const uint32_t a = add_mod(u[j], v[j], p);
-      const uint32_t b = mul_shoup(u[j] - v[j] + p, w, p);
+      const uint32_t a = add_lz(u[j], v[j], p);
+      const uint32_t b = mul_shoup_lz(u[j] - v[j] + 2 * p, w, p);
       u[j] = a;
       v[j] = b;
     }

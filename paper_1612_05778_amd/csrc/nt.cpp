@@ -1,7 +1,7 @@
 // Host number theory for the word-size prime variant (Section 4: machine-word
 // Fourier primes combined by the Chinese remaindering algorithm).
 //
-// * Fourier primes p < 2^31 with 2^21 | p - 1 (Section 2.1, root-of-unity
+// * Fourier primes p < 2^30 with 2^21 | p - 1 (Section 2.1, root-of-unity
 //   condition), found by deterministic Miller-Rabin, largest first.
 // * A primitive 2^21-th root of unity per prime; every transform length used
 //   takes its roots as powers of it, so all tables agree.
@@ -84,9 +84,10 @@ const std::vector<PrimeHost> &prime_table() {
   static std::once_flag once;
   std::call_once(once, [] {
     const uint32_t step = 1u << LOG2_ROOT_ORDER;
-    for (uint64_t k = ((1ull << 31) - 1) / step; k >= 1 && (int)table.size() < MAXNP; --k) {
+    // below 2^30: the transforms keep values in [0, 2p) and sums of two in [0, 4p)
+    for (uint64_t k = ((1ull << PRIME_BITS) - 1) / step; k >= 1 && (int)table.size() < MAXNP; --k) {
       uint64_t p = k * step + 1;
-      if (p >= (1ull << 31) || !is_prime((uint32_t)p)) continue;
+      if (p >= (1ull << PRIME_BITS) || !is_prime((uint32_t)p)) continue;
       PrimeHost h;
       h.p = (uint32_t)p;
       uint32_t g = generator(h.p);
@@ -156,16 +157,23 @@ int bitlen_product(int np) {
   return 0;
 }
 
-// True if prod_{k<np} p_k > 4 d K 2^(2M): Relation (recoveryModulo) with the
-// product of the primes in the role of p (Section 4, CRA variant).
+// True if P = prod_{k<np} p_k > 2 d K 2^(2M) (1 + 2^-12), with d = min(da, db).
+// Relation (recoveryModulo) bounds the prime by 4 d K 2^(2M) because it must hold
+// c+_{i,j} and c-_{i,j} (each below 2 d K 2^(2M) in magnitude) in its symmetric range.
+// Here the halving (c+ + c-) / 2 and (c- - c+) / 2 is done modulo each prime before the
+// Chinese remaindering, which therefore recovers c_{i,j} itself: a sum of at most
+// min(da, db) K products of limbs below 2^M in magnitude, so |c_{i,j}| < d K 2^(2M) and
+// P > 2 |c_{i,j}| suffices for (-P/2, P/2).  The factor 1 + 2^-12 keeps |c_{i,j}| / P at
+// least 2^-13 below 1/2, the margin the recovery's floating-point quotient needs.
 bool primes_cover(int np, int64_t d, int64_t K, int64_t M) {
   const int n = MAXW + 1;
   uint32_t R[MAXW + 1];
   std::memset(R, 0, sizeof(R));
   const uint64_t dk = (uint64_t)d * (uint64_t)K;      // callers keep d K < 2^62
-  const int64_t shift = 2 * M + 2;
+  // 4096 P > 4097 d K 2^(2M+1)
+  const int64_t shift = 2 * M + 1;
   const int64_t w = shift / 32;
-  const unsigned __int128 t = (unsigned __int128)dk << (shift % 32);
+  const unsigned __int128 t = ((unsigned __int128)dk * 4097u) << (shift % 32);   // < 2^107
   for (int i = 0; i < 4; ++i) {
     uint32_t part = (uint32_t)(t >> (32 * i));
     if (!part) continue;
@@ -176,6 +184,7 @@ bool primes_cover(int np, int64_t d, int64_t K, int64_t M) {
   std::memset(P, 0, sizeof(P));
   P[0] = 1;
   for (int k = 0; k < np; ++k) mw_mul_small(P, n, prime_table()[k].p);
+  mw_mul_small(P, n, 4096u);
   for (int i = n - 1; i >= 0; --i) {
     if (P[i] != R[i]) return P[i] > R[i];
   }

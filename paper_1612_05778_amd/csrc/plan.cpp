@@ -4,8 +4,10 @@
 // For every power-of-two K (K >= 2) the limb width is M = max(2, ceil(N/K)) so
 // that K M >= N (Relation (minimalConditionsForN) with N padded up to K M; sign
 // extension keeps the value).  The prime count np is the smallest whose product
-// exceeds 4 d K 2^(2M), Relation (recoveryModulo) with the product of the primes
-// playing the role of p (Section 4).  The transform length along y is the power
+// exceeds 2 d K 2^(2M) (1 + 2^-12) with d = min(da, db): Relation (recoveryModulo) with
+// the product of the primes playing the role of p (Section 4), halved because the
+// recovery reconstructs c_{i,j} rather than c+_{i,j} and c-_{i,j} (primes_cover
+// states why).  The transform length along y is the power
 // of two L >= da + db - 1, and L and 2K must divide p - 1 (Section 2.1).
 //
 // Among the feasible K the planner keeps the one with the lowest modelled time,
@@ -93,7 +95,7 @@ static bool split_y(Plan &pl, int reg_k_max, int col_tile) {
 
 static bool finish(Plan &pl) {
   pl.log2P = bitlen_product(pl.np);
-  pl.W = pl.np;                      // >= (log2P + 1) / 32: every prime is below 2^31
+  pl.W = pl.np;                      // >= (log2P + 1) / 32: every prime is below 2^30
   if (pl.W > MAXW) return false;
   const int wa = (pl.Na + 63) / 64, wb = (pl.Nb + 63) / 64;
   const int wmax = std::max(wa, wb);
@@ -137,9 +139,12 @@ static double model_cost(const Plan &pl) {
                       + K * L * pl.logL           // inverse y, 2K columns
                       + 3.0 * L * K * logK2       // forward x (two operands) + inverse x
                       + 2.0 * K * L);             // pointwise
-  double alu = bfly * 12.0;
+  double alu = bfly * 10.0;
   const double J = 2.0 * K - 1.0;
-  alu += (double)pl.nout * J * (np * 4.0 + (np + 1.0) * pl.W * 3.0);   // CRT
+  // CRT per value c_{i,j}: on the matrix cores up to CRT_MFMA_NP primes (its residue
+  // products, staging, digit folding and carries), else np W word multiply-adds
+  const double crt = pl.np <= CRT_MFMA_NP ? 17.0 * np + 450.0 : np * 4.0 + (np + 1.0) * pl.W * 3.0;
+  alu += (double)pl.nout * J * crt;
   double words = np * 2.0 * K * L;
   double bytes = 4.0 * words * 2.0 * (1 + pl.ncol * 1.5) + 4.0 * words;   // passes over the spectra
   bytes += 8.0 * (pl.da * ((pl.Na + 63) / 64) + pl.db * ((pl.Nb + 63) / 64) +
@@ -168,7 +173,7 @@ bool make_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, 
   const int logL = ceil_log2(nout);
   if (logL > LOG2_ROOT_ORDER) { *why = "da + db - 1 exceeds 2^21"; return false; }
   const int32_t N = std::max(std::max(Na, Nb), 2);
-  const int64_t d = std::max(da, db);
+  const int64_t d = std::min(da, db);   // terms of each c_{i,j}: at most min(da, db) K
   bool found = false;
   Plan best;
   for (int logK = 1; logK <= 20; ++logK) {

@@ -19,7 +19,7 @@ __device__ __forceinline__ uint2 ld_tab(const uint2 *__restrict__ tab, int64_t i
 }
 
 // ------------------------------------------------------------------------------------
-// modular arithmetic on 32-bit words, p < 2^31
+// modular arithmetic on 32-bit words, p < 2^30
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t p) {
   uint32_t s = a + b;
@@ -44,6 +44,31 @@ __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t p,
   uint32_t mp = __umulhi(m, p);
   uint32_t r = hi - mp;   // wraps above 2^32 - p when hi < mp, and then r + p < r
   return min(r, r + p);
+}
+
+// Lazy forms for the transforms: operands and results in [0, 2p), i.e. reduced only up to
+// one p (Harvey's butterflies).  Every prime is below 2^30, so 4p < 2^32: a sum of two
+// such values, or u - v + 2p, still fits a word.
+__device__ __forceinline__ uint32_t add_lz(uint32_t a, uint32_t b, uint32_t p) {
+  const uint32_t s = a + b;                   // [0, 4p)
+  return min(s, s - 2 * p);
+}
+__device__ __forceinline__ uint32_t sub_lz(uint32_t a, uint32_t b, uint32_t p) {
+  const uint32_t d = a - b;                   // wraps when a < b, and then d + 2p < d
+  return min(d, d + 2 * p);
+}
+// x w mod p up to one p, in [0, 2p), for any x < 2^32 (Shoup's product without its final
+// subtraction).
+__device__ __forceinline__ uint32_t mul_shoup_lz(uint32_t x, uint2 w, uint32_t p) {
+  const uint32_t q = __umulhi(x, w.y);
+  return x * w.x + q * (0u - p);
+}
+// a b 2^-32 mod p up to one p, in [0, 2p), for a, b < 2p: a b < 4p^2 < p 2^32, so
+// hi - mp lies in (-p, p).
+__device__ __forceinline__ uint32_t mont_mul_lz(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
+  const uint32_t lo = a * b, hi = __umulhi(a, b);
+  const uint32_t m = lo * pinv;
+  return hi - __umulhi(m, p) + p;
 }
 // w_m^e from a heap table (tab[m/2 + e] = w_m^e for e < m/2), any e in [0, m).
 __device__ __forceinline__ uint2 heap_root(const uint2 *__restrict__ tab, int64_t m, int64_t e, uint32_t p) {
@@ -114,8 +139,8 @@ __device__ void dif_group(uint32_t *s, const SH &sh, int logh0_rt, const uint2 *
         if (m & half) continue;
         const uint2 w = ld_tab(tw, hsz + j + (m & (half - 1)) * hl);
         const uint32_t u = x[m], v = x[m + half];
-        x[m] = add_mod(u, v, p);
-        x[m + half] = mul_shoup(u - v + p, w, p);
+        x[m] = add_lz(u, v, p);
+        x[m + half] = mul_shoup_lz(u - v + 2 * p, w, p);
       }
     }
 #pragma unroll
@@ -160,9 +185,9 @@ __device__ void dit_group(uint32_t *s, const SH &sh, int logh0_rt, const uint2 *
         if (m & half) continue;
         const uint2 w = ld_tab(tw, hsz + j + (m & (half - 1)) * h0);
         const uint32_t u = x[m];
-        const uint32_t v = mul_shoup(x[m + half], w, p);
-        x[m] = add_mod(u, v, p);
-        x[m + half] = sub_mod(u, v, p);
+        const uint32_t v = mul_shoup_lz(x[m + half], w, p);
+        x[m] = add_lz(u, v, p);
+        x[m + half] = sub_lz(u, v, p);
       }
     }
 #pragma unroll
@@ -433,8 +458,8 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     if constexpr (fixed) lds_dif_c<CSH>(s, pr.hf, p);
     else lds_dif(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hf, p);
     for (int e = e0; e < n; e += de) {
-      const uint32_t v = mont_mul(s[(bitrev(e, logn) << logT) + t], cur, p, pr.pinv);
-      cur = mont_mul(cur, step, p, pr.pinv);
+      const uint32_t v = mont_mul_lz(s[(bitrev(e, logn) << logT) + t], cur, p, pr.pinv);
+      cur = mont_mul_lz(cur, step, p, pr.pinv);
       bt[e << logS] = v;
     }
   } else {
@@ -450,8 +475,8 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
       for (int u = 0; u < 8; ++u) {
         const int ee = e + u * de;
         if (ee < n) {
-          s[(bitrev(ee, logn) << logT) + t] = mont_mul(v[u], cur, p, pr.pinv);
-          cur = mont_mul(cur, step, p, pr.pinv);
+          s[(bitrev(ee, logn) << logT) + t] = mont_mul_lz(v[u], cur, p, pr.pinv);
+          cur = mont_mul_lz(cur, step, p, pr.pinv);
         }
       }
     }
@@ -551,7 +576,7 @@ __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   const uint2 sc = pd->scale[k];
   const uint32_t *F = mode == CM_SQUARE ? A : B;
   for (int idx = threadIdx.x; idx < (twoK << logL1); idx += BLOCK)
-    A[idx] = mul_shoup(mont_mul(A[idx], F[idx], p, pr.pinv), sc, p);
+    A[idx] = mul_shoup_lz(mont_mul_lz(A[idx], F[idx], p, pr.pinv), sc, p);
   __syncthreads();
   if constexpr (fixed) {
     lds_dit_c<CShape<FL1, FK + 1, 1, (1 << FL1)>>(s, pr.hi, p);
@@ -577,7 +602,7 @@ __device__ __forceinline__ void reg_dif(uint32_t (&x)[2 << LOGK], const uint2 *_
   constexpr int N2 = 2 << LOGK;
   // first stage: the upper half is zero, so x[j + K] = x[j] theta^j (the twist)
 #pragma unroll
-  for (int j = 0; j < N2 / 2; ++j) x[j + N2 / 2] = j ? mul_shoup(x[j], ld_tab(tw, N2 / 2 + j), p) : x[j];
+  for (int j = 0; j < N2 / 2; ++j) x[j + N2 / 2] = j ? mul_shoup_lz(x[j], ld_tab(tw, N2 / 2 + j), p) : x[j];
 #pragma unroll
   for (int h = N2 / 4; h >= 1; h >>= 1) {
 #pragma unroll
@@ -585,8 +610,8 @@ __device__ __forceinline__ void reg_dif(uint32_t (&x)[2 << LOGK], const uint2 *_
 #pragma unroll
       for (int j = 0; j < h; ++j) {
         const uint32_t u = x[blk + j], v = x[blk + j + h];
-        x[blk + j] = add_mod(u, v, p);
-        x[blk + j + h] = j ? mul_shoup(u - v + p, ld_tab(tw, h + j), p) : sub_mod(u, v, p);
+        x[blk + j] = add_lz(u, v, p);
+        x[blk + j + h] = j ? mul_shoup_lz(u - v + 2 * p, ld_tab(tw, h + j), p) : sub_lz(u, v, p);
       }
     }
   }
@@ -603,9 +628,9 @@ __device__ __forceinline__ void reg_dit(uint32_t (&x)[2 << LOGK], const uint2 *_
 #pragma unroll
       for (int j = 0; j < h; ++j) {
         const uint32_t u = x[blk + j];
-        const uint32_t v = j ? mul_shoup(x[blk + j + h], ld_tab(tw, h + j), p) : x[blk + j + h];
-        x[blk + j] = add_mod(u, v, p);
-        x[blk + j + h] = sub_mod(u, v, p);
+        const uint32_t v = j ? mul_shoup_lz(x[blk + j + h], ld_tab(tw, h + j), p) : x[blk + j + h];
+        x[blk + j] = add_lz(u, v, p);
+        x[blk + j + h] = sub_lz(u, v, p);
       }
     }
   }
@@ -674,11 +699,11 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
       reg_dif<LOGK>(a, pr.hf, p);
       if constexpr (MODE == CM_SQUARE) {
 #pragma unroll
-        for (int j = 0; j < K2; ++j) a[j] = mul_shoup(mont_mul(a[j], a[j], p, pr.pinv), sc, p);
+        for (int j = 0; j < K2; ++j) a[j] = mul_shoup_lz(mont_mul_lz(a[j], a[j], p, pr.pinv), sc, p);
       } else {
 #pragma unroll
         for (int j = 0; j < K2; ++j)
-          a[j] = mul_shoup(mont_mul(a[j], sb[j * L32 + e], p, pr.pinv), sc, p);
+          a[j] = mul_shoup_lz(mont_mul_lz(a[j], sb[j * L32 + e], p, pr.pinv), sc, p);
       }
       reg_dit<LOGK>(a, pr.hi, p);
 #pragma unroll
@@ -701,7 +726,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
     }
     reg_dif<LOGK>(b, pr.hf, p);
 #pragma unroll
-    for (int j = 0; j < K2; ++j) b[j] = mul_shoup(mont_mul(s[j * RS + e], b[j], p, pr.pinv), sc, p);
+    for (int j = 0; j < K2; ++j) b[j] = mul_shoup_lz(mont_mul_lz(s[j * RS + e], b[j], p, pr.pinv), sc, p);
     reg_dit<LOGK>(b, pr.hi, p);
 #pragma unroll
     for (int j = 0; j < K2; ++j) s[j * RS + e] = b[j];
@@ -746,8 +771,8 @@ __device__ __forceinline__ void reg_half_dif(uint32_t (&x)[1 << LOGN], ctw_ptr t
 #pragma unroll
       for (int j = 0; j < h; ++j) {
         const uint32_t u = x[blk + j], v = x[blk + j + h];
-        x[blk + j] = add_mod(u, v, p);
-        x[blk + j + h] = j ? mul_shoup(u - v + p, ctw(tw, h + j), p) : sub_mod(u, v, p);
+        x[blk + j] = add_lz(u, v, p);
+        x[blk + j + h] = j ? mul_shoup_lz(u - v + 2 * p, ctw(tw, h + j), p) : sub_lz(u, v, p);
       }
     }
   }
@@ -763,9 +788,9 @@ __device__ __forceinline__ void reg_half_dit(uint32_t (&x)[1 << LOGN], ctw_ptr t
 #pragma unroll
       for (int j = 0; j < h; ++j) {
         const uint32_t u = x[blk + j];
-        const uint32_t v = j ? mul_shoup(x[blk + j + h], ctw(tw, h + j), p) : x[blk + j + h];
-        x[blk + j] = add_mod(u, v, p);
-        x[blk + j + h] = sub_mod(u, v, p);
+        const uint32_t v = j ? mul_shoup_lz(x[blk + j + h], ctw(tw, h + j), p) : x[blk + j + h];
+        x[blk + j] = add_lz(u, v, p);
+        x[blk + j + h] = sub_lz(u, v, p);
       }
     }
   }
@@ -812,7 +837,7 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
   // the twisted half: x_j theta^j, then its K-point DIF (rows K..2K-1 of the spectrum)
   auto twisted = [&](uint32_t (&x)[K]) {
 #pragma unroll
-    for (int j = 1; j < K; ++j) x[j] = mul_shoup(x[j], ctw(hf, K + j), p);
+    for (int j = 1; j < K; ++j) x[j] = mul_shoup_lz(x[j], ctw(hf, K + j), p);
     reg_half_dif<LOGK>(x, hf, p);
   };
   if constexpr (MODE == CM_SPECTRUM) {
@@ -856,10 +881,10 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
       twisted(x);
 #pragma unroll
       for (int j = 0; j < K; ++j)
-        s[(K + j) * RS + e] = mul_shoup(mont_mul(s[(K + j) * RS + e], x[j], p, pr.pinv), sc, p);
+        s[(K + j) * RS + e] = mul_shoup_lz(mont_mul_lz(s[(K + j) * RS + e], x[j], p, pr.pinv), sc, p);
       reg_half_dif<LOGK>(b, hf, p);
 #pragma unroll
-      for (int j = 0; j < K; ++j) s[j * RS + e] = mul_shoup(mont_mul(s[j * RS + e], b[j], p, pr.pinv), sc, p);
+      for (int j = 0; j < K; ++j) s[j * RS + e] = mul_shoup_lz(mont_mul_lz(s[j * RS + e], b[j], p, pr.pinv), sc, p);
     } else {
       // one operand transformed once: times itself, or times b's stored spectra
 #pragma unroll
@@ -868,7 +893,7 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const uint32_t f = MODE == CM_SQUARE ? x[j] : sb[(K + j) * L32 + e];
-        x[j] = mul_shoup(mont_mul(x[j], f, p, pr.pinv), sc, p);
+        x[j] = mul_shoup_lz(mont_mul_lz(x[j], f, p, pr.pinv), sc, p);
       }
       uint32_t t[K];
 #pragma unroll
@@ -879,7 +904,7 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const uint32_t f = MODE == CM_SQUARE ? t[j] : sb[j * L32 + e];
-        s[j * RS + e] = mul_shoup(mont_mul(t[j], f, p, pr.pinv), sc, p);
+        s[j * RS + e] = mul_shoup_lz(mont_mul_lz(t[j], f, p, pr.pinv), sc, p);
       }
     }
     // inverse: the two K-point DITs, then the joining stage with theta^-j
@@ -894,9 +919,9 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const uint32_t u = x[j];
-        const uint32_t v = j ? mul_shoup(y[j], ctw(hi, K + j), p) : y[j];
-        s[j * RS + e] = add_mod(u, v, p);
-        s[(K + j) * RS + e] = sub_mod(u, v, p);
+        const uint32_t v = j ? mul_shoup_lz(y[j], ctw(hi, K + j), p) : y[j];
+        s[j * RS + e] = add_lz(u, v, p);
+        s[(K + j) * RS + e] = sub_lz(u, v, p);
       }
     }
   }
@@ -917,7 +942,7 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
 // ------------------------------------------------------------------------------------
 // RecoveringProduct.  For each output coefficient i and each j < 2K-1:
 //   c_{i,j} from its np residues by CRT into (-P/2, P/2) (exact because
-//   |c_{i,j}| < d K 2^(2M) < P/4), as W-word two's complement;
+//   |c_{i,j}| < d K 2^(2M) < P/2 (1 - 2^-12)), as W-word two's complement;
 // then c_i = sum_j c_{i,j} 2^(M j) (evaluation at beta = 2^M) by per-word sums of
 // shifted windows and a wave-wide carry scan.
 // ------------------------------------------------------------------------------------
@@ -935,8 +960,9 @@ typedef int crt_i32x4 __attribute__((ext_vector_type(4)));
 // CRT_MFMA_NP).  Per wave and 64 values (one per lane): each lane reads its value's np
 // residues, takes y_k = r_k (P/p_k)^{-1} mod p_k centred in (-p_k/2, p_k/2) and
 // t = round(sum_k y_k / p_k), so that c_{i,j} = sum_k y_k (P/p_k) - t P, and stages the
-// terms as balanced signed bytes in LDS.  (|c_{i,j}| < P/4 leaves t a margin of 1/4,
-// far above the error of the single-precision sum.)  Then four products of 16 values
+// terms as balanced signed bytes in LDS.  (|c_{i,j}| < P/2 (1 - 2^-12) leaves the
+// rounding of t a margin of 2^-13, far above the error of the single-precision sum, below
+// 2^-16 for 18 terms.)  Then four products of 16 values
 // each: D = A Y with A the constants' digit matrix (built on the host in fragment order),
 // whose 16-digit tiles T give lane group g the digits 4 TN g + 4 T + i of value
 // v = lane mod 16.  The lane folds its 4 TN digit sums into TN consecutive 32-bit words
@@ -1080,7 +1106,7 @@ struct CrtMatrix {
 };
 
 // NP = np exactly and W = NP words per CRT value (32 NP >= log2 P + 1 since every
-// prime is below 2^31).  Per workgroup: TI consecutive coefficients; S holds their
+// prime is below 2^30).  Per workgroup: TI consecutive coefficients; S holds their
 // output words as 64-bit partial sums.
 template <int NP>
 __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__restrict__ X,
@@ -1147,7 +1173,7 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
       cc[k] = mul_shoup(cc[k], make_uint2(ci[3 * k], ci[3 * k + 1]), ci[3 * k + 2]);
       f += (double)cc[k] * cr[k];
     }
-    // c_{i,j} = sum_k c_k (P/p_k) - t P, where sum_k c_k P/p_k = c + t P with |c| < P/4,
+    // c_{i,j} = sum_k c_k (P/p_k) - t P, where sum_k c_k P/p_k = c + t P with |c| < P/2,
     // so t = round(sum_k c_k / p_k).  Adding t (2^(32 W) - P) instead of subtracting t P
     // gives c + t 2^(32 W), whose low W words are c in two's complement: every term is
     // an unsigned product.  The value is produced one 32-bit word u at a time (column

@@ -6,9 +6,10 @@
 
 namespace zpm {
 
-// Word-size Fourier primes p < 2^31 with 2^LOG2_ROOT_ORDER | p - 1 (Section 2.1,
+// Word-size Fourier primes p < 2^30 with 2^LOG2_ROOT_ORDER | p - 1 (Section 2.1,
 // Relation (HavingAppropriatePrimitiveRootsOfUnity): the transform lengths along
 // y and the 2K-th root theta along x must divide p - 1).
+constexpr int PRIME_BITS = 30;          // every prime is below 2^PRIME_BITS
 constexpr int MAXNP = 48;               // largest prime count a plan may use
 constexpr int LOG2_ROOT_ORDER = 21;     // every prime has a primitive 2^21-th root
 constexpr int MAXW = 48;                // 32-bit words of a CRT value (> 31*MAXNP + 2 bits)
@@ -17,9 +18,9 @@ constexpr int LDS_WORDS = 16384;        // 64 KiB of LDS staging per workgroup
 constexpr int MAX_COL_PASSES = 4;
 // The recovery's CRT runs on int8 matrix cores up to this prime count: np + 1 terms of 4
 // bytes in CRT_STEPS steps of 64 slots, values of up to 16 CRT_TILES signed bytes.
-constexpr int CRT_MFMA_NP = 18;
+constexpr int CRT_MFMA_NP = 20;
 constexpr int CRT_STEPS = 2;
-constexpr int CRT_TILES = 5;
+constexpr int CRT_TILES = 6;
 // Words each recovery value stages in LDS for the matrix cores: its np terms and t,
 // rounded to a 16-byte fragment.
 constexpr int crt_stage_words(int np) { return 4 * ((np + 4) / 4); }

@@ -8,17 +8,20 @@ forward transforms and the untwist after its inverse), not what a particular
 kernel happens to execute (the kernels run the x part as 2K-point transforms
 whose first stage is the twist):
 
-* one radix-2 butterfly = 11 int32 VALU operations (Shoup product: 2 mul_lo,
-  1 mul_hi, 1 sub, 2 for the final reduction; modular add 3; modular sub 2);
-* one pointwise product = 13 (Montgomery product 7, Shoup scaling 6);
-* one four-step twiddle product = 6 (Shoup product with reduction);
+* values are kept in [0, 2p) (every prime is below 2^30) and reduced only that far;
+* one forward (DIF) radix-2 butterfly = 8 int32 VALU operations: u + v reduced below
+  2p (add, sub, min), u - v + 2p (2), its Shoup product with the twiddle (mul_hi,
+  mul_lo and a multiply-add); one inverse (DIT) butterfly = 9: the Shoup product (3),
+  u + v and u - v reduced below 2p (3 each);
+* one pointwise product = 9 (Montgomery product up to one p 6, Shoup scaling 3);
+* one four-step twiddle or twist product = 3 (Shoup product up to one p);
 * convert-in, per limb residue: 2 per 32-bit word of the limb (a multiply-add with
   the table entry 2^(32 t) mod p and its carry) plus 6 for the final reduction;
 * CRT of one value c_{i,j} from np residues (Section 2.2, the recovery through
   the Chinese remaindering of Section 4): 6 per residue (its Shoup product with
   (P/p_k)^{-1}), 2 per word of each of the np products y_k (P/p_k) summed over W
   words (multiply-add and carry), and 4 per word for the quotient correction and
-  the shifted accumulation at 2^(Mj).  Up to 18 primes the kernel forms the sum
+  the shifted accumulation at 2^(Mj).  Up to 20 primes the kernel forms the sum
   sum_k y_k (P/p_k) - t P on the int8 matrix cores: each 32 x 32-bit word product
   is 16 byte products, 2 int8 operations each, counted against the int8 matrix
   peak instead of the int32 one.
@@ -30,13 +33,14 @@ from __future__ import annotations
 
 import math
 
-OPS_BFLY = 11
-OPS_POINTWISE = 13
-OPS_TWIDDLE = 6
+OPS_BFLY_DIF = 8
+OPS_BFLY_DIT = 9
+OPS_POINTWISE = 9
+OPS_TWIDDLE = 3
 INT32_PEAK = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes x 2.4 GHz: int32 VALU op/s
 HBM_PEAK = 8.0e12                   # bytes/s
 MFMA_I8_PEAK = 5.0e15               # dense int8 matrix operations/s (published)
-CRT_MFMA_NP = 18                    # prime counts whose CRT sum runs on the matrix cores
+CRT_MFMA_NP = 20                    # prime counts whose CRT sum runs on the matrix cores
 
 
 def kernel_work(plan: dict, name: str) -> dict:
@@ -49,12 +53,16 @@ def kernel_work(plan: dict, name: str) -> dict:
     logx = int(math.log2(2 * K))
     if name == "convolve_rows":
         logK = logx - 1
-        bfly = np_ * L * K * (2 * logL1 + 3 * logK)
+        # forward: the inner y factor on both operands' K rows, four K-point transforms
+        # per position (cyclic and negacyclic, a and b); inverse: the inner y factor on
+        # 2K rows, two K-point transforms per position
+        dif = np_ * L * K * (logL1 + 2 * logK)
+        dit = np_ * L * K * (logL1 + logK)
         twists = np_ * L * 3 * K               # theta^j on both operands, theta^-j after
         pw = np_ * 2 * K * L
         words_in = np_ * 2 * K * L
-        return {"ops": bfly * OPS_BFLY + twists * OPS_TWIDDLE + pw * OPS_POINTWISE,
-                "bytes": 4 * 2 * words_in}
+        return {"ops": dif * OPS_BFLY_DIF + dit * OPS_BFLY_DIT + twists * OPS_TWIDDLE
+                + pw * OPS_POINTWISE, "bytes": 4 * 2 * words_in}
     if name in ("col_pass_fwd", "col_pass_inv"):
         # per launch = one pass; the mean over the passes.  The first forward pass
         # reads only the rows below da (db) of a's (b's) columns, the rest being zero.
@@ -69,7 +77,8 @@ def kernel_work(plan: dict, name: str) -> dict:
             read = (first_read + (npass - 1) * full) / npass
         else:
             read = full
-        return {"ops": bfly * OPS_BFLY + tw * OPS_TWIDDLE, "bytes": read + full}
+        ob = OPS_BFLY_DIF if name == "col_pass_fwd" else OPS_BFLY_DIT
+        return {"ops": bfly * ob + tw * OPS_TWIDDLE, "bytes": read + full}
     if name == "bivariate_representation":
         # per launch = one operand; the mean of the two
         w = ((plan["Na"] + 63) // 64 * da + (plan["Nb"] + 63) // 64 * db) / 2

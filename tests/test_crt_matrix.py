@@ -1,6 +1,6 @@
 """Host pins of the recovery's Chinese remaindering in matrix form (no GPU needed).
 
-For np <= 18 primes the recovery computes c_{i,j} = sum_k y_k (P/p_k) - t P (Section 4,
+For np <= 20 primes the recovery computes c_{i,j} = sum_k y_k (P/p_k) - t P (Section 4,
 the Chinese remaindering of each c_{i,j}: y_k = r_k (P/p_k)^{-1} mod p_k centred,
 t = round(sum_k y_k / p_k)) as int8 products on the matrix cores: the terms' balanced
 bytes times a digit matrix A the host builds (``zpm_crt_matrix``).  This test models that
@@ -14,8 +14,9 @@ computation on the CPU with the library's A, in the kernel's lane order:
   t in byte 0 of term np, zeros up to the fragment;
 * each lane group's fold of its digit sums into consecutive 32-bit words and a carry.
 
-The reconstruction must equal c exactly for random c in (-P/4, P/4) and the extremes, for
-every np from 1 to 18, with P from the library's own prime table.  A's entries must be
+The reconstruction must equal c exactly for random c with |c| < P / (2 (1 + 2^-12)) (the
+planner's bound) and at its extremes, for every np from 1 to 20, with P from the
+library's own prime table; a single-precision quotient sum rounds to the same t.  A's entries must be
 signed bytes and every digit sum must fit the int32 accumulator.
 """
 import ctypes
@@ -92,7 +93,7 @@ def fold(D, TN, v):
     return total
 
 
-@pytest.mark.parametrize("np_", list(range(1, 19)))
+@pytest.mark.parametrize("np_", list(range(1, 21)))
 def test_matrix_crt_reconstructs(np_):
     ps = primes(np_)
     P = 1
@@ -100,8 +101,9 @@ def test_matrix_crt_reconstructs(np_):
         P *= p
     TN, A = matrix(np_)
     rng = random.Random(np_)
-    vals = [P // 4 - 1, -(P // 4) + 1, 0, 1, -1] + [x for x in (2**31, -(2**31)) if 4 * abs(x) < P] + \
-           [rng.randrange(-(P // 4) + 1, P // 4) for _ in range(57)]
+    cmax = P * 4096 // (2 * 4097) - 1          # the planner keeps |c| below this
+    vals = [cmax, -cmax, 0, 1, -1] + [x for x in (2**31, -(2**31)) if abs(x) < cmax] + \
+           [rng.randrange(-cmax, cmax + 1) for _ in range(57)]
     for chunk in range(0, len(vals), 16):
         cs = vals[chunk:chunk + 16]
         cs = cs + [0] * (16 - len(cs))
@@ -115,6 +117,12 @@ def test_matrix_crt_reconstructs(np_):
             f = sum(yk / p for yk, p in zip(y, ps))
             t = int(round(f))
             assert abs(t) <= np_ // 2 + 1
+            # the kernel's single-precision sum rounds to the same t
+            f32 = np.float32(0)
+            for yk, p in zip(y, ps):
+                f32 = np.float32(f32 + np.float32(yk) * np.float32(1.0 / p))
+            # (its error stays far below the 2^-13 the bound leaves between c / P and 1/2)
+            assert int(np.rint(f32)) == t and abs(float(f32) - f) < 2.0**-16
             words.append(stage(y, t, np_))
         D = mfma_model(A, words, TN)
         assert np.abs(D).max() < 2**31
@@ -126,5 +134,5 @@ def test_matrix_rejects():
     buf = (ctypes.c_int8 * 16)()
     tiles = ctypes.c_int32()
     assert nat.zpm_crt_matrix(0, buf, 16, ctypes.byref(tiles)) == nat.ZPM_EINVAL
-    assert nat.zpm_crt_matrix(19, buf, 16, ctypes.byref(tiles)) == nat.ZPM_EINVAL
+    assert nat.zpm_crt_matrix(21, buf, 16, ctypes.byref(tiles)) == nat.ZPM_EINVAL
     assert nat.zpm_crt_matrix(18, buf, 16, ctypes.byref(tiles)) == nat.ZPM_EINVAL

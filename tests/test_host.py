@@ -1,10 +1,14 @@
 """Host-side logic of the HIP library (CPU only, no kernels run).
 
 * The C-ABI library loads and exports every function ``include/zpm.h`` declares.
-* The prime table: primes (sympy), 2^21 | p - 1, the stored root has order 2^21.
-* The planner (DetermineBase + RecoveryPrime of Section 2.3): K M >= N, the
-  prime product exceeds 4 d K 2^(2M) (Relation (recoveryModulo)), L >= da+db-1,
-  2K and L divide p - 1, CRT words hold P; checked with Python integers.
+* The prime table: the 48 largest primes c 2^21 + 1 below 2^30 (enumerated here with
+  sympy), the stored root has order 2^21.
+* The planner (DetermineBase + RecoveryPrime of Section 2.3): K M >= N, the prime
+  product P exceeds 2 d K 2^(2M) (1 + 2^-12) with d = min(da, db), and no fewer primes
+  would (Relation (recoveryModulo) for c_{i,j} itself), L >= da+db-1, 2K and L divide
+  p - 1, CRT words hold P; checked with Python integers.
+* The bound's premise: every c_{i,j} of the limb products is below min(da, db) K 2^(2M)
+  in magnitude, checked on extreme and random operands with Python integers.
 * Output width (Relation (citighterbound)) agrees with the extreme cases.
 """
 import os
@@ -51,10 +55,12 @@ def test_prime_table(nat):
     ps = []
     for k in range(48):
         p, r = api.prime(k)
-        assert p < 2**31 and sympy.isprime(p) and (p - 1) % 2**21 == 0
+        assert p < 2**30 and sympy.isprime(p) and (p - 1) % 2**21 == 0
         assert pow(r, 2**20, p) == p - 1          # order exactly 2^21
         ps.append(p)
     assert ps == sorted(ps, reverse=True) and len(set(ps)) == 48
+    expect = [c * 2**21 + 1 for c in range(2**9 - 1, 0, -1) if sympy.isprime(c * 2**21 + 1)][:48]
+    assert ps == expect
     with pytest.raises(Exception):
         api.prime(48)
 
@@ -78,11 +84,14 @@ def test_plan_invariants(nat, da, Na, db, Nb):
     K, M, np_ = pl["K"], pl["M"], pl["np"]
     N = max(Na, Nb, 2)
     assert K >= 2 and M >= 2 and K & (K - 1) == 0 and K * M >= N
-    d = max(da, db)
+    d = min(da, db)
     P = 1
     for k in range(np_):
         P *= api.prime(k)[0]
-    assert P > 4 * d * K * 2 ** (2 * M)
+    assert 4096 * P > 4097 * 2 * d * K * 2 ** (2 * M)
+    if np_ <= 24:                       # every count up to 24 has compiled kernels
+        P1 = P // api.prime(np_ - 1)[0]
+        assert not 4096 * P1 > 4097 * 2 * d * K * 2 ** (2 * M), "fewer primes would do"
     L = 1 << pl["log2_L"]
     assert L >= da + db - 1 and (L == 1 or L // 2 < da + db - 1)
     assert max(L, 2 * K) <= 2**21
@@ -176,3 +185,39 @@ def test_from_to_ints_roundtrip(nat):
     assert N == 300 and api.to_ints(t) == [5, -3]
     with pytest.raises(ValueError):
         api.from_ints([2**10], 10, device="cpu")
+
+
+def limbs(x, N, K, M):
+    """The limb split of Section 2: K limbs of M bits, the lower ones unsigned and the
+    top one the signed rest (x is an N-bit two's complement value, K M >= N)."""
+    out = []
+    for j in range(K - 1):
+        out.append((x >> (M * j)) & ((1 << M) - 1))
+    out.append(x >> (M * (K - 1)))
+    assert sum(a << (M * j) for j, a in enumerate(out)) == x
+    return out
+
+
+@pytest.mark.parametrize("da,db,N,K", [(3, 5, 40, 4), (7, 2, 33, 8), (4, 4, 64, 2), (6, 9, 17, 16)])
+def test_cij_bound(da, db, N, K):
+    """|c_{i,j}| < min(da, db) K 2^(2M) for c_{i,j} = sum a_{l,k} b_{m,h} over l + m = i,
+    k + h = j: the premise of the planner's prime bound."""
+    import random
+    rng = random.Random(da * 100 + db * 10 + K)
+    M = max(2, -(-N // K))
+    lo, hi = -(1 << (N - 1)), (1 << (N - 1)) - 1
+    cases = [([lo] * da, [lo] * db), ([hi] * da, [hi] * db), ([lo] * da, [hi] * db)]
+    cases += [([rng.randint(lo, hi) for _ in range(da)], [rng.randint(lo, hi) for _ in range(db)])
+              for _ in range(20)]
+    bound = min(da, db) * K * 2 ** (2 * M)
+    worst = 0
+    for a, b in cases:
+        A = [limbs(x, N, K, M) for x in a]
+        B = [limbs(x, N, K, M) for x in b]
+        for i in range(da + db - 1):
+            for j in range(2 * K - 1):
+                c = sum(A[l][k] * B[i - l][j - k] for l in range(max(0, i - db + 1), min(da, i + 1))
+                        for k in range(max(0, j - K + 1), min(K, j + 1)))
+                worst = max(worst, abs(c))
+    assert worst < bound
+    assert worst > bound // 16          # the extreme cases come close to it
