@@ -98,10 +98,11 @@ int zpm_prime(int32_t k, uint32_t *p, uint32_t *root);
  * plan of np <= 20 primes, c_{i,j} = sum_k y_k (P/p_k) - t P (Section 4, the Chinese
  * remaindering of each c_{i,j}; y_k the residue times (P/p_k)^{-1} mod p_k, centred) is
  * computed as int8 products on the matrix cores.  Writes the A operand the recovery loads,
- * tiles x 2 steps x 64 lanes x 16 signed bytes in that order (lane l of tile T, step s
- * holds row l mod 16 and the 16 slots 64 s + 16 (l / 16) + b; slot 4 q + a is byte a of
- * staged term q: y_q for q < np, t for q = np), and the tile count in *tiles.  Row m of
- * tile T is the weight-2^(8n) digit n = 4 tiles (m / 4) + 4 T + (m mod 4).  `cap` is the
+ * tiles x 2 steps x 64 lanes x 16 signed bytes in that order: lane l of tile T, step s
+ * holds row l mod 16 and, at byte 4 w + a, the weight of byte a of term q, where
+ * q = 4 (l / 16) + w in step 0 and q = 16 + l / 16 + 4 w in step 1 (y_q for q < np, t for
+ * q = np, nothing above).  Row m of tile T is the weight-2^(8n) digit
+ * n = 4 tiles (m / 4) + 4 T + (m mod 4); *tiles receives the tile count.  `cap` is the
  * size of `out` in bytes.  ZPM_EINVAL for np outside 1..20 or a short buffer. */
 int zpm_crt_matrix(int32_t np, int8_t *out, int64_t cap, int32_t *tiles);
 

@@ -93,14 +93,14 @@ __global__ __launch_bounds__(BLOCK) void k_convolve_rows_split(
                                           pd, spec);
 }
 
-template <int NP>
+template <int NP, int FORM>
 __global__ __launch_bounds__(BLOCK) void k_recovering_product(
     const uint32_t *__restrict__ X, int64_t L, int32_t K, int32_t M, int64_t nout, int32_t nw32,
     int32_t wc, int32_t logTI, const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd,
     uint64_t *__restrict__ out) {
   extern __shared__ uint64_t S[];
-  body_recover<NP>(S, xcd_tile((nout + (1 << logTI) - 1) >> logTI), X, L, K, M, nout, nw32, wc,
-                   logTI, primes, pd, out);
+  body_recover<NP, FORM>(S, xcd_tile((nout + (1 << logTI) - 1) >> logTI), X, L, K, M, nout, nw32,
+                         wc, logTI, primes, pd, out);
 }
 
 // Range check of the inputs (checked-input mode): in the top word of each coefficient the
@@ -250,10 +250,19 @@ hipError_t launch_recover(const Plan &pl, const DevState &ds, uint64_t *out, int
   const int logTI = pl.log_ti_out;
   const int64_t blocks = xcd_grid((pl.nout + (1 << logTI) - 1) >> logTI);
   const size_t lds = recover_lds_bytes(pl.np, pl.K, pl.M, nw32, logTI);
+  // the matrix form's staged and register variants are compiled apart, each with its own
+  // register count
+  const bool staged = recover_staged(pl.np, pl.K, pl.M, nw32, logTI);
 #define ZPM_REC(NP_)                                                                           \
   case NP_:                                                                                    \
-    hipLaunchKernelGGL(k_recovering_product<NP_>, dim3((unsigned)blocks), dim3(BLOCK), lds, st, \
-                       ds.X, L, pl.K, pl.M, pl.nout, nw32, wc, logTI, ds.primes, ds.plan, out); \
+    if (staged)                                                                                \
+      hipLaunchKernelGGL((k_recovering_product<NP_, 1>), dim3((unsigned)blocks), dim3(BLOCK), lds, \
+                         st, ds.X, L, pl.K, pl.M, pl.nout, nw32, wc, logTI, ds.primes, ds.plan, \
+                         out);                                                                 \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_recovering_product<NP_, 0>), dim3((unsigned)blocks), dim3(BLOCK), lds, \
+                         st, ds.X, L, pl.K, pl.M, pl.nout, nw32, wc, logTI, ds.primes, ds.plan, \
+                         out);                                                                 \
     break;
   switch (pl.np) {
     ZPM_NP_CASES(ZPM_REC)

@@ -212,9 +212,10 @@ static bool balanced_bytes(const uint32_t *mag, int nw, int sign, int nd, int8_t
 
 // The CRT sum c = sum_k y_k (P / p_k) - t P as an int8 matrix product.  Each term (y_k
 // centred in (-p_k/2, p_k/2), and t, |t| <= np/2) is split into balanced signed bytes,
-// the slots (term, a) with a < 4 (t uses a = 0 only); each constant P/p_k and -P is
-// written in balanced bytes too, and A[n][(term, a)] = digit n - a of the term's
-// constant, so that c = sum_n 2^(8n) sum_slot A[n][slot] y_slot.  Rows are placed so that
+// one slot per byte a < 4 (t uses a = 0 only), placed in the B operand as crt_term
+// says; each constant P/p_k and -P is written in balanced bytes too, and
+// A[n][(term, a)] = digit n - a of the term's constant, so that
+// c = sum_n 2^(8n) sum_slot A[n][slot] y_slot.  Rows are placed so that
 // lane group g of the product's output holds digits 4 TN g + 4 T + i (tile T, row i),
 // i.e. the consecutive words TN g .. TN g + TN - 1 of the value.
 static void crt_matrix_constants(int np, const uint32_t *P, const uint32_t (*Q)[MAXW],
@@ -229,8 +230,8 @@ static void crt_matrix_constants(int np, const uint32_t *P, const uint32_t (*Q)[
   for (int k = 0; k < np; ++k)
     if (!balanced_bytes(Q[k], MAXW, 1, ND - 3, &dig[(size_t)k * ND])) std::abort();
   if (!balanced_bytes(P, MAXW, -1, ND, &dig[(size_t)np * ND])) std::abort();
-  auto A = [&](int n, int slot) -> int {
-    const int term = slot >> 2, a = slot & 3;
+  // slot (s, g, 4 w + a): byte a of term crt_term(s, g, w)
+  auto A = [&](int n, int term, int a) -> int {
     if (term > np || (term == np && a != 0) || n - a < 0) return 0;
     return dig[(size_t)term * ND + (n - a)];
   };
@@ -240,8 +241,8 @@ static void crt_matrix_constants(int np, const uint32_t *P, const uint32_t (*Q)[
       for (int lane = 0; lane < 64; ++lane) {
         const int n = row_digit(T, lane & 15);
         for (int b = 0; b < 16; ++b) {
-          const int slot = 64 * st + 16 * (lane >> 4) + b;
-          pd.crt_afrag[T][st][lane][b >> 2] |= (uint32_t)(uint8_t)(int8_t)A(n, slot)
+          const int term = crt_term(st, lane >> 4, b >> 2);
+          pd.crt_afrag[T][st][lane][b >> 2] |= (uint32_t)(uint8_t)(int8_t)A(n, term, b & 3)
                                                << (8 * (b & 3));
         }
       }

@@ -120,9 +120,8 @@ static bool finish(Plan &pl) {
   lt = 6;
   while (lt > 0 && ((nw32 << lt) * 2 > 12288 || (J << lt) > 1024)) --lt;
   while (lt > 2 && (J << (lt - 1)) >= 192) --lt;
-  // the CRT's matrix form stages each value's terms in LDS (20 KiB at most) and may touch
-  // 4 TN + 1 words past a row: such a recovery may take up to 96 of the 160 KiB a gfx950
-  // workgroup can address
+  // the CRT's matrix form may touch 4 TN + 1 words past a row: such a recovery may take
+  // more than 64 KiB (up to 96 of the 160 KiB a gfx950 workgroup can address)
   const size_t lds_cap = pl.np <= CRT_MFMA_NP ? 96 * 1024 : 4 * (size_t)LDS_WORDS;
   if (recover_lds_bytes(pl.np, pl.K, pl.M, (int)nw32, lt) > lds_cap) return false;
   pl.log_ti_out = lt;

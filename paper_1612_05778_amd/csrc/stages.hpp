@@ -957,44 +957,70 @@ __device__ __forceinline__ int fcompose(int g, int f) {   // g after f
 typedef int crt_i32x4 __attribute__((ext_vector_type(4)));
 
 // The CRT of each c_{i,j} on the int8 matrix cores, added at bit M j into S (np <=
-// CRT_MFMA_NP).  Per wave and 64 values (one per lane): each lane reads its value's np
-// residues, takes y_k = r_k (P/p_k)^{-1} mod p_k centred in (-p_k/2, p_k/2) and
-// t = round(sum_k y_k / p_k), so that c_{i,j} = sum_k y_k (P/p_k) - t P, and stages the
-// terms as balanced signed bytes in LDS.  (|c_{i,j}| < P/2 (1 - 2^-12) leaves the
-// rounding of t a margin of 2^-13, far above the error of the single-precision sum, below
-// 2^-16 for 18 terms.)  Then four products of 16 values
-// each: D = A Y with A the constants' digit matrix (built on the host in fragment order),
-// whose 16-digit tiles T give lane group g the digits 4 TN g + 4 T + i of value
-// v = lane mod 16.  The lane folds its 4 TN digit sums into TN consecutive 32-bit words
-// plus a signed carry, exactly its share of c_{i,j}, and adds them, shifted by M j bits,
-// into its row of S (RS words, with room for every word a lane group touches; S[-1]
-// exists).  Values past the tile's end stage zero terms and add zeros to row 0.
-// The residues of each wave's first 64 values and the A fragments are loaded before the
-// workgroup's set-up (constants to LDS, S cleared, barrier), whose time they overlap.
-// cw: per prime (c_k, its Shoup companion, p_k, 1/p_k as float bits).
+// CRT_MFMA_NP).  c_{i,j} = sum_k y_k (P/p_k) - t P with y_k = r_k (P/p_k)^{-1} mod p_k
+// centred in (-p_k/2, p_k/2) and t = round(sum_k y_k / p_k).  (|c_{i,j}| < P/2 (1 - 2^-12)
+// leaves the rounding of t a margin of 2^-13, far above the error of the single-precision
+// sum, below 2^-16 for 20 terms.)  Per wave, rounds of 16 values: value v = lane mod 16,
+// and lane group g = lane / 16 holds the terms crt_term(s, g, w) of step s (w < 4): it
+// loads and reduces those residues, the four groups add their shares of the quotient sum,
+// and the terms' balanced signed bytes form the B operand in registers.  D = A Y with A
+// the constants' digit matrix (built on the host in fragment order); its 16-digit tiles T
+// give lane group g the digits 4 TN g + 4 T + i of value v.  The lane folds its 4 TN digit
+// sums into TN consecutive 32-bit words plus a signed carry, exactly its share of
+// c_{i,j}, and adds them, shifted by M j bits, into its row of S (RS words, with room for
+// every word a lane group touches; S[-1] exists).  Values past the tile's end add zeros
+// to row 0.  With short rows (recover_staged) the terms are formed one value per lane
+// and passed to the lane groups through LDS instead.  Each round's residues are loaded two rounds ahead; the first two rounds',
+// and the A fragments, before the workgroup's set-up (constants to LDS, S cleared,
+// barrier).  cw: per prime (c_k, its Shoup companion, p_k, 1/p_k as float bits).
 template <int NP>
 struct CrtMatrix {
   static constexpr int NT = NP + 1;
-  static constexpr int YW = crt_stage_words(NP);
   static constexpr int NS = (NT + 15) / 16;
   static constexpr int TN = crt_tiles(NP);
-  static constexpr int CH = 6;        // terms whose constants are read from LDS together
   static_assert(NS <= CRT_STEPS && TN <= CRT_TILES, "CRT matrix shape");
+  static constexpr int YW = crt_stage_words(NP);
   crt_i32x4 af[TN][NS];
-  uint32_t pre[NP];
+  uint32_t pre[NS][4];                // register form: the next round's residues
+  uint32_t pres[NP];                  // staged form: the first value's residues
 
-  __device__ __forceinline__ void prefetch(const uint32_t *__restrict__ X, int64_t L, int32_t K,
-                                           int32_t logTI, int ti, int64_t i0,
-                                           const PlanDev *__restrict__ pd) {
-    const int lane = threadIdx.x & 63;
+  // round gr of this wave: values wave 64 + (gr / 4) BLOCK + (gr % 4) 16 + 0..15
+  __device__ __forceinline__ static int round_item(int gr, int v) {
+    return (threadIdx.x & ~63) + (gr >> 2) * BLOCK + (gr & 3) * 16 + v;
+  }
+  // the residues of lane group g's terms for one value (zero past the tile)
+  __device__ __forceinline__ static void load(uint32_t (&r)[NS][4], const uint32_t *__restrict__ X,
+                                              int64_t L, int32_t K, int32_t logTI, int ti,
+                                              int64_t i0, int item, int g) {
     const int TI = 1 << logTI;
     const int items = (2 * K - 1) << logTI;
-    const int item = (threadIdx.x & ~63) + lane;
-    const int il = item & (TI - 1), j = item >> logTI;
-    const bool ok = item < items && il < ti;
-    const int64_t off = (int64_t)j * L + i0 + il;
+    const bool ok = item < items && (item & (TI - 1)) < ti;
+    const int64_t off = (int64_t)(item >> logTI) * L + i0 + (item & (TI - 1));
 #pragma unroll
-    for (int k = 0; k < NP; ++k) pre[k] = ok ? X[(int64_t)k * 2 * K * L + off] : 0u;
+    for (int st = 0; st < NS; ++st)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int q = crt_term(st, g, w);
+        r[st][w] = ok && q < NP ? X[(int64_t)q * 2 * K * L + off] : 0u;
+      }
+  }
+
+  template <int FORM>
+  __device__ __forceinline__ void prefetch(bool staged, const uint32_t *__restrict__ X, int64_t L,
+                                           int32_t K, int32_t logTI, int ti, int64_t i0,
+                                           const PlanDev *__restrict__ pd) {
+    const int lane = threadIdx.x & 63;
+    if (FORM == 1 || (FORM < 0 && staged)) {
+      const int TI = 1 << logTI;
+      const int items = (2 * K - 1) << logTI;
+      const int item = threadIdx.x;
+      const bool ok = item < items && (item & (TI - 1)) < ti;
+      const int64_t off = (int64_t)(item >> logTI) * L + i0 + (item & (TI - 1));
+#pragma unroll
+      for (int k = 0; k < NP; ++k) pres[k] = ok ? X[(int64_t)k * 2 * K * L + off] : 0u;
+    } else if (FORM != 1) {
+      load(pre, X, L, K, logTI, ti, i0, round_item(0, lane & 15), lane >> 4);
+    }
 #pragma unroll
     for (int T = 0; T < TN; ++T)
 #pragma unroll
@@ -1004,111 +1030,186 @@ struct CrtMatrix {
       }
   }
 
-  __device__ __forceinline__ void run(uint64_t *S, int32_t RS, uint32_t *Y, const uint4 *cw,
+  // D = A Y for this round's 16 values (B fragments bw), then each lane's share of
+  // c_{i,j} 2^(M j) into row il of S
+  __device__ __forceinline__ void product_add(const uint32_t (&bw)[NS][4], uint64_t *S, int32_t RS,
+                                              int32_t M, int il, int j, int g) {
+    crt_i32x4 acc[TN];
+#pragma unroll
+    for (int T = 0; T < TN; ++T) acc[T] = crt_i32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const crt_i32x4 bf{(int)bw[st][0], (int)bw[st][1], (int)bw[st][2], (int)bw[st][3]};
+#pragma unroll
+      for (int T = 0; T < TN; ++T)
+        acc[T] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[T][st], bf, acc[T], 0, 0, 0);
+    }
+    // c_{i,j} 2^(M j) = c_{i,j} 2^s 2^(32 q) with s in 1..32 (q = -1 for j = 0: word -1
+    // of a row is the end of the previous row or, for row 0, a spare word, and only
+    // receives the zero below the value's first word)
+    const int64_t bit = (int64_t)M * j;
+    // M j < 2 N, and convert-in's LDS tile keeps N below 2^19 bits: a 32-bit word index
+    const int qw = (int)((bit - 1) >> 5);
+    const uint32_t rsh = (uint32_t)(32 * (qw + 1) - bit);  // 32 - s, in 0..31
+    unsigned long long *Sw =
+        reinterpret_cast<unsigned long long *>(S + (int64_t)il * RS + qw + TN * g);
+    // the words of sum_i D[4 T + i] 2^(8 i) plus the carry, in 32-bit steps (every
+    // digit sum is below 2^21 in magnitude, so t1, t2, t3 fit 31 bits)
+    int32_t c = 0;
+    uint32_t prev = 0;
+#pragma unroll
+    for (int T = 0; T < TN; ++T) {
+      const int32_t t1 = acc[T][0] + c + (int32_t)((uint32_t)acc[T][1] << 8);
+      const int32_t t2 = (t1 >> 16) + acc[T][2];
+      const int32_t t3 = t2 + (int32_t)((uint32_t)acc[T][3] << 8);
+      const uint32_t wd = __builtin_amdgcn_perm((uint32_t)t3, (uint32_t)t1, 0x05040100u);
+      c = t3 >> 16;
+      // bits 32 - s .. 63 - s of (wd, prev): the word shifted left by s, with the
+      // previous word's top s bits below
+      atomicAdd(&Sw[T], (unsigned long long)__builtin_amdgcn_alignbit(wd, prev, rsh));
+      prev = wd;
+    }
+    // the lane's carry out (a signed multiple of 2^(32 TN)) with the last word's top bits
+    atomicAdd(&Sw[TN],
+              (unsigned long long)((int64_t)(((uint64_t)(int64_t)c << 32) | prev) >> rsh));
+  }
+
+  // Staged form: the wave's 64 values' terms go through LDS (Y, YW words per value), one
+  // value per lane while the residues are reduced.
+  __device__ __forceinline__ void run_staged(uint64_t *S, int32_t RS, uint32_t *Y,
+                                             const uint4 *cw, const uint32_t *__restrict__ X,
+                                             int64_t L, int32_t K, int32_t M, int32_t logTI,
+                                             int ti, int64_t i0) {
+    constexpr int CH = 6;             // terms whose constants are read from LDS together
+    const int TI = 1 << logTI;
+    const int J = 2 * K - 1;
+    const int64_t twoK = 2 * (int64_t)K;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, v = lane & 15;
+    uint32_t *Yw = Y + wave * 64 * YW;
+    const int items = J << logTI;
+    for (int base = wave * 64; base < items; base += BLOCK) {   // uniform per wave
+      {
+        const int item = base + lane;
+        const bool ok = item < items && (item & (TI - 1)) < ti;
+        const int64_t off = (int64_t)(item >> logTI) * L + i0 + (item & (TI - 1));
+        uint32_t y[YW];
+        if (base == wave * 64) {
+#pragma unroll
+          for (int k = 0; k < NP; ++k) y[k] = pres[k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < NP; ++k) y[k] = ok ? X[(int64_t)k * twoK * L + off] : 0u;
+        }
+        float f = 0.0f;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          if (k % CH == 0) asm volatile("" ::: "memory");   // bounds the constants in flight
+          const uint4 c = cw[k];
+          const uint32_t u = mul_shoup(y[k], make_uint2(c.x, c.y), c.z);
+          const int32_t yc = u > (c.z >> 1) ? (int32_t)(u - c.z) : (int32_t)u;
+          f = fmaf((float)yc, __uint_as_float(c.w), f);
+          y[k] = ((uint32_t)yc + 0x80808080u) ^ 0x80808080u;
+        }
+        y[NP] = (uint32_t)__float2int_rn(f) & 0xFFu;
+#pragma unroll
+        for (int k = NP + 1; k < YW; ++k) y[k] = 0;
+#pragma unroll
+        for (int q = 0; q < YW / 4; ++q)
+          *reinterpret_cast<uint4 *>(&Yw[lane * YW + 4 * q]) =
+              make_uint4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll 1
+      for (int r = 0; r < 4; ++r) {
+        const int vi = 16 * r + v;
+        const int item = base + vi;
+        const bool ok = item < items && (item & (TI - 1)) < ti;
+        const int il = ok ? item & (TI - 1) : 0, j = ok ? item >> logTI : 0;
+        const uint32_t *yv = Yw + vi * YW;
+        uint32_t bw[NS][4];
+        {
+          uint4 q = make_uint4(0u, 0u, 0u, 0u);
+          if (4 * g < YW) q = *reinterpret_cast<const uint4 *>(yv + 4 * g);   // terms 4 g + w
+          bw[0][0] = q.x; bw[0][1] = q.y; bw[0][2] = q.z; bw[0][3] = q.w;
+        }
+#pragma unroll
+        for (int st = 1; st < NS; ++st)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int q = crt_term(st, g, w);
+            bw[st][w] = q < NT ? yv[q] : 0u;
+          }
+        product_add(bw, S, RS, M, il, j, g);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+  }
+
+  // Register form: lane group g loads and reduces the residues of its terms for the round's
+  // value and builds its share of the B operand in registers.
+  __device__ __forceinline__ void run(uint64_t *S, int32_t RS, const uint4 *cw,
                                       const uint32_t *__restrict__ X, int64_t L, int32_t K,
                                       int32_t M, int32_t logTI, int ti, int64_t i0) {
-  const int TI = 1 << logTI;
-  const int J = 2 * K - 1;
-  const int64_t twoK = 2 * (int64_t)K;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = lane >> 4, v = lane & 15;
-  uint32_t *Yw = Y + wave * 64 * YW;
-  const int items = J << logTI;
-  for (int base = wave * 64; base < items; base += BLOCK) {   // uniform per wave
-    {
-      const int item = base + lane;
-      const int il = item & (TI - 1), j = item >> logTI;
-      const bool ok = item < items && il < ti;
-      const int64_t off = (int64_t)j * L + i0 + il;
-      uint32_t y[YW];
-      if (base == wave * 64) {
-#pragma unroll
-        for (int k = 0; k < NP; ++k) y[k] = pre[k];
-      } else {
-#pragma unroll
-        for (int k = 0; k < NP; ++k) y[k] = ok ? X[(int64_t)k * twoK * L + off] : 0u;
-      }
-      float f = 0.0f;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        if (k % CH == 0) asm volatile("" ::: "memory");   // bounds the constants in flight
-        const uint4 c = cw[k];
-        const uint32_t u = mul_shoup(y[k], make_uint2(c.x, c.y), c.z);
-        const int32_t yc = u > (c.z >> 1) ? (int32_t)(u - c.z) : (int32_t)u;
-        f = fmaf((float)yc, __uint_as_float(c.w), f);
-        // |yc| < 2^30: the bytes of yc + 0x80808080 are its balanced digits plus 128
-        y[k] = ((uint32_t)yc + 0x80808080u) ^ 0x80808080u;
-      }
-      y[NP] = (uint32_t)__float2int_rn(f) & 0xFFu;
-#pragma unroll
-      for (int k = NP + 1; k < YW; ++k) y[k] = 0;
-#pragma unroll
-      for (int q = 0; q < YW / 4; ++q)
-        *reinterpret_cast<uint4 *>(&Yw[lane * YW + 4 * q]) =
-            make_uint4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int TI = 1 << logTI;
+    const int J = 2 * K - 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, v = lane & 15;
+    const int items = J << logTI;
+    // rounds of 16 values; each round's residues are loaded one round ahead
+    const int nbase = items > wave * 64 ? (items - wave * 64 + BLOCK - 1) / BLOCK : 0;
+    const int nr = 4 * nbase;
 #pragma unroll 1
-    for (int r = 0; r < 4; ++r) {
-      const int vi = 16 * r + v;
-      crt_i32x4 acc[TN];
+    for (int gr = 0; gr < nr; ++gr) {
+        const int item = round_item(gr, v);
+        const bool ok = item < items && (item & (TI - 1)) < ti;
+        const int il = ok ? item & (TI - 1) : 0, j = ok ? item >> logTI : 0;
+        uint32_t res[NS][4];
 #pragma unroll
-      for (int T = 0; T < TN; ++T) acc[T] = crt_i32x4{0, 0, 0, 0};
+        for (int st = 0; st < NS; ++st)
 #pragma unroll
-      for (int st = 0; st < NS; ++st) {
-        const int w0 = 16 * st + 4 * g;
-        uint4 q = make_uint4(0u, 0u, 0u, 0u);
-        if (w0 < YW) q = *reinterpret_cast<const uint4 *>(&Yw[vi * YW + w0]);
-        const crt_i32x4 bf{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+          for (int w = 0; w < 4; ++w) res[st][w] = pre[st][w];
+        if (gr + 1 < nr) load(pre, X, L, K, logTI, ti, i0, round_item(gr + 1, v), g);
+        uint32_t bw[NS][4];
+        float f = 0.0f;
 #pragma unroll
-        for (int T = 0; T < TN; ++T)
-          acc[T] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[T][st], bf, acc[T], 0, 0, 0);
-      }
-      const int item = base + vi;
-      const bool ok = item < items && (item & (TI - 1)) < ti;
-      const int il = ok ? item & (TI - 1) : 0, j = ok ? item >> logTI : 0;
-      // c_{i,j} 2^(M j) = c_{i,j} 2^s 2^(32 q) with s in 1..32 (q = -1 for j = 0: word -1
-      // of a row is the end of the previous row or, for row 0, a spare word, and only
-      // receives the zero below the value's first word)
-      const int64_t bit = (int64_t)M * j;
-      // M j < 2 N, and convert-in's LDS tile keeps N below 2^19 bits: a 32-bit word index
-      const int q = (int)((bit - 1) >> 5);
-      const uint32_t rsh = (uint32_t)(32 * (q + 1) - bit);  // 32 - s, in 0..31
-      unsigned long long *Sw =
-          reinterpret_cast<unsigned long long *>(S + (int64_t)il * RS + q + TN * g);
-      // the words of sum_i D[4 T + i] 2^(8 i) plus the carry, in 32-bit steps (every
-      // digit sum is below 2^21 in magnitude, so t1, t2, t3 fit 31 bits)
-      int32_t c = 0;
-      uint32_t prev = 0;
+        for (int st = 0; st < NS; ++st)
 #pragma unroll
-      for (int T = 0; T < TN; ++T) {
-        const int32_t t1 = acc[T][0] + c + (int32_t)((uint32_t)acc[T][1] << 8);
-        const int32_t t2 = (t1 >> 16) + acc[T][2];
-        const int32_t t3 = t2 + (int32_t)((uint32_t)acc[T][3] << 8);
-        const uint32_t wd = __builtin_amdgcn_perm((uint32_t)t3, (uint32_t)t1, 0x05040100u);
-        c = t3 >> 16;
-        // bits 32 - s .. 63 - s of (wd, prev): the word shifted left by s, with the
-        // previous word's top s bits below
-        atomicAdd(&Sw[T], (unsigned long long)__builtin_amdgcn_alignbit(wd, prev, rsh));
-        prev = wd;
-      }
-      // the lane's carry out (a signed multiple of 2^(32 TN)) with the last word's top bits
-      atomicAdd(&Sw[TN],
-                (unsigned long long)((int64_t)(((uint64_t)(int64_t)c << 32) | prev) >> rsh));
+          for (int w = 0; w < 4; ++w) {
+            const int q = crt_term(st, g, w);
+            bw[st][w] = 0u;
+            if (q < NP) {
+              const uint4 c = cw[q];
+              const uint32_t u = mul_shoup(res[st][w], make_uint2(c.x, c.y), c.z);
+              const int32_t yc = u > (c.z >> 1) ? (int32_t)(u - c.z) : (int32_t)u;
+              f = fmaf((float)yc, __uint_as_float(c.w), f);
+              // |yc| < 2^29: the bytes of yc + 0x80808080 are its balanced digits plus 128
+              bw[st][w] = ((uint32_t)yc + 0x80808080u) ^ 0x80808080u;
+            }
+          }
+        // the four groups' shares (every lane adds them in the same pairs, so all agree)
+        f += __shfl_xor(f, 16, 64);
+        f += __shfl_xor(f, 32, 64);
+        const uint32_t tb = (uint32_t)__float2int_rn(f) & 0xFFu;
+#pragma unroll
+        for (int st = 0; st < NS; ++st)
+#pragma unroll
+          for (int w = 0; w < 4; ++w)
+            if (crt_term(st, g, w) == NP) bw[st][w] = tb;
+        product_add(bw, S, RS, M, il, j, g);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  }
   }
 };
 
 // NP = np exactly and W = NP words per CRT value (32 NP >= log2 P + 1 since every
 // prime is below 2^30).  Per workgroup: TI consecutive coefficients; S holds their
-// output words as 64-bit partial sums.
-template <int NP>
+// output words as 64-bit partial sums.  FORM: the matrix form's staged (1) or register
+// (0) variant fixed at compile time, or chosen at run time by recover_staged (-1).
+template <int NP, int FORM = -1>
 __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__restrict__ X,
                              int64_t L, int32_t K, int32_t M, int64_t nout, int32_t nw32,
                              int32_t wc, int32_t logTI, const PrimeDev *__restrict__ primes,
@@ -1124,17 +1225,18 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
   if (i0 >= nout) return;
   const int ti = (int)min<int64_t>(TI, nout - i0);
   // S: TI rows of RS partial sums (nw32 output words and, in the matrix form, room for
-  // every word the CRT's lane groups touch), then either the staged CRT terms and per
-  // prime (c_k Shoup pair, p_k, 1/p_k in single precision) (matrix form), or, as [u][k]
+  // every word the CRT's lane groups touch), then either per prime (c_k Shoup pair, p_k,
+  // 1/p_k in single precision) (matrix form), or, as [u][k]
   // (W x NPE words), P/p_k for k < np and, at k = np, 2^(32 W) - P (P is odd, so its
   // negation is ~P + 1 = -P[0], ~P[1], ...), then per prime (c_k Shoup pair, p_k) and 1/p_k
   CrtMatrix<MF ? NP : 1> cm;
-  if constexpr (MF) cm.prefetch(X, L, K, logTI, ti, i0, pd);
+  const bool staged = FORM >= 0 ? FORM == 1 : recover_staged(NP, K, M, nw32, logTI);
+  if constexpr (MF) cm.template prefetch<FORM>(staged, X, L, K, logTI, ti, i0, pd);
   const int RS = recover_row_words(NP, K, M, nw32);
   uint64_t *const S0 = S;             // a spare word, then the rows
   S = S0 + 1;
   uint32_t *cq = reinterpret_cast<uint32_t *>(S0 + ((((int64_t)RS << logTI) + 2) & ~(int64_t)1));
-  uint32_t *ci = cq + (MF ? BLOCK * crt_stage_words(NP) : NPE * W);
+  uint32_t *ci = cq + (MF ? (staged ? BLOCK * crt_stage_words(NP) : 0) : NPE * W);
   double *cr = reinterpret_cast<double *>(ci + ((3 * NP + 1) & ~1));
   if constexpr (MF) {
     uint4 *cw = reinterpret_cast<uint4 *>(ci);
@@ -1157,7 +1259,10 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
   for (int idx = threadIdx.x; idx < ti * RS; idx += BLOCK) S[idx] = 0;
   __syncthreads();
   if constexpr (MF) {
-    cm.run(S, RS, cq, reinterpret_cast<const uint4 *>(ci), X, L, K, M, logTI, ti, i0);
+    if (FORM != 0 && staged)
+      cm.run_staged(S, RS, cq, reinterpret_cast<const uint4 *>(ci), X, L, K, M, logTI, ti, i0);
+    else if (FORM != 1)
+      cm.run(S, RS, reinterpret_cast<const uint4 *>(ci), X, L, K, M, logTI, ti, i0);
   } else {
   // ---- CRT of each c_{i,j}, then add c_{i,j} 2^(M j) into the output words ----
   for (int idx = threadIdx.x; idx < (J << logTI); idx += BLOCK) {

@@ -21,9 +21,12 @@ constexpr int MAX_COL_PASSES = 4;
 constexpr int CRT_MFMA_NP = 20;
 constexpr int CRT_STEPS = 2;
 constexpr int CRT_TILES = 6;
-// Words each recovery value stages in LDS for the matrix cores: its np terms and t,
-// rounded to a 16-byte fragment.
-constexpr int crt_stage_words(int np) { return 4 * ((np + 4) / 4); }
+// The CRT term (y_q for q < np, t for q = np, none above) whose four bytes lane group g
+// supplies as word w of the matrix product's step s: terms 0..15 in step 0, four per
+// group, then 16, 17, ... spread over the groups first.
+__host__ __device__ constexpr int crt_term(int s, int g, int w) {
+  return s == 0 ? 4 * g + w : 16 + g + 4 * w;
+}
 // 16-digit tiles of one CRT value, each lane group of the matrix product holding one
 // 32-bit word of each: 4 TN words >= the bytes of P plus the three bytes of the offsets.
 constexpr int crt_tiles(int np) { return (4 * np + 8 + 15) / 16; }
@@ -91,14 +94,29 @@ __host__ __device__ inline int recover_row_words(int np, int K, int M, int nw32)
 }
 
 // LDS of one recovery workgroup: a spare word, 2^log_ti coefficient rows of partial sums
-// (rounded to 16 bytes), then either
-// the CRT's staged terms and 4 words of constants per prime (matrix form), or its word
-// table and 3 words and a double per prime.
+// (rounded to 16 bytes), then either the staged terms (staged matrix form) and 4 words of
+// constants per prime (matrix form), or the CRT's word table and 3 words and a double per
+// prime.
+// Words each value stages in LDS in the recovery's staged matrix form: its np terms and
+// t, rounded to a 16-byte fragment.
+__host__ __device__ constexpr int crt_stage_words(int np) { return 4 * ((np + 4) / 4); }
+
+// The matrix-form recovery stages each wave's 64 values' terms in LDS (one value per
+// lane while the residues are reduced) when the rows and the staging fit in 40 KiB, so
+// that four workgroups share a CU; with longer rows each lane group builds its share of
+// the terms in registers instead.
+__host__ __device__ inline bool recover_staged(int np, int K, int M, int nw32, int log_ti) {
+  if (np > CRT_MFMA_NP) return false;
+  const int64_t rows = 8 * ((((int64_t)recover_row_words(np, K, M, nw32) << log_ti) + 2) & ~(int64_t)1);
+  return rows + 4 * (int64_t)BLOCK * crt_stage_words(np) <= 40 * 1024;
+}
+
 inline size_t recover_lds_bytes(int np, int K, int M, int nw32, int log_ti) {
   // a spare word before the rows, rounded to 16 bytes
   size_t b = sizeof(uint64_t) * ((((size_t)recover_row_words(np, K, M, nw32) << log_ti) + 2) & ~(size_t)1);
-  if (np <= CRT_MFMA_NP)
-    return b + sizeof(uint32_t) * ((size_t)BLOCK * crt_stage_words(np) + 4 * (size_t)np);
+  if (recover_staged(np, K, M, nw32, log_ti))
+    b += sizeof(uint32_t) * (size_t)BLOCK * crt_stage_words(np);
+  if (np <= CRT_MFMA_NP) return b + sizeof(uint32_t) * 4 * (size_t)np;
   b += sizeof(uint32_t) * (size_t)((np + 2) & ~1) * np;
   return b + sizeof(uint32_t) * ((3 * np + 1) & ~1) + sizeof(double) * np;
 }

@@ -10,8 +10,9 @@ computation on the CPU with the library's A, in the kernel's lane order:
   column l mod 16 of B, each with the 16 consecutive slots 16 (l / 16) + b of a 64-slot
   step; D row 4 (l / 16) + i, column l mod 16 to lane l) -- the layout a probe on gfx950
   confirmed;
-* the staged terms: y_k + 0x80808080 with every byte flipped, i.e. balanced signed bytes,
-  t in byte 0 of term np, zeros up to the fragment;
+* the terms: y_k + 0x80808080 with every byte flipped, i.e. balanced signed bytes, t in
+  byte 0 of term np, lane group g supplying term 4 g + w of step 0 and 16 + g + 4 w of
+  step 1 as its word w;
 * each lane group's fold of its digit sums into consecutive 32-bit words and a carry.
 
 The reconstruction must equal c exactly for random c with |c| < P / (2 (1 + 2^-12)) (the
@@ -47,29 +48,33 @@ def matrix(np_):
     return TN, frag.reshape(TN, 2, 64, 16)
 
 
+def term(st, g, w):
+    """The term lane group g supplies as word w of step st."""
+    return 4 * g + w if st == 0 else 16 + g + 4 * w
+
+
 def stage(y, t, np_):
-    """The words the kernel stages for one value: 4 * ceil((np + 1) / 4) of them."""
-    yw = 4 * ((np_ + 4) // 4)
-    w = [((v + 0x80808080) & 0xFFFFFFFF) ^ 0x80808080 for v in y] + [t & 0xFF]
-    return w + [0] * (yw - len(w))
+    """One value's terms as the kernel encodes them: y_q's balanced bytes (the bytes of
+    y_q + 0x80808080, each flipped), t in byte 0 of term np."""
+    return [((v + 0x80808080) & 0xFFFFFFFF) ^ 0x80808080 for v in y] + [t & 0xFF]
 
 
 def mfma_model(A_frag, words, TN):
     """D for 16 values: A fragments (TN, 2, 64, 16) and each value's staged words."""
-    yw = len(words[0])
+    nterms = len(words[0])
     D = np.zeros((TN, 16, 16), dtype=np.int64)          # tile, row, column (value)
     for st in range(2):
         B = np.zeros((64, 16), dtype=np.int64)         # slot, value
         for v in range(16):
             for g in range(4):
-                w0 = 16 * st + 4 * g
-                if w0 >= yw:
-                    continue
-                for q in range(4):
-                    x = words[v][w0 + q]
+                for w in range(4):
+                    q = term(st, g, w)
+                    if q >= nterms:
+                        continue
+                    x = words[v][q]
                     for a in range(4):
                         b = ((x >> (8 * a)) & 255)
-                        B[16 * g + 4 * q + a, v] = b - 256 if b >= 128 else b
+                        B[16 * g + 4 * w + a, v] = b - 256 if b >= 128 else b
         for T in range(TN):
             A = np.zeros((16, 64), dtype=np.int64)
             for lane in range(64):
