@@ -383,10 +383,11 @@ __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__
       const uint32_t p = pk[k];
       const uint2 one = make_uint2(1u, primes[k].ones);
       const uint2 c32 = make_uint2(primes[k].c32, primes[k].c32s);
-      uint32_t r = add_mod(mul_shoup((uint32_t)lo[k], one, p),
-                           mul_shoup((uint32_t)(lo[k] >> 32), c32, p), p);
-      r = add_mod(r, mul_shoup(hi[k], ld_tab(primes[k].pow32, 2), p), p);   // 2^64 mod p
-      if (neg_top) r = sub_mod(r, pd->pow2M[k], p);
+      // reduced up to one p, as the transforms take their inputs
+      uint32_t r = add_lz(mul_shoup_lz((uint32_t)lo[k], one, p),
+                          mul_shoup_lz((uint32_t)(lo[k] >> 32), c32, p), p);
+      r = add_lz(r, mul_shoup_lz(hi[k], ld_tab(primes[k].pow32, 2), p), p);   // 2^64 mod p
+      if (neg_top) r = sub_lz(r, pd->pow2M[k], p);
       X[((int64_t)k * twoK + col_off + j) * L + i0 + il] = r;
     }
   }
@@ -398,7 +399,8 @@ __device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__
 // frequencies in natural order.  Forward: DIF, then multiply frequency k by
 // w_{nS}^(inner k).  Inverse: multiply by w_{nS}^(-inner k), then DIT.  Each thread
 // meets the frequencies k = e0, e0 + de, ... of one column, so its twiddles form a
-// geometric progression kept in Montgomery form (no table gathers).
+// geometric progression kept in Montgomery form (no table gathers), advanced by a Shoup
+// product with the constant ratio.
 // ------------------------------------------------------------------------------------
 // cols: columns transformed per prime, those from col0 on among each prime's 2K (K of
 // them when only one operand's limbs need a forward transform: a square, or one
@@ -439,8 +441,11 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   const int64_t inner = inner0 + t;
   const uint2 *tab = inverse ? pr.hi : pr.hf;
   const uint32_t R = pr.c32;   // 2^32 mod p
+  // cur: the twiddle in Montgomery form (times 2^32), applied by a Montgomery product;
+  // step: the ratio of consecutive twiddles with its Shoup companion, so that the
+  // progression is a Shoup product (which keeps the Montgomery form)
   uint32_t cur = mul_shoup(R, heap_root(tab, m, (inner * e0) & (m - 1), p), p);
-  const uint32_t step = mul_shoup(R, heap_root(tab, m, (inner * de) & (m - 1), p), p);
+  const uint2 step = heap_root(tab, m, (inner * de) & (m - 1), p);
   // offsets inside the column stay below L <= 2^21: 32-bit index arithmetic
   const int lim_store = (int)std::min<int64_t>(std::max<int64_t>(nlimit - first, 0), L);
   // every global access of this thread is in its own column t (BLOCK is a multiple of
@@ -459,7 +464,7 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     else lds_dif(s, LdsShape{logT, logn, 1, T, 0, 0}, pr.hf, p);
     for (int e = e0; e < n; e += de) {
       const uint32_t v = mont_mul_lz(s[(bitrev(e, logn) << logT) + t], cur, p, pr.pinv);
-      cur = mont_mul_lz(cur, step, p, pr.pinv);
+      cur = mul_shoup_lz(cur, step, p);
       bt[e << logS] = v;
     }
   } else {
@@ -476,7 +481,7 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
         const int ee = e + u * de;
         if (ee < n) {
           s[(bitrev(ee, logn) << logT) + t] = mont_mul_lz(v[u], cur, p, pr.pinv);
-          cur = mont_mul_lz(cur, step, p, pr.pinv);
+          cur = mul_shoup_lz(cur, step, p);
         }
       }
     }
