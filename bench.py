@@ -17,7 +17,9 @@ operands), ``p64`` (64-bit machine-word primes) and ``gfp`` (one generalized Fer
 prime) on the same product, ``latency`` (d = 1024 signed 64-bit coefficients, median and
 p99 per call), ``large`` (d = 2^18, 16384-bit magnitudes), ``batched`` (4096 products of
 uneven size, one at a time through zpm_mul against tuned zpm_mul_batch with graph
-replay) and ``served`` (an open-loop Poisson stream through the continuous-batching
+replay), ``operand_batch`` (1024 products of 512 x 1025-bit coefficients with one factor
+held as a resident operand: zpm_mul_operand_batch against zpm_mul_batch and against
+zpm_mul_operand one at a time) and ``served`` (an open-loop Poisson stream through the continuous-batching
 server at a stated fraction of its saturated throughput, with p50/p99 latency, and the
 same stream through the single-product baseline).  Batched, served and large legs state
 their roofline fraction T*/T, T* being the sum over each product's kernels of
@@ -190,6 +192,84 @@ def batch_leg(ctx, reps: int) -> dict:
             "persistent_identical_to_plain": same_persistent,
             "t_star_ms": ts, "roofline_frac": ts / batch_ms, "plain_roofline_frac": ts / plain_ms,
             "tune_s": tune_s, "tuned_classes": len(ctx.tune_table())}
+
+
+def operand_batch_leg(ctx, reps: int, n: int = 1024, d: int = 512, mag: int = 1024) -> dict:
+    """One factor b held as a resident operand times n different a of the same shape (d
+    coefficients, magnitudes uniform below 2^mag, uniform signs; seeds 21 and 22):
+    zpm_mul_operand_batch (graph replay) against zpm_mul_batch of the same products,
+    which converts and transforms b in every product, and against zpm_mul_operand one
+    product at a time.  All three outputs must be identical."""
+    import torch
+    from paper_1612_05778_amd import _native as nat
+    from paper_1612_05778_amd import synth
+    from paper_1612_05778_amd.api import Operand, out_words
+    print(f"[bench] operand batch leg: {n} x {d} coefficients of {mag + 1} bits",
+          file=sys.stderr, flush=True)
+    N = mag + 1
+    w = (N + 63) // 64
+    pb = synth.dense(21, d, mag)
+    r = synth.rng_for(22)
+    A = torch.empty((n, d, w), dtype=torch.int64)
+    for i in range(n):
+        words, _ = synth.signed_words(r, d, mag)
+        A[i] = torch.from_numpy(words.view(np.int64))
+    A = A.cuda()
+    B = torch.from_numpy(np.ascontiguousarray(pb.b).view(np.int64)).cuda()
+    wc = out_words(d, N, d, N)
+    C = torch.zeros((n, 2 * d - 1, wc), dtype=torch.int64, device="cuda")
+    op = Operand(ctx, B, N, d, N)
+    jobs = (nat.Job * n)()
+    ojobs = (nat.OperandJob * n)()
+    for i in range(n):
+        jobs[i].a, jobs[i].da, jobs[i].Na = A[i].data_ptr(), d, N
+        jobs[i].b, jobs[i].db, jobs[i].Nb = B.data_ptr(), d, N
+        jobs[i].c, jobs[i].wc = C[i].data_ptr(), wc
+        ojobs[i].a, ojobs[i].da, ojobs[i].Na, ojobs[i].op = A[i].data_ptr(), d, N, op._h
+        ojobs[i].c, ojobs[i].wc = C[i].data_ptr(), wc
+    st = torch.cuda.current_stream()
+    h = st.cuda_stream
+    bits = float(n * (2 * d - 1) * (64 * wc))
+
+    def timed(fn, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(k):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    def plain_batch():
+        nat.check(nat.zpm_mul_batch(ctx.handle, jobs, n, nat.ZPM_BATCH_GRAPH, h), "zpm_mul_batch")
+
+    def operand_batch():
+        nat.check(nat.zpm_mul_operand_batch(ctx.handle, ojobs, n, nat.ZPM_BATCH_GRAPH, h),
+                  "zpm_mul_operand_batch")
+
+    def one_by_one():
+        for i in range(n):
+            nat.check(nat.zpm_mul_operand(ctx.handle, ojobs[i].a, d, N, op._h, ojobs[i].c, wc, h),
+                      "zpm_mul_operand")
+
+    batch_ms = timed(plain_batch, reps)
+    ref = C.clone()
+    C.zero_()
+    single_ms = timed(one_by_one, 2)
+    same_single = bool(torch.equal(C, ref))
+    C.zero_()
+    op_ms = timed(operand_batch, reps)
+    same = bool(torch.equal(C, ref))
+    info = op.info()
+    op.close()
+    return {"workload": f"operand{d}x{N}_batch{n}", "products": n, "out_bits": bits,
+            "ms": op_ms, "value": bits / (op_ms / 1e3),
+            "plan": {"K": info["K"], "np": info["np"], "log2_L": info["log2_L"]},
+            "batch_ms": batch_ms, "vs_batch": batch_ms / op_ms,
+            "single_ms": single_ms, "vs_single": single_ms / op_ms,
+            "identical_to_batch": same, "single_identical_to_batch": same_single}
 
 
 def t_star_of(da: int, Na: int, db: int, Nb: int) -> float:
@@ -822,6 +902,7 @@ def main() -> int:
         line["large"] = large_leg(ctx, args.large_steps)
     if not args.no_batch:
         line["batched"] = batch_leg(ctx, args.batch_reps)
+        line["operand_batch"] = operand_batch_leg(ctx, args.batch_reps)
     if not args.no_served:
         line["served"] = served_leg(ctx, args.served_requests, args.served_warmup, args.served_load,
                                     int(args.served_budget_gib * (1 << 30)), args.served_streams,

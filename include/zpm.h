@@ -376,6 +376,37 @@ int zpm_mul_operand(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, con
 int zpm_operand_info(const zpm_operand *op, zpm_plan_info *out);
 void zpm_operand_destroy(zpm_operand *op);
 
+/* Many products with resident operands.  Each job multiplies its a (da coefficients of
+ * Na bits, within its operand's bounds) by the b of its operand op (Section 2.1: only
+ * a is converted and transformed; the pointwise products take b's spectra as they
+ * are) into c of wc words per coefficient, as zpm_mul_operand would.  Jobs may name
+ * different operands, and one operand any number of times.
+ * zpm_mul_operand_batch runs them as zpm_mul_batch runs its jobs: one grouped launch
+ * per pipeline level, stage and compiled variant, and flags = ZPM_BATCH_GRAPH replays a
+ * captured graph while the jobs (and their operands) stay the same; ZPM_BATCH_PERSISTENT
+ * returns ZPM_ENOTIMPL.  ZPM_EUNSUPPORTED when an operand's plan is beyond the batch
+ * kernels (more than 20 primes, or K = 32): such
+ * products run through zpm_mul_operand.  Ownership and streams are as for zpm_mul_batch;
+ * the operands must outlive the products that use them.
+ *
+ * zpm_server_submit_operand queues one such product on a server (zpm_server_create)
+ * of the operand's context and returns its ticket, as zpm_server_submit does.  Small
+ * requests join the server's batches beside ordinary ones; large ones, and those whose
+ * operand plan the batch kernels do not cover, run alone.  The caller keeps a, c and the
+ * operand alive until the ticket is reported finished.  ZPM_EINVAL for a null operand,
+ * an operand of another context (or a simulated server), or an a beyond its bounds. */
+typedef struct zpm_operand_job {
+  const uint64_t *a;
+  int64_t da;
+  int32_t Na;
+  const zpm_operand *op;
+  uint64_t *c;
+  int32_t wc;
+} zpm_operand_job;
+int zpm_mul_operand_batch(zpm_ctx *ctx, const zpm_operand_job *jobs, int64_t n, int32_t flags,
+                          void *stream);
+int zpm_server_submit_operand(zpm_server *srv, const zpm_operand_job *job, uint64_t *ticket);
+
 /* 64-bit machine-word primes (Section 4: the modulus is one machine-word Fourier
  * prime or the product of two or three of them, combined by the Chinese remaindering
  * algorithm; the paper's implementation uses two).  Same method and result as

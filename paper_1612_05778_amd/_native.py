@@ -167,6 +167,17 @@ zpm_mul_operand = _sig("zpm_mul_operand", ctypes.c_int,
 zpm_operand_info = _sig("zpm_operand_info", ctypes.c_int, [c_vp, ctypes.POINTER(PlanInfo)])
 zpm_operand_destroy = _sig("zpm_operand_destroy", None, [c_vp])
 
+
+class OperandJob(ctypes.Structure):
+    _fields_ = [("a", c_vp), ("da", c_i64), ("Na", c_i32), ("op", c_vp), ("c", c_vp),
+                ("wc", c_i32)]
+
+
+zpm_mul_operand_batch = _sig("zpm_mul_operand_batch", ctypes.c_int,
+                             [c_vp, ctypes.POINTER(OperandJob), c_i64, c_i32, c_vp])
+zpm_server_submit_operand = _sig("zpm_server_submit_operand", ctypes.c_int,
+                                 [c_vp, ctypes.POINTER(OperandJob), ctypes.POINTER(c_u64)])
+
 class KronInfo(ctypes.Structure):
     _fields_ = [("chunk_bits", c_i32), ("s_a", c_i32), ("s_b", c_i32), ("S", c_i32),
                 ("da2", c_i64), ("db2", c_i64), ("N2", c_i32), ("wc2", c_i32),
@@ -240,7 +251,8 @@ EXPORTS = ["zpm_version", "zpm_strerror", "zpm_out_bits", "zpm_plan", "zpm_prime
            "zpm_server_create_simulated", "zpm_server_submit", "zpm_server_poll",
            "zpm_server_wait", "zpm_server_completions", "zpm_server_stats",
            "zpm_server_reset_stats", "zpm_server_destroy", "zpm_operand_create",
-           "zpm_mul_operand", "zpm_operand_info", "zpm_operand_destroy", "zpm_mul_kronecker",
+           "zpm_mul_operand", "zpm_operand_info", "zpm_operand_destroy",
+           "zpm_mul_operand_batch", "zpm_server_submit_operand", "zpm_mul_kronecker",
            "zpm_kronecker_plan", "zpm_plan_p64", "zpm_prime64", "zpm_mul_p64",
            "zpm_noalloc_max_bytes", "zpm_mul_noalloc", "zpm_gfp_prime", "zpm_gfp_root",
            "zpm_plan_gfp", "zpm_mul_gfp", "zpm_butterfly_ceiling", "zpm_crt_matrix"]

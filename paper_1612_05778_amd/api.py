@@ -303,6 +303,21 @@ class Context:
         nat.check(rc, "zpm_mul_batch")
         return res
 
+    def mul_operand_batch(self, items, graph: bool = False, stream=None, outs=None):
+        """Products a * b for many (a, Na, operand) in one call (zpm_mul_operand_batch):
+        each operand's b is taken as its resident spectra.  Returns the output tensors."""
+        n = len(items)
+        jobs = (nat.OperandJob * max(n, 1))()
+        res = []
+        for i, (a, Na, op) in enumerate(items):
+            jobs[i], o = op.job(a, Na, outs[i] if outs is not None else None)
+            res.append(o)
+        self._batch_jobs = (jobs, [op for (_, _, op) in items])
+        flags = nat.ZPM_BATCH_GRAPH if graph else 0
+        nat.check(nat.zpm_mul_operand_batch(self._h, jobs, n, flags, _stream_handle(stream)),
+                  "zpm_mul_operand_batch")
+        return res
+
     def _jobs(self, items, outs=None):
         n = len(items)
         jobs = (nat.Job * max(n, 1))()
@@ -394,6 +409,21 @@ class Operand:
                                       _stream_handle(stream)), "zpm_mul_operand")
         return out
 
+    def job(self, a: torch.Tensor, Na: int, out: torch.Tensor | None = None):
+        """(zpm_operand_job for a * b, output tensor); the job holds raw pointers, so the
+        caller keeps a, out and this operand alive while it is in use."""
+        da = _check_operand(a, Na, "a")
+        n = da + self.db - 1 if da else 0
+        wc = out_words(da, Na, self.db, self.Nb) if n else 1
+        if out is None:
+            out = torch.empty((n, wc), dtype=torch.int64, device=a.device)
+        elif out.dim() != 2 or out.shape[0] != n or out.dtype != torch.int64 or not out.is_contiguous():
+            raise ValueError("out has the wrong shape or dtype")
+        j = nat.OperandJob()
+        j.a, j.da, j.Na, j.op = a.data_ptr(), da, Na, self._h
+        j.c, j.wc = (out.data_ptr() if n else None), (out.shape[1] if n else wc)
+        return j, out
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             nat.zpm_operand_destroy(self._h)
@@ -468,6 +498,17 @@ class Server:
         job.b, job.db, job.Nb = b.data_ptr(), db, Nb
         job.c, job.wc = (out.data_ptr() if n else None), out.shape[1] if n else wc
         return self.submit_job(job, keep=(a, b, out)), out
+
+    def submit_operand(self, a: torch.Tensor, Na: int, op: "Operand",
+                       out: torch.Tensor | None = None) -> tuple[int, torch.Tensor]:
+        """Queue a * (op's b) against the operand's resident spectra; returns (ticket,
+        output tensor).  a, out and the operand are kept alive until the ticket ends."""
+        job, out = op.job(a, Na, out)
+        t = nat.c_u64()
+        nat.check(nat.zpm_server_submit_operand(self._h, ctypes.byref(job), ctypes.byref(t)),
+                  "zpm_server_submit_operand")
+        self._keep[t.value] = (a, out, op)
+        return t.value, out
 
     def poll(self, ticket: int):
         """None while queued or running, else (status, latency_s)."""

@@ -31,7 +31,8 @@ __global__ __launch_bounds__(BLOCK) void kg_convert(const JobDev *__restrict__ j
   const GroupSeg g = segs[find_seg(segs, nseg, blockIdx.x)];
   const JobDev &jb = jobs[g.job];
   const int64_t tile = (int64_t)blockIdx.x - g.start;
-  const bool ob = tile >= jb.tiles_a;      // tiles of a first, then tiles of b (none for a square)
+  // tiles of a first, then tiles of b (none for a square or a resident operand)
+  const bool ob = tile >= jb.tiles_a;
   const int32_t N = ob ? jb.Nb : jb.Na;
   body_convert_in<NP>(s, ob ? tile - jb.tiles_a : tile, ob ? jb.b : jb.a, ob ? jb.db : jb.da, N,
                       (N + 63) / 64, jb.K, jb.M, NP, jb.X, jb.L, ob ? jb.K : 0, jb.log_ti_in,
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(BLOCK) void kg_col(const JobDev *__restrict__ jobs,
   body_col_pass<CLOGN, CLOGT>(s, b - g.start, jb.X, L, 2 * jb.K, jb.col_logn[c], jb.col_S[c],
                 jb.col_logT[c], (outer && !inverse) ? jb.da : L, (outer && !inverse) ? jb.db : L,
                 jb.K, (outer && inverse) ? jb.nout : L, inverse, primes,
-                (jb.square && !inverse) ? jb.K : 2 * jb.K, 0);
+                ((jb.square || jb.spec) && !inverse) ? jb.K : 2 * jb.K, 0);
 }
 
 template <int LOGK, int MODE, int CLOGL1>
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(BLOCK) void kg_convolve_reg(const JobDev *__restric
   const bool direct = jb.ncol == 0;
   body_convolve_reg<LOGK, MODE, CLOGL1>(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.logL1,
                                 direct ? jb.da : L, direct ? jb.db : L, direct ? jb.nout : L,
-                                primes, jb.plan, nullptr);
+                                primes, jb.plan, jb.spec);
 }
 
 template <int CLOGK, int CLOGL1>
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(BLOCK) void kg_convolve(const JobDev *__restrict__ 
   while ((1 << logK) < jb.K) ++logK;
   body_convolve<CLOGK, CLOGL1>(s, (int64_t)blockIdx.x - g.start, jb.X, L, jb.K, logK, jb.logL1,
                 direct ? jb.da : L, direct ? jb.db : L, direct ? jb.nout : L, primes, jb.plan,
-                jb.square ? CM_SQUARE : CM_PRODUCT, nullptr);
+                jb.spec ? CM_WITH_SPECTRUM : jb.square ? CM_SQUARE : CM_PRODUCT, jb.spec);
 }
 
 hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *segs,
@@ -114,6 +115,7 @@ hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *seg
   case NP_: hipLaunchKernelGGL(kg_convert<NP_>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
         ZPM_G(1) ZPM_G(2) ZPM_G(3) ZPM_G(4) ZPM_G(5) ZPM_G(6) ZPM_G(7) ZPM_G(8)
         ZPM_G(9) ZPM_G(10) ZPM_G(11) ZPM_G(12) ZPM_G(13) ZPM_G(14) ZPM_G(15) ZPM_G(16)
+        ZPM_G(17) ZPM_G(18) ZPM_G(19) ZPM_G(20)
 #undef ZPM_G
         default: return hipErrorInvalidValue;
       }
@@ -124,6 +126,7 @@ hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *seg
   case NP_: hipLaunchKernelGGL(kg_recover<NP_>, grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
         ZPM_G(1) ZPM_G(2) ZPM_G(3) ZPM_G(4) ZPM_G(5) ZPM_G(6) ZPM_G(7) ZPM_G(8)
         ZPM_G(9) ZPM_G(10) ZPM_G(11) ZPM_G(12) ZPM_G(13) ZPM_G(14) ZPM_G(15) ZPM_G(16)
+        ZPM_G(17) ZPM_G(18) ZPM_G(19) ZPM_G(20)
 #undef ZPM_G
         default: return hipErrorInvalidValue;
       }
@@ -144,9 +147,10 @@ hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *seg
       break;
     }
     case SK_CONVOLVE: {
-      // variant: register kernel: log2 K, plus 16 for squares, plus 32 for the full inner
-      // factor; LDS kernel: 0 (any K), or 64 + log2 K with its full inner factor
-      if (gr.variant >= 64) {
+      // variant: register kernel: log2 K, plus 16 for squares or 128 for products with
+      // resident spectra, plus 32 for the full inner factor; LDS kernel: 0 (any K), or
+      // 64 + log2 K with its full inner factor
+      if (gr.variant >= 64 && gr.variant < 128) {
         switch (gr.variant - 64) {
           case 6: hipLaunchKernelGGL((kg_convolve<6, 5>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
           case 7: hipLaunchKernelGGL((kg_convolve<7, 4>), grid, blk, gr.lds, st, jobs, sg, ns, primes); break;
@@ -155,14 +159,16 @@ hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *seg
         }
         break;
       }
-      const bool sq = (gr.variant & 16) != 0, full = (gr.variant & 32) != 0;
+      const bool sq = (gr.variant & 16) != 0, full = (gr.variant & 32) != 0,
+                 ws = (gr.variant & 128) != 0;
       switch (gr.variant & 15) {
 #define ZPM_GM(LK_, M_)                                                                                      \
   if (full) hipLaunchKernelGGL((kg_convolve_reg<LK_, M_, 12 - LK_>), grid, blk, gr.lds, st, jobs, sg, ns, primes); \
   else hipLaunchKernelGGL((kg_convolve_reg<LK_, M_, -1>), grid, blk, gr.lds, st, jobs, sg, ns, primes);
 #define ZPM_G(LK_)                                                                            \
   case LK_:                                                                                   \
-    if (sq) { ZPM_GM(LK_, CM_SQUARE) } else { ZPM_GM(LK_, CM_PRODUCT) }                        \
+    if (ws) { ZPM_GM(LK_, CM_WITH_SPECTRUM) }                                                  \
+    else if (sq) { ZPM_GM(LK_, CM_SQUARE) } else { ZPM_GM(LK_, CM_PRODUCT) }                   \
     break;
         ZPM_G(1) ZPM_G(2) ZPM_G(3) ZPM_G(4)
 #undef ZPM_G
@@ -202,7 +208,7 @@ size_t stage_lds(const Plan &pl, int kind, int pass) {
 }
 
 bool batch_supports(const Plan &pl) {
-  if (pl.np < 1 || pl.np > 16) return false;
+  if (pl.np < 1 || pl.np > BATCH_NP_MAX) return false;
   for (int c = 0; c < pl.ncol; ++c)
     if (pl.col_tile[c] < 1 || pl.col_tile[c] > BLOCK) return false;   // steps by BLOCK / T
   if (pl.conv_reg && pl.K > 16) return false;

@@ -22,6 +22,7 @@ struct JobDev {
   uint64_t *c;
   uint32_t *X;              // this product's workspace slice (np * 2K * L words)
   const PlanDev *plan;
+  const uint32_t *spec;     // b's resident spectra (an operand's), or null
   int64_t da, db, nout, L;
   int64_t tiles_a;          // convert-in tiles of a; the following tiles convert b
   int64_t col_S[MAX_COL_PASSES];
@@ -67,7 +68,11 @@ hipError_t launch_persistent(const JobDev *jobs, const GroupSeg *segs, const Gro
                              hipStream_t st);
 // LDS bytes a stage of a plan needs (same formulas as the per-stage launchers).
 size_t stage_lds(const Plan &pl, int kind, int pass);
-// Whether the batch kernels have code for this plan.
+// Whether the batch kernels have code for this plan.  They take up to BATCH_NP_MAX
+// primes (the batch planner itself stays within 16; larger counts come with resident
+// operands planned for single products), the persistent kernel up to 16.
+constexpr int BATCH_NP_MAX = 20;
+constexpr int PERSIST_NP_MAX = 16;
 bool batch_supports(const Plan &pl);
 
 }  // namespace zpm

@@ -90,11 +90,22 @@ static int grow_host(T **p, int64_t *cap, int64_t n) {
   return ZPM_OK;
 }
 
-uint64_t BatchState::hash(const zpm_job *jobs, int64_t n, int32_t K_force, int32_t T_force) {
+uint64_t BatchState::hash(const zpm_job *jobs, int64_t n, int32_t K_force, int32_t T_force,
+                          const uint32_t *const *specs, const Plan *given) {
   uint64_t h = 1469598103934665603ull ^ (uint64_t)n ^ ((uint64_t)K_force << 40) ^
                ((uint64_t)T_force << 52);
   const unsigned char *p = reinterpret_cast<const unsigned char *>(jobs);
   for (size_t i = 0; i < sizeof(zpm_job) * (size_t)n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  if (specs) {
+    p = reinterpret_cast<const unsigned char *>(specs);
+    h = (h ^ 0x5bu) * 1099511628211ull;
+    for (size_t i = 0; i < sizeof(*specs) * (size_t)n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  }
+  if (given) {
+    p = reinterpret_cast<const unsigned char *>(given);
+    h = (h ^ 0xa7u) * 1099511628211ull;
+    for (size_t i = 0; i < sizeof(*given) * (size_t)n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  }
   return h;
 }
 
@@ -125,13 +136,13 @@ static int64_t stage_tiles(const Plan &pl, int kind, int pass) {
   switch (kind) {
     case SK_CONVERT: {
       const int64_t ti = (int64_t)1 << pl.log_ti_in;
-      return (pl.da + ti - 1) / ti + (pl.square ? 0 : (pl.db + ti - 1) / ti);
+      return (pl.da + ti - 1) / ti + ((pl.square || pl.spec) ? 0 : (pl.db + ti - 1) / ti);
     }
     case SK_COL_FWD:
     case SK_COL_INV: {
       const int64_t S = pl.col[pass].S;
       const int64_t nn = (int64_t)1 << pl.col[pass].logn;
-      const int64_t cols = (pl.square && kind == SK_COL_FWD) ? pl.K : 2 * pl.K;
+      const int64_t cols = ((pl.square || pl.spec) && kind == SK_COL_FWD) ? pl.K : 2 * pl.K;
       return (S / pl.col_tile[pass]) * (L / (nn * S)) * pl.np * cols;
     }
     case SK_CONVOLVE:
@@ -150,8 +161,9 @@ static int stage_variant(const Plan &pl, int kind, int pass) {
   int lk = 0;
   while ((1 << lk) < pl.K) ++lk;
   if (kind == SK_CONVOLVE && pl.conv_reg) {
-    // squares have a register kernel of their own; so has the full inner factor
-    return lk + (pl.square ? 16 : 0) + (fixed_reg_l1(lk, pl.logL1) ? 32 : 0);
+    // squares and products with resident spectra have register kernels of their own;
+    // so has the full inner factor
+    return lk + (pl.spec ? 128 : pl.square ? 16 : 0) + (fixed_reg_l1(lk, pl.logL1) ? 32 : 0);
   }
   if (kind == SK_CONVOLVE) return fixed_lds_kl1(lk, pl.logL1) ? 64 + lk : 0;
   if (kind == SK_COL_FWD || kind == SK_COL_INV) {
@@ -165,7 +177,7 @@ static int stage_variant(const Plan &pl, int kind, int pass) {
 // Host part of a batch: plans, job descriptors (X holds the workspace offset in words
 // until the buffer exists), grouped launches in level order.  No device work.
 int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHost &bh,
-                        const Plan *given, int32_t T_force) {
+                        const Plan *given, int32_t T_force, const uint32_t *const *specs) {
   int rc;
   bh = BatchHost();
   std::vector<Plan> &pls = bh.plans;
@@ -177,14 +189,17 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
     if (j.da < 0 || j.db < 0 || j.Na < 1 || j.Nb < 1) return ZPM_EINVAL;
     if (j.da == 0 || j.db == 0) continue;
     if (j.wc < (out_bits(j.da, j.Na, j.db, j.Nb) + 63) / 64) return ZPM_EINVAL;
+    const bool sp = specs && specs[i];
+    if (sp && !given) return ZPM_EINVAL;   // resident spectra come with their operand's plan
     if (given) {
       if (!batch_supports(given[i])) return ZPM_EUNSUPPORTED;
       pls[i] = given[i];
     } else if ((rc = get_plan_batch(j.da, j.Na, j.db, j.Nb, K_force, T_force, &pls[i])) != ZPM_OK) {
       return rc;
     }
-    // one operand passed twice is transformed once
-    pls[i].square = (j.a && j.a == j.b && j.da == j.db && j.Na == j.Nb) ? 1 : 0;
+    // one operand passed twice is transformed once; resident spectra are not transformed
+    pls[i].spec = sp ? 1 : 0;
+    pls[i].square = (!sp && j.a && j.a == j.b && j.da == j.db && j.Na == j.Nb) ? 1 : 0;
     live[i] = 1;
     const Plan &pl = pls[i];
     bh.npmax = std::max(bh.npmax, pl.np);
@@ -200,6 +215,7 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
     JobDev jd;
     std::memset(&jd, 0, sizeof(jd));
     jd.a = jobs[i].a; jd.b = jobs[i].b; jd.c = jobs[i].c;
+    jd.spec = pl.spec ? specs[i] : nullptr;
     jd.X = reinterpret_cast<uint32_t *>((uintptr_t)off);
     off += align_up(pl.ws_words, 64);
     jd.da = pl.da; jd.db = pl.db; jd.nout = pl.nout; jd.L = (int64_t)1 << pl.logL;
@@ -263,7 +279,8 @@ int Ctx::schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHo
 }
 
 int Ctx::build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState &bs,
-                     const Plan *given, uint32_t *ws_ext, int64_t ws_ext_words, int32_t T_force) {
+                     const Plan *given, uint32_t *ws_ext, int64_t ws_ext_words, int32_t T_force,
+                     const uint32_t *const *specs) {
   int rc;
   // the previous upload from the pinned buffers must be done before they are rewritten
   if (bs.upload_done) (void)hipEventSynchronize(bs.upload_done);
@@ -271,7 +288,7 @@ int Ctx::build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState
     if (jobs[i].da > 0 && jobs[i].db > 0 && (!jobs[i].a || !jobs[i].b || !jobs[i].c))
       return ZPM_EINVAL;
   BatchHost &bh = bs.host;
-  if ((rc = schedule_batch(jobs, n, K_force, bh, given, T_force)) != ZPM_OK) return rc;
+  if ((rc = schedule_batch(jobs, n, K_force, bh, given, T_force, specs)) != ZPM_OK) return rc;
   const int64_t nlive = (int64_t)bh.jobs.size();
   if ((rc = ensure_tables(bh.npmax, bh.H, bh.TP)) != ZPM_OK) return rc;
   uint32_t *base = ws_ext;
@@ -349,6 +366,8 @@ int Ctx::enqueue_persistent(BatchState &bs, hipStream_t st) {
     t += gr.blocks;
     lds = std::max(lds, gr.lds);
     if (gr.level >= PERSIST_LEVELS) return ZPM_EINVAL;
+    if ((gr.kind == SK_CONVERT || gr.kind == SK_RECOVER) && gr.variant > PERSIST_NP_MAX)
+      return ZPM_EUNSUPPORTED;
     for (int32_t k = 0; k < gr.nseg; ++k) {
       const GroupSeg &sg = bh.segs[gr.seg0 + k];
       bs.need_h[(int64_t)sg.job * PERSIST_LEVELS + gr.level] = (uint32_t)sg.ntiles;
@@ -381,14 +400,16 @@ int Ctx::enqueue_persistent(BatchState &bs, hipStream_t st) {
 }
 
 int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_force, hipStream_t st,
-                   int32_t T_force) {
+                   int32_t T_force, const Plan *given, const uint32_t *const *specs) {
   int rc;
   if (flags & ZPM_BATCH_PERSISTENT) {
+    for (int64_t i = 0; specs && i < n; ++i)
+      if (specs[i]) return ZPM_ENOTIMPL;   // the persistent kernel has no resident-spectra mode
     BatchState &bs = batch_eager;
     if (!bs.upload_done &&
         hipEventCreateWithFlags(&bs.upload_done, hipEventDisableTiming) != hipSuccess)
       return ZPM_EDEVICE;
-    if ((rc = build_batch(jobs, n, K_force, bs, nullptr, nullptr, 0, T_force)) != ZPM_OK) return rc;
+    if ((rc = build_batch(jobs, n, K_force, bs, given, nullptr, 0, T_force)) != ZPM_OK) return rc;
     rc = enqueue_persistent(bs, st);
     if (hipEventRecord(bs.upload_done, st) != hipSuccess && rc == ZPM_OK) rc = ZPM_EDEVICE;
     return rc;
@@ -401,7 +422,7 @@ int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_forc
     // every launch of the graph is followed by upload_done on the caller's stream: the
     // graph reads the pinned descriptors (its copy nodes), the device descriptors and
     // the workspace until then, so none of them is rewritten, freed or destroyed before
-    const uint64_t h = BatchState::hash(jobs, n, K_force, T_force);
+    const uint64_t h = BatchState::hash(jobs, n, K_force, T_force, specs, given);
     if (bs.exec && bs.key == h) {
       prof.begin(KK_BATCH, st);
       const hipError_t e = hipGraphLaunch(bs.exec, st);
@@ -414,7 +435,8 @@ int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_forc
       (void)hipGraphExecDestroy(bs.exec);
       bs.exec = nullptr;
     }
-    if ((rc = build_batch(jobs, n, K_force, bs, nullptr, nullptr, 0, T_force)) != ZPM_OK) return rc;
+    if ((rc = build_batch(jobs, n, K_force, bs, given, nullptr, 0, T_force, specs)) != ZPM_OK)
+      return rc;
     if (bs.host.groups.empty()) return ZPM_OK;
     // capture on a stream of our own (the caller's may be the legacy default stream,
     // which cannot be captured); the graph is then launched on the caller's stream
@@ -446,7 +468,7 @@ int Ctx::mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_forc
     if (e != hipSuccess || hipEventRecord(bs.upload_done, st) != hipSuccess) return ZPM_EDEVICE;
     return ZPM_OK;
   }
-  if ((rc = build_batch(jobs, n, K_force, bs, nullptr, nullptr, 0, T_force)) != ZPM_OK) return rc;
+  if ((rc = build_batch(jobs, n, K_force, bs, given, nullptr, 0, T_force, specs)) != ZPM_OK) return rc;
   rc = enqueue_batch(bs, st);
   // recorded even after a failed enqueue: what was enqueued may still read the buffers
   if (hipEventRecord(bs.upload_done, st) != hipSuccess && rc == ZPM_OK) rc = ZPM_EDEVICE;

@@ -229,6 +229,40 @@ Ctx::~Ctx() {
 
 }  // namespace zpm
 
+namespace zpm {
+
+Plan operand_plan(const zpm_operand &op, int64_t da, int32_t Na) {
+  Plan pl = op.pl;
+  pl.da = da;
+  pl.Na = Na;
+  pl.nout = da + op.db - 1;
+  pl.nout_bits = out_bits(da, Na, op.db, op.Nb);
+  pl.square = 0;
+  pl.spec = 1;
+  return pl;
+}
+
+int operand_product(Ctx &cx, const zpm_operand &op, const Plan &pl, const uint64_t *a, uint64_t *c,
+                    int32_t wc, uint32_t *ws, hipStream_t st) {
+  int rc;
+  PlanDev *pd = nullptr;
+  if ((rc = cx.plan_consts(pl, &pd, st)) != ZPM_OK) return rc;
+  DevState ds;
+  ds.X = ws;
+  ds.primes = cx.primes;
+  ds.plan = pd;
+  // a's limbs into rows 0..K-1 and their forward column passes; the row kernel takes
+  // b's spectra as they are
+  bool ok = launch_convert_in(pl, ds, a, pl.da, pl.Na, 0, st) == hipSuccess;
+  for (int k = 0; ok && k < pl.ncol; ++k) ok = launch_col(pl, ds, k, false, st, pl.K, 0) == hipSuccess;
+  ok = ok && launch_convolve(pl, ds, st, CM_WITH_SPECTRUM, op.spec) == hipSuccess;
+  for (int k = pl.ncol - 1; ok && k >= 0; --k) ok = launch_col(pl, ds, k, true, st) == hipSuccess;
+  ok = ok && launch_recover(pl, ds, c, wc, st) == hipSuccess;
+  return ok ? ZPM_OK : ZPM_EDEVICE;
+}
+
+}  // namespace zpm
+
 extern "C" {
 
 int zpm_version(void) { return 100; }
@@ -542,17 +576,6 @@ int zpm_mul_p64(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const u
   return mul_p64(*cx, pl, a, b, c, wc, st);
 }
 
-// A resident operand: b's spectra under a plan sized for products with any a of at
-// most da_max coefficients and Na_max bits.
-struct zpm_operand {
-  Ctx *cx;
-  Plan pl;             // plan for (da_max, Na_max, db, Nb)
-  uint32_t *spec;      // np * 2K * L words: b's forward transforms
-  const uint64_t *b;   // the operand's words, for the overlap check only
-  int64_t db, da_max;
-  int32_t Nb, Na_max;
-};
-
 int zpm_operand_create(zpm_ctx *ctx, const uint64_t *b, int64_t db, int32_t Nb, int64_t da_max,
                        int32_t Na_max, int32_t K, zpm_operand **out, void *stream) {
   if (!ctx || !b || !out || db < 1 || Nb < 1 || da_max < 1 || Na_max < 1 || K < 0)
@@ -613,25 +636,41 @@ int zpm_mul_operand(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, con
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if ((rc = cx->check_range(a, da, Na, st)) != ZPM_OK) return rc;
   // the operand's plan, for this a: K, M, np and L are fixed by the bounds
-  Plan pl = op->pl;
-  pl.da = da;
-  pl.Na = Na;
-  pl.nout = da + op->db - 1;
-  pl.nout_bits = out_bits(da, Na, op->db, op->Nb);
-  pl.square = 0;
-  PlanDev *pd = nullptr;
-  if ((rc = cx->plan_consts(pl, &pd, st)) != ZPM_OK) return rc;
+  const Plan pl = operand_plan(*op, da, Na);
   if ((rc = cx->ensure_ws(pl.ws_words)) != ZPM_OK) return rc;
-  DevState ds;
-  ds.X = cx->ws;
-  ds.primes = cx->primes;
-  ds.plan = pd;
-  bool ok = launch_convert_in(pl, ds, a, da, Na, 0, st) == hipSuccess;
-  for (int k = 0; ok && k < pl.ncol; ++k) ok = launch_col(pl, ds, k, false, st, pl.K, 0) == hipSuccess;
-  ok = ok && launch_convolve(pl, ds, st, CM_WITH_SPECTRUM, op->spec) == hipSuccess;
-  for (int k = pl.ncol - 1; ok && k >= 0; --k) ok = launch_col(pl, ds, k, true, st) == hipSuccess;
-  ok = ok && launch_recover(pl, ds, c, wc, st) == hipSuccess;
-  return ok ? ZPM_OK : ZPM_EDEVICE;
+  return operand_product(*cx, *op, pl, a, c, wc, cx->ws, st);
+}
+
+int zpm_mul_operand_batch(zpm_ctx *ctx, const zpm_operand_job *jobs, int64_t n, int32_t flags,
+                          void *stream) {
+  if (!ctx || n < 0 || (n > 0 && !jobs)) return ZPM_EINVAL;
+  if (flags != 0 && flags != ZPM_BATCH_GRAPH && flags != ZPM_BATCH_PERSISTENT) return ZPM_EINVAL;
+  Ctx *cx = reinterpret_cast<Ctx *>(ctx);
+  std::vector<zpm_job> js((size_t)n);
+  std::vector<Plan> pls((size_t)n);
+  std::vector<const uint32_t *> specs((size_t)n, nullptr);
+  for (int64_t i = 0; i < n; ++i) {
+    const zpm_operand_job &o = jobs[i];
+    if (!o.op || o.op->cx != cx || o.da > o.op->da_max || o.Na > o.op->Na_max) return ZPM_EINVAL;
+    int rc = check_mul_args(o.a, o.da, o.Na, o.op->b, o.op->db, o.op->Nb, o.c, o.wc);
+    if (rc != ZPM_OK) return rc;
+    zpm_job &j = js[(size_t)i];
+    j.a = o.a; j.da = o.da; j.Na = o.Na;
+    j.b = o.op->b; j.db = o.op->db; j.Nb = o.op->Nb;
+    j.c = o.c; j.wc = o.wc;
+    if (o.da == 0) continue;
+    pls[(size_t)i] = operand_plan(*o.op, o.da, o.Na);
+    specs[(size_t)i] = o.op->spec;
+  }
+  std::lock_guard<std::mutex> lock(cx->mu);
+  if (hipSetDevice(cx->device) != hipSuccess) return ZPM_EDEVICE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (int64_t i = 0; cx->check_inputs && i < n; ++i) {
+    if (js[(size_t)i].da <= 0) continue;
+    const int rc = cx->check_range(js[(size_t)i].a, js[(size_t)i].da, js[(size_t)i].Na, st);
+    if (rc != ZPM_OK) return rc;
+  }
+  return cx->mul_batch(js.data(), n, flags, 0, st, 0, pls.data(), specs.data());
 }
 
 int zpm_operand_info(const zpm_operand *op, zpm_plan_info *out) {

@@ -47,7 +47,8 @@ struct BatchState {
   int64_t need_hcap = 0, need_dcap = 0, done_dcap = 0;
   PersistCtl *ctl_h = nullptr, *ctl_d = nullptr;
   uint64_t key = 0;
-  static uint64_t hash(const zpm_job *jobs, int64_t n, int32_t K_force, int32_t T_force);
+  static uint64_t hash(const zpm_job *jobs, int64_t n, int32_t K_force, int32_t T_force,
+                       const uint32_t *const *specs = nullptr, const Plan *given = nullptr);
   void release();
 };
 
@@ -123,13 +124,15 @@ struct Ctx {
   int prepare(const Plan &pl, DevState *ds, hipStream_t st = nullptr);
   int get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force,
                      int32_t T_force, Plan *out);
-  // given: plans per job (from plan_for_batch) instead of the context's choice
+  // given: plans per job (from plan_for_batch) instead of the context's choice; specs:
+  // per job, b's resident spectra (an operand's, whose plan given[] then holds) or null
   int schedule_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchHost &bh,
-                     const Plan *given = nullptr, int32_t T_force = 0);
+                     const Plan *given = nullptr, int32_t T_force = 0,
+                     const uint32_t *const *specs = nullptr);
   // ws_ext: workspace of ws_ext_words words to use instead of the state's own buffer
   int build_batch(const zpm_job *jobs, int64_t n, int32_t K_force, BatchState &bs,
                   const Plan *given = nullptr, uint32_t *ws_ext = nullptr, int64_t ws_ext_words = 0,
-                  int32_t T_force = 0);
+                  int32_t T_force = 0, const uint32_t *const *specs = nullptr);
   // sizes the descriptor buffers of bs for batches of up to `jobs` products and `segs`
   // segments, so that later batches within those bounds allocate nothing
   int reserve_batch(BatchState &bs, int64_t jobs, int64_t segs);
@@ -139,9 +142,33 @@ struct Ctx {
   int enqueue_persistent(BatchState &bs, hipStream_t st);
   int ncu = 0;                                 // compute units of the device (persistent grid)
   int mul_batch(const zpm_job *jobs, int64_t n, int32_t flags, int32_t K_force, hipStream_t st,
-                int32_t T_force = 0);
+                int32_t T_force = 0, const Plan *given = nullptr,
+                const uint32_t *const *specs = nullptr);
   int tune(const zpm_job *sample, int64_t n, hipStream_t st);
   ~Ctx();
 };
+
+}  // namespace zpm
+
+// A resident operand: b's spectra under a plan sized for products with any a of at
+// most da_max coefficients and Na_max bits.
+struct zpm_operand {
+  zpm::Ctx *cx;
+  zpm::Plan pl;        // plan for (da_max, Na_max, db, Nb)
+  uint32_t *spec;      // np * 2K * L words: b's forward transforms
+  const uint64_t *b;   // the operand's words, for the overlap check only
+  int64_t db, da_max;
+  int32_t Nb, Na_max;
+};
+
+namespace zpm {
+
+// The operand's plan for a product with an a of da coefficients and Na bits: K, M, np
+// and L are the operand's.
+Plan operand_plan(const zpm_operand &op, int64_t da, int32_t Na);
+// c = a * (the operand's b) under pl (from operand_plan) with workspace ws of pl.ws_words
+// words, on st; the caller holds cx.mu.
+int operand_product(Ctx &cx, const zpm_operand &op, const Plan &pl, const uint64_t *a, uint64_t *c,
+                    int32_t wc, uint32_t *ws, hipStream_t st);
 
 }  // namespace zpm

@@ -16,7 +16,9 @@
 // in throughput.  While the device is busy, a small batch of fewer than min_batch
 // requests is held until its oldest request has waited linger_s, so that arrivals
 // coalesce into fewer, larger batches.  Twiddle tables and plan constants stay resident
-// in the context.
+// in the context, and requests against a resident operand (zpm_operand) take its
+// spectra as they are: only their a is converted and transformed, in a batch beside
+// ordinary requests or alone.
 //
 // The executor is an interface so that the admission and batching policy can also run
 // against a simulated device (no computation, a modelled duration per batch).
@@ -35,6 +37,7 @@
 #include <vector>
 
 #include "../../include/zpm.h"
+#include "batch.hpp"
 #include "ctx.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -56,6 +59,7 @@ static double seconds(Clock::duration d) { return std::chrono::duration<double>(
 struct SReq {
   uint64_t ticket = 0;
   zpm_job job;
+  const zpm_operand *op = nullptr;   // resident b (job.b is then the operand's words)
   Plan plan;
   bool batch = true;       // planned for the batch kernels
   bool large = false;
@@ -158,20 +162,27 @@ class GpuExec final : public Exec {
     if (f.batch) {
       jobs_.clear();
       plans_.clear();
+      specs_.clear();
       for (const SReq &r : f.reqs) {
         jobs_.push_back(r.job);
         plans_.push_back(r.plan);
+        specs_.push_back(r.op ? r.op->spec : nullptr);
       }
       const bool was_on = cx_->prof.on;
       cx_->prof.on = false;
       rc = cx_->build_batch(jobs_.data(), (int64_t)jobs_.size(), 0, bs_[slot], plans_.data(), ws,
-                            f.bytes / 4);
+                            f.bytes / 4, 0, specs_.data());
       if (rc == ZPM_OK) rc = cx_->enqueue_batch(bs_[slot], st);
       cx_->prof.on = was_on;
       if (rc != ZPM_OK) return rc;
     } else {
       const SReq &r = f.reqs[0];
       const Plan &pl = r.plan;
+      if (r.op) {   // the operand's tables were built when it was created
+        rc = operand_product(*cx_, *r.op, pl, r.job.a, r.job.c, r.job.wc, ws, st);
+        if (rc != ZPM_OK) return rc;
+        return hipEventRecord(ev_[slot], st) == hipSuccess ? ZPM_OK : ZPM_EDEVICE;
+      }
       const int64_t H = std::max<int64_t>((int64_t)1 << pl.logL, 2 * (int64_t)pl.K);
       if ((rc = cx_->ensure_tables(pl.np, H, (pl.M + 31) / 32 + 1)) != ZPM_OK) return rc;
       PlanDev *pd = nullptr;
@@ -215,6 +226,7 @@ class GpuExec final : public Exec {
   std::vector<BatchState> bs_;
   std::vector<zpm_job> jobs_;
   std::vector<Plan> plans_;
+  std::vector<const uint32_t *> specs_;
 };
 
 // Simulated device: a batch takes overhead_s + (its output bits) / bits_per_s seconds
@@ -297,6 +309,14 @@ int Server::plan_req(SReq &r) {
   const zpm_job &j = r.job;
   r.bits = (double)(j.da + j.db - 1) * (double)out_bits(j.da, j.Na, j.db, j.Nb);
   r.large = r.bits >= cfg.large_bits;
+  if (r.op) {
+    // the operand fixes K, M, np and L; small requests join batches when the batch
+    // kernels cover that plan
+    r.plan = operand_plan(*r.op, j.da, j.Na);
+    r.batch = !cfg.single_product && !r.large && batch_supports(r.plan);
+    r.bytes = align_up(r.plan.ws_words, 64) * 4;
+    return ZPM_OK;
+  }
   const auto key = std::make_tuple(j.da, j.Na, j.db, j.Nb);
   {
     std::lock_guard<std::mutex> lock(pm);
@@ -590,14 +610,13 @@ extern "C" int zpm_server_create_simulated(const zpm_server_config *cfg, double 
   return ZPM_OK;
 }
 
-extern "C" int zpm_server_submit(zpm_server *srv, const zpm_job *job, uint64_t *ticket) {
-  if (!srv || !job || !ticket) return ZPM_EINVAL;
-  Server *sv = reinterpret_cast<Server *>(srv);
-  int rc = zpm::check_job(*job);
-  if (rc != ZPM_OK) return rc;
-  zpm::SReq r;
-  r.job = *job;
-  r.t0 = zpm::Clock::now();
+namespace zpm {
+
+// Plans and queues r (its job checked); the ticket goes to *ticket.
+static int submit(Server *sv, SReq &r, uint64_t *ticket) {
+  int rc;
+  const zpm_job *job = &r.job;
+  r.t0 = Clock::now();
   const bool empty = job->da == 0 || job->db == 0;
   if (!empty) {
     if ((rc = sv->plan_req(r)) != ZPM_OK) return rc;
@@ -629,6 +648,46 @@ extern "C" int zpm_server_submit(zpm_server *srv, const zpm_job *job, uint64_t *
   sv->lane[r.large ? 1 : 0].push_back(std::move(r));
   sv->cv_work.notify_one();
   return ZPM_OK;
+}
+
+}  // namespace zpm
+
+extern "C" int zpm_server_submit(zpm_server *srv, const zpm_job *job, uint64_t *ticket) {
+  if (!srv || !job || !ticket) return ZPM_EINVAL;
+  Server *sv = reinterpret_cast<Server *>(srv);
+  int rc = zpm::check_job(*job);
+  if (rc != ZPM_OK) return rc;
+  zpm::SReq r;
+  r.job = *job;
+  return zpm::submit(sv, r, ticket);
+}
+
+extern "C" int zpm_server_submit_operand(zpm_server *srv, const zpm_operand_job *job,
+                                         uint64_t *ticket) {
+  if (!srv || !job || !ticket || !job->op) return ZPM_EINVAL;
+  Server *sv = reinterpret_cast<Server *>(srv);
+  const zpm_operand *op = job->op;
+  if (!sv->cx || op->cx != sv->cx || job->da > op->da_max || job->Na > op->Na_max)
+    return ZPM_EINVAL;
+  zpm::SReq r;
+  r.job.a = job->a;
+  r.job.da = job->da;
+  r.job.Na = job->Na;
+  r.job.b = op->b;
+  r.job.db = op->db;
+  r.job.Nb = op->Nb;
+  r.job.c = job->c;
+  r.job.wc = job->wc;
+  r.op = op;
+  int rc = zpm::check_job(r.job);
+  if (rc != ZPM_OK) return rc;
+  if (job->da > 0) {   // c may overlap neither a nor the operand's words
+    const uint64_t *c_end = job->c + (size_t)(job->da + op->db - 1) * job->wc;
+    const uint64_t *a_end = job->a + (size_t)job->da * ((job->Na + 63) / 64);
+    const uint64_t *b_end = op->b + (size_t)op->db * ((op->Nb + 63) / 64);
+    if ((job->c < a_end && job->a < c_end) || (job->c < b_end && op->b < c_end)) return ZPM_EINVAL;
+  }
+  return zpm::submit(sv, r, ticket);
 }
 
 extern "C" int zpm_server_poll(zpm_server *srv, uint64_t ticket, int32_t *status, double *latency_s) {

@@ -133,6 +133,8 @@ struct Plan {
   int32_t logL1;       // innermost y factor handled inside the fused convolution kernel
   int32_t conv_reg;    // 1: x-transforms in registers (K <= 32), 0: in LDS
   int32_t square;      // 1: a and b are one operand, transformed once (c = a^2)
+  int32_t spec;        // 1: b's spectra are resident (an operand's); only a is converted
+                       //    and transformed, the row kernel takes b's spectra as they are
   int32_t ncol;        // number of strided column passes (outermost first)
   ColPass col[MAX_COL_PASSES];
   int32_t col_tile[MAX_COL_PASSES];  // inner indices per workgroup of each column pass

@@ -48,6 +48,8 @@ def test_error_codes_and_host_argument_checks(nat):
     assert nat.zpm_set_option(None, nat.ZPM_OPT_CHECK_INPUTS, 1) == nat.ZPM_EINVAL
     assert nat.zpm_mul(None, None, 1, 64, None, 1, 64, None, 3, None) == nat.ZPM_EINVAL
     assert nat.zpm_mul_batch_ex(None, None, 0, 0, 0, None) == nat.ZPM_EINVAL
+    assert nat.zpm_mul_operand_batch(None, None, 0, 0, None) == nat.ZPM_EINVAL
+    assert nat.zpm_server_submit_operand(None, None, None) == nat.ZPM_EINVAL
 
 
 def test_prime_table(nat):

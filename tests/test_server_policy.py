@@ -163,6 +163,13 @@ def test_bad_and_empty_jobs():
     with pytest.raises(nat.ZpmError) as e:
         s.poll(123456789)
     assert e.value.code == nat.ZPM_ENOTFOUND
+    # a request against a resident operand needs one (a simulated server has no
+    # context, so no operand can belong to it)
+    oj = nat.OperandJob()
+    oj.a, oj.da, oj.Na, oj.op, oj.c, oj.wc = FAKE, 10, 100, None, FAKE, 4
+    tk = nat.c_u64()
+    assert nat.zpm_server_submit_operand(s._h, ctypes.byref(oj), ctypes.byref(tk)) == nat.ZPM_EINVAL
+    assert nat.zpm_server_submit_operand(s._h, None, ctypes.byref(tk)) == nat.ZPM_EINVAL
     s.close()
 
 
