@@ -254,6 +254,34 @@ def operand_batch_leg(ctx, reps: int, n: int = 1024, d: int = 512, mag: int = 10
             nat.check(nat.zpm_mul_operand(ctx.handle, ojobs[i].a, d, N, op._h, ojobs[i].c, wc, h),
                       "zpm_mul_operand")
 
+    def served(use_operand):
+        # all n requests submitted at once to a server (4 streams), until the last ends
+        from paper_1612_05778_amd.api import Server
+        srv = Server(ctx, hbm_budget=4 << 30, n_streams=4)
+        tk = nat.c_u64()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = []
+        for i in range(n):
+            if use_operand:
+                nat.check(nat.zpm_server_submit_operand(srv._h, ctypes.byref(ojobs[i]), ctypes.byref(tk)),
+                          "zpm_server_submit_operand")
+            else:
+                nat.check(nat.zpm_server_submit(srv._h, ctypes.byref(jobs[i]), ctypes.byref(tk)),
+                          "zpm_server_submit")
+            tickets.append(tk.value)
+        t_sub = time.perf_counter() - t0
+        stt, lat = nat.c_i32(), ctypes.c_double()
+        for t in tickets:
+            nat.check(nat.zpm_server_wait(srv._h, t, 60.0, ctypes.byref(stt), ctypes.byref(lat)),
+                      "zpm_server_wait")
+            if stt.value != 0:
+                raise RuntimeError(f"served request ended with {stt.value}")
+        dt = time.perf_counter() - t0
+        mean_batch = srv.stats()["mean_batch"]
+        srv.close()
+        return dt * 1e3, mean_batch, t_sub * 1e3
+
     batch_ms = timed(plain_batch, reps)
     ref = C.clone()
     C.zero_()
@@ -262,6 +290,11 @@ def operand_batch_leg(ctx, reps: int, n: int = 1024, d: int = 512, mag: int = 10
     C.zero_()
     op_ms = timed(operand_batch, reps)
     same = bool(torch.equal(C, ref))
+    served(True)                                   # first use of the server's plans
+    C.zero_()
+    srv_op_ms, srv_op_batch, srv_op_sub = served(True)
+    same_served = bool(torch.equal(C, ref))
+    srv_ms, srv_batch, srv_sub = served(False)
     info = op.info()
     op.close()
     return {"workload": f"operand{d}x{N}_batch{n}", "products": n, "out_bits": bits,
@@ -269,7 +302,13 @@ def operand_batch_leg(ctx, reps: int, n: int = 1024, d: int = 512, mag: int = 10
             "plan": {"K": info["K"], "np": info["np"], "log2_L": info["log2_L"]},
             "batch_ms": batch_ms, "vs_batch": batch_ms / op_ms,
             "single_ms": single_ms, "vs_single": single_ms / op_ms,
-            "identical_to_batch": same, "single_identical_to_batch": same_single}
+            "identical_to_batch": same, "single_identical_to_batch": same_single,
+            # wall-clock from the first submission to the last completion; the Python
+            # submission loop alone takes submit_ms of it
+            "served_operand_ms": srv_op_ms, "served_operand_submit_ms": srv_op_sub,
+            "served_operand_mean_batch": srv_op_batch, "served_identical_to_batch": same_served,
+            "served_plain_ms": srv_ms, "served_plain_submit_ms": srv_sub,
+            "served_plain_mean_batch": srv_batch}
 
 
 def t_star_of(da: int, Na: int, db: int, Nb: int) -> float:
