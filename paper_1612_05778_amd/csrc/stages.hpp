@@ -63,6 +63,10 @@ __device__ __forceinline__ uint32_t mul_shoup_lz(uint32_t x, uint2 w, uint32_t p
   const uint32_t q = __umulhi(x, w.y);
   return x * w.x + q * (0u - p);
 }
+// mul_shoup_lz with -p mod 2^32 given instead of p.
+__device__ __forceinline__ uint32_t shoup_neg_lz(uint32_t x, uint2 w, uint32_t negp) {
+  return x * w.x + __umulhi(x, w.y) * negp;
+}
 // a b 2^-32 mod p up to one p, in [0, 2p), for a, b < 2p: a b < 4p^2 < p 2^32, so
 // hi - mp lies in (-p, p).
 __device__ __forceinline__ uint32_t mont_mul_lz(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
@@ -962,10 +966,13 @@ __device__ __forceinline__ int fcompose(int g, int f) {   // g after f
 typedef int crt_i32x4 __attribute__((ext_vector_type(4)));
 
 // The CRT of each c_{i,j} on the int8 matrix cores, added at bit M j into S (np <=
-// CRT_MFMA_NP).  c_{i,j} = sum_k y_k (P/p_k) - t P with y_k = r_k (P/p_k)^{-1} mod p_k
-// centred in (-p_k/2, p_k/2) and t = round(sum_k y_k / p_k).  (|c_{i,j}| < P/2 (1 - 2^-12)
-// leaves the rounding of t a margin of 2^-13, far above the error of the single-precision
-// sum, below 2^-16 for 20 terms.)  Per wave, rounds of 16 values: value v = lane mod 16,
+// CRT_MFMA_NP).  c_{i,j} = sum_k y_k (P/p_k) - t P with y_k = u_k - p_k, u_k the lazy
+// Shoup product r_k (P/p_k)^{-1} mod p_k in [0, 2 p_k) (so y_k in [-p_k, p_k)), and
+// t = round(sum_k y_k / p_k), summed in single precision as round(sum_k u_k / p_k) - np.
+// (|c_{i,j}| < P/2 (1 - 2^-12) leaves the rounding of t a margin of 2^-13; the sum's error
+// is below 2^-15 for 20 terms below 2: each term's conversion and reciprocal add 2^-23,
+// each fused multiply-add rounds its partial sum, below 2 k, to 2^-24.)
+// Per wave, rounds of 16 values: value v = lane mod 16,
 // and lane group g = lane / 16 holds the terms crt_term(s, g, w) of step s (w < 4): it
 // loads and reduces those residues, the four groups add their shares of the quotient sum,
 // and the terms' balanced signed bytes form the B operand in registers.  D = A Y with A
@@ -977,7 +984,7 @@ typedef int crt_i32x4 __attribute__((ext_vector_type(4)));
 // to row 0.  With short rows (recover_staged) the terms are formed one value per lane
 // and passed to the lane groups through LDS instead.  Each round's residues are loaded two rounds ahead; the first two rounds',
 // and the A fragments, before the workgroup's set-up (constants to LDS, S cleared,
-// barrier).  cw: per prime (c_k, its Shoup companion, p_k, 1/p_k as float bits).
+// barrier).  cw: per prime (c_k, its Shoup companion, -p_k mod 2^32, 1/p_k as float bits).
 template <int NP>
 struct CrtMatrix {
   static constexpr int NT = NP + 1;
@@ -1111,12 +1118,12 @@ struct CrtMatrix {
         for (int k = 0; k < NP; ++k) {
           if (k % CH == 0) asm volatile("" ::: "memory");   // bounds the constants in flight
           const uint4 c = cw[k];
-          const uint32_t u = mul_shoup(y[k], make_uint2(c.x, c.y), c.z);
-          const int32_t yc = u > (c.z >> 1) ? (int32_t)(u - c.z) : (int32_t)u;
-          f = fmaf((float)yc, __uint_as_float(c.w), f);
-          y[k] = ((uint32_t)yc + 0x80808080u) ^ 0x80808080u;
+          const uint32_t u = shoup_neg_lz(y[k], make_uint2(c.x, c.y), c.z);   // [0, 2p)
+          f = fmaf((float)u, __uint_as_float(c.w), f);
+          // |u - p| < 2^30: the bytes of u - p + 0x80808080 are its balanced digits plus 128
+          y[k] = (u + c.z + 0x80808080u) ^ 0x80808080u;
         }
-        y[NP] = (uint32_t)__float2int_rn(f) & 0xFFu;
+        y[NP] = (uint32_t)(__float2int_rn(f) - NP) & 0xFFu;
 #pragma unroll
         for (int k = NP + 1; k < YW; ++k) y[k] = 0;
 #pragma unroll
@@ -1189,17 +1196,17 @@ struct CrtMatrix {
             bw[st][w] = 0u;
             if (q < NP) {
               const uint4 c = cw[q];
-              const uint32_t u = mul_shoup(res[st][w], make_uint2(c.x, c.y), c.z);
-              const int32_t yc = u > (c.z >> 1) ? (int32_t)(u - c.z) : (int32_t)u;
-              f = fmaf((float)yc, __uint_as_float(c.w), f);
-              // |yc| < 2^29: the bytes of yc + 0x80808080 are its balanced digits plus 128
-              bw[st][w] = ((uint32_t)yc + 0x80808080u) ^ 0x80808080u;
+              const uint32_t u = shoup_neg_lz(res[st][w], make_uint2(c.x, c.y), c.z);
+              f = fmaf((float)u, __uint_as_float(c.w), f);
+              // |u - p| < 2^30: the bytes of u - p + 0x80808080 are its balanced digits
+              // plus 128
+              bw[st][w] = (u + c.z + 0x80808080u) ^ 0x80808080u;
             }
           }
         // the four groups' shares (every lane adds them in the same pairs, so all agree)
         f += __shfl_xor(f, 16, 64);
         f += __shfl_xor(f, 32, 64);
-        const uint32_t tb = (uint32_t)__float2int_rn(f) & 0xFFu;
+        const uint32_t tb = (uint32_t)(__float2int_rn(f) - NP) & 0xFFu;
 #pragma unroll
         for (int st = 0; st < NS; ++st)
 #pragma unroll
@@ -1230,7 +1237,7 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
   if (i0 >= nout) return;
   const int ti = (int)min<int64_t>(TI, nout - i0);
   // S: TI rows of RS partial sums (nw32 output words and, in the matrix form, room for
-  // every word the CRT's lane groups touch), then either per prime (c_k Shoup pair, p_k,
+  // every word the CRT's lane groups touch), then either per prime (c_k Shoup pair, -p_k,
   // 1/p_k in single precision) (matrix form), or, as [u][k]
   // (W x NPE words), P/p_k for k < np and, at k = np, 2^(32 W) - P (P is odd, so its
   // negation is ~P + 1 = -P[0], ~P[1], ...), then per prime (c_k Shoup pair, p_k) and 1/p_k
@@ -1246,7 +1253,7 @@ __device__ void body_recover(uint64_t *S, int64_t tile_id, const uint32_t *__res
   if constexpr (MF) {
     uint4 *cw = reinterpret_cast<uint4 *>(ci);
     for (int idx = threadIdx.x; idx < NP; idx += BLOCK)
-      cw[idx] = make_uint4(pd->crt_inv[idx].x, pd->crt_inv[idx].y, primes[idx].p,
+      cw[idx] = make_uint4(pd->crt_inv[idx].x, pd->crt_inv[idx].y, 0u - primes[idx].p,
                            __float_as_uint((float)pd->crt_rcp[idx]));
   } else {
     for (int idx = threadIdx.x; idx < NPE * W; idx += BLOCK) {

@@ -1,8 +1,10 @@
 """Host pins of the recovery's Chinese remaindering in matrix form (no GPU needed).
 
 For np <= 20 primes the recovery computes c_{i,j} = sum_k y_k (P/p_k) - t P (Section 4,
-the Chinese remaindering of each c_{i,j}: y_k = r_k (P/p_k)^{-1} mod p_k centred,
-t = round(sum_k y_k / p_k)) as int8 products on the matrix cores: the terms' balanced
+the Chinese remaindering of each c_{i,j}: y_k = u_k - p_k with u_k = r_k (P/p_k)^{-1} mod
+p_k as the lazy product leaves it, in [0, 2 p_k), and t = round(sum_k y_k / p_k), summed in
+single precision as round(sum_k u_k / p_k) - np) as int8 products on the matrix cores: the
+terms' balanced
 bytes times a digit matrix A the host builds (``zpm_crt_matrix``).  This test models that
 computation on the CPU with the library's A, in the kernel's lane order:
 
@@ -17,11 +19,13 @@ computation on the CPU with the library's A, in the kernel's lane order:
 
 The reconstruction must equal c exactly for random c with |c| < P / (2 (1 + 2^-12)) (the
 planner's bound) and at its extremes, for every np from 1 to 20, with P from the
-library's own prime table; a single-precision quotient sum rounds to the same t.  A's entries must be
+library's own prime table and u_k drawn from both halves of [0, 2 p_k); the single-precision
+quotient sum must round to the same t, with an error below 2^-15.  A's entries must be
 signed bytes and every digit sum must fit the int32 accumulator.
 """
 import ctypes
 import random
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -114,20 +118,21 @@ def test_matrix_crt_reconstructs(np_):
         cs = cs + [0] * (16 - len(cs))
         words = []
         for c in cs:
-            y = []
+            us = []
             for p in ps:
                 Bk = P // p
                 u = (c % p) * pow(Bk % p, -1, p) % p
-                y.append(u - p if u > p // 2 else u)
-            f = sum(yk / p for yk, p in zip(y, ps))
-            t = int(round(f))
-            assert abs(t) <= np_ // 2 + 1
-            # the kernel's single-precision sum rounds to the same t
+                us.append(u + p if rng.random() < 0.5 else u)   # the lazy product's range
+            y = [u - p for u, p in zip(us, ps)]
+            f = sum(Fraction(yk, p) for yk, p in zip(y, ps))
+            t = round(f)
+            assert abs(t) <= np_
+            # the kernel's single-precision sum of u_k / p_k, less np, rounds to the same t
             f32 = np.float32(0)
-            for yk, p in zip(y, ps):
-                f32 = np.float32(f32 + np.float32(yk) * np.float32(1.0 / p))
+            for u, p in zip(us, ps):
+                f32 = np.float32(f32 + np.float32(u) * np.float32(1.0 / p))
             # (its error stays far below the 2^-13 the bound leaves between c / P and 1/2)
-            assert int(np.rint(f32)) == t and abs(float(f32) - f) < 2.0**-16
+            assert int(np.rint(f32)) - np_ == t and abs(Fraction(float(f32)) - np_ - f) < Fraction(1, 2**15)
             words.append(stage(y, t, np_))
         D = mfma_model(A, words, TN)
         assert np.abs(D).max() < 2**31
