@@ -260,6 +260,17 @@ __device__ __forceinline__ void lds_dit_c(uint32_t *s, const uint2 *__restrict__
 __device__ __forceinline__ int bitrev(int x, int logn) {
   return logn ? (int)(__brev((unsigned)x) >> (32 - logn)) : 0;
 }
+__host__ __device__ constexpr int bitrev_c(int x, int logn) {
+  int r = 0;
+  for (int b = 0; b < logn; ++b) r |= ((x >> b) & 1) << (logn - 1 - b);
+  return r;
+}
+
+// A raw buffer resource over `bytes` bytes from p (gfx9 word 3: 32-bit data format):
+// loads past the end read zero, stores past it are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_col_rsrc(uint32_t *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000);
+}
 
 // Element-wise staging between global memory and LDS: for idx = threadIdx.x, +BLOCK, ...
 // below `total`, put(idx, load(idx)).  U loads are issued before their results are
@@ -452,6 +463,75 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
   const uint2 step = heap_root(tab, m, (inner * de) & (m - 1), p);
   // offsets inside the column stay below L <= 2^21: 32-bit index arithmetic
   const int lim_store = (int)std::min<int64_t>(std::max<int64_t>(nlimit - first, 0), L);
+  if constexpr (fixed) {
+    // Compile-time shape: every loop fully unrolled, so that the bit-reversed LDS indices
+    // are immediate offsets, and global memory reached through buffer instructions over
+    // the tile's column.  Element (t, e) of the tile is at byte (t + e S) 4 past `base`;
+    // this thread's rows are e0 + i de (i < NI), the staged loops' rows idx / T with
+    // idx = threadIdx + k BLOCK, i.e. the same rows.  Bounded accesses keep the whole
+    // offset in the per-lane part, which the hardware checks against the buffer's size
+    // (loads past it read zero, stores past it are dropped); the others put i's row step
+    // in the scalar offset.
+    constexpr int LDE = 8 - CLOGT;                  // log2(BLOCK / T)
+    constexpr int LI = CLOGN - LDE;
+    constexpr int NI = 1 << LI;                     // rows per thread (>= 8)
+    static_assert(LI >= 3 && (BLOCK >> CLOGT) << LI == (1 << CLOGN), "column pass shape");
+    const int voff0 = (t + (e0 << logS)) * 4;
+    const int vstep = (de << logS) * 4;
+    const uint32_t col_bytes = (uint32_t)(L - first) * 4u;
+    uint32_t *srow = s + ((bitrev(e0, LDE) << LI) << CLOGT) + t;   // bitrev(e0 + i de) = that | bitrev(i)
+    if (!inverse) {
+      // rows past nz (zero limbs) read as zero
+      const int64_t nzr = std::min<int64_t>(std::max<int64_t>(nz - first, 0), L - first);
+      const __amdgpu_buffer_rsrc_t rin = make_col_rsrc(base, (uint32_t)nzr * 4u);
+#pragma unroll
+      for (int k0 = 0; k0 < NI; k0 += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          v[u] = __builtin_amdgcn_raw_buffer_load_b32(rin, voff0 + (k0 + u) * vstep, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[threadIdx.x + (k0 + u) * BLOCK] = v[u];
+      }
+      __syncthreads();
+      lds_dif_c<CSH>(s, pr.hf, p);
+      const __amdgpu_buffer_rsrc_t rout = make_col_rsrc(base, col_bytes);
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        const uint32_t v = mont_mul_lz(srow[bitrev_c(i, LI) << CLOGT], cur, p, pr.pinv);
+        cur = mul_shoup_lz(cur, step, p);
+        __builtin_amdgcn_raw_buffer_store_b32(v, rout, voff0, i * vstep, 0);
+      }
+    } else {
+      const __amdgpu_buffer_rsrc_t rin = make_col_rsrc(base, col_bytes);
+#pragma unroll
+      for (int i0 = 0; i0 < NI; i0 += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          v[u] = __builtin_amdgcn_raw_buffer_load_b32(rin, voff0, (i0 + u) * vstep, 0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          srow[bitrev_c(i0 + u, LI) << CLOGT] = mont_mul_lz(v[u], cur, p, pr.pinv);
+          cur = mul_shoup_lz(cur, step, p);
+        }
+      }
+      __syncthreads();
+      lds_dit_c<CSH>(s, pr.hi, p);
+      // rows with t + e S at or past lim_store are not stored
+      const __amdgpu_buffer_rsrc_t rst = make_col_rsrc(base, (uint32_t)lim_store * 4u);
+#pragma unroll
+      for (int k0 = 0; k0 < NI; k0 += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = s[threadIdx.x + (k0 + u) * BLOCK];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          __builtin_amdgcn_raw_buffer_store_b32(v[u], rst, voff0 + (k0 + u) * vstep, 0, 0);
+      }
+    }
+    return;
+  }
   // every global access of this thread is in its own column t (BLOCK is a multiple of
   // T), at row offsets e S (e S < L <= 2^21)
   uint32_t *bt = base + t;
