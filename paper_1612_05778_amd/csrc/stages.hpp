@@ -475,6 +475,7 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     constexpr int LDE = 8 - CLOGT;                  // log2(BLOCK / T)
     constexpr int LI = CLOGN - LDE;
     constexpr int NI = 1 << LI;                     // rows per thread (>= 8)
+    constexpr int LG = NI < 32 ? NI : 32;           // loads in flight per thread
     static_assert(LI >= 3 && (BLOCK >> CLOGT) << LI == (1 << CLOGN), "column pass shape");
     const int voff0 = (t + (e0 << logS)) * 4;
     const int vstep = (de << logS) * 4;
@@ -485,13 +486,13 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
       const int64_t nzr = std::min<int64_t>(std::max<int64_t>(nz - first, 0), L - first);
       const __amdgpu_buffer_rsrc_t rin = make_col_rsrc(base, (uint32_t)nzr * 4u);
 #pragma unroll
-      for (int k0 = 0; k0 < NI; k0 += 8) {
-        uint32_t v[8];
+      for (int k0 = 0; k0 < NI; k0 += LG) {
+        uint32_t v[LG];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < LG; ++u)
           v[u] = __builtin_amdgcn_raw_buffer_load_b32(rin, voff0 + (k0 + u) * vstep, 0, 0);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s[threadIdx.x + (k0 + u) * BLOCK] = v[u];
+        for (int u = 0; u < LG; ++u) s[threadIdx.x + (k0 + u) * BLOCK] = v[u];
       }
       __syncthreads();
       lds_dif_c<CSH>(s, pr.hf, p);
@@ -505,13 +506,13 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     } else {
       const __amdgpu_buffer_rsrc_t rin = make_col_rsrc(base, col_bytes);
 #pragma unroll
-      for (int i0 = 0; i0 < NI; i0 += 8) {
-        uint32_t v[8];
+      for (int i0 = 0; i0 < NI; i0 += LG) {
+        uint32_t v[LG];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < LG; ++u)
           v[u] = __builtin_amdgcn_raw_buffer_load_b32(rin, voff0, (i0 + u) * vstep, 0);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < LG; ++u) {
           srow[bitrev_c(i0 + u, LI) << CLOGT] = mont_mul_lz(v[u], cur, p, pr.pinv);
           cur = mul_shoup_lz(cur, step, p);
         }
