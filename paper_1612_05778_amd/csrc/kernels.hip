@@ -18,6 +18,7 @@
 //   recovering_product       : CRT over the primes, evaluation at x = 2^M with carries
 //                              (Section 2.2, RecoveringProduct)
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "kernels.hpp"
 
@@ -33,6 +34,23 @@ namespace zpm {
 #endif
 
 static inline int64_t xcd_grid(int64_t ntiles) { return 8 * ((ntiles + 7) >> 3); }
+
+// Timing events for the next stage kernel this thread launches (set by launch_mul while
+// the profiler records that kind): hipExtLaunchKernelGGL records them in the kernel's own
+// dispatch, so timing a kernel adds no packets, and no gaps, between the kernels.
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+#define ZPM_LAUNCH(KERN_, GRID_, BLK_, LDS_, ST_, ...)                                        \
+  do {                                                                                     \
+    if (t_ev_start) {                                                                      \
+      hipExtLaunchKernelGGL(KERN_, GRID_, BLK_, (std::uint32_t)(LDS_), ST_, t_ev_start, t_ev_stop, \
+                            0u, __VA_ARGS__);                                              \
+      t_ev_start = t_ev_stop = nullptr;                                                    \
+    } else {                                                                               \
+      hipLaunchKernelGGL(KERN_, GRID_, BLK_, LDS_, ST_, __VA_ARGS__);                   \
+    }                                                                                      \
+  } while (0)
+// the same with its arguments expanded first (for argument lists held in a macro)
+#define ZPM_LAUNCH_X(...) ZPM_LAUNCH(__VA_ARGS__)
 
 template <int NP>
 __global__ __launch_bounds__(BLOCK) void k_bivariate_representation(
@@ -140,7 +158,7 @@ hipError_t launch_convert_in(const Plan &pl, const DevState &ds, const uint64_t 
                      sizeof(uint2) * (size_t)nchunks * pl.np;
 #define ZPM_CIN(NP_)                                                                          \
   case NP_:                                                                                   \
-    hipLaunchKernelGGL(k_bivariate_representation<NP_>, dim3((unsigned)blocks), dim3(BLOCK),  \
+    ZPM_LAUNCH(k_bivariate_representation<NP_>, dim3((unsigned)blocks), dim3(BLOCK),  \
                        lds, st, src, d, N, w, pl.K, pl.M, pl.np, ds.X, (int64_t)1 << pl.logL,  \
                        col_off, logTI, ds.primes, ds.plan);                                   \
     break;
@@ -175,12 +193,12 @@ hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, h
       pl.K, nlimit, inverse ? 1 : 0, ds.primes, blocks, cols, col0
   switch (fixed_col_index(logn, logT)) {
 #define ZPM_COL_FIXED(I, LN, LT)                                                             \
-  case I: hipLaunchKernelGGL((k_col_pass<LN, LT>), ZPM_COL_ARGS); break;
+  case I: ZPM_LAUNCH_X((k_col_pass<LN, LT>), ZPM_COL_ARGS); break;
     ZPM_COL_FIXED(1, 5, 6) ZPM_COL_FIXED(2, 6, 5) ZPM_COL_FIXED(3, 7, 4)
     ZPM_COL_FIXED(4, 8, 3) ZPM_COL_FIXED(5, 9, 3) ZPM_COL_FIXED(6, 10, 3)
     ZPM_COL_FIXED(7, 8, 4) ZPM_COL_FIXED(8, 9, 4) ZPM_COL_FIXED(9, 10, 4)
 #undef ZPM_COL_FIXED
-    default: hipLaunchKernelGGL((k_col_pass<-1, -1>), ZPM_COL_ARGS); break;
+    default: ZPM_LAUNCH_X((k_col_pass<-1, -1>), ZPM_COL_ARGS); break;
   }
 #undef ZPM_COL_ARGS
   return hipGetLastError();
@@ -199,7 +217,7 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
     // 2K (L1 + 1) <= LDS_WORDS, i.e. L1 = 2^(12 - log2 K)
     const bool full_l1 = fixed_reg_l1(ilog2(pl.K), pl.logL1);
 #define ZPM_CONV_LAUNCH(KERN, LK_, M_, C_)                                                     \
-  hipLaunchKernelGGL((KERN<LK_, M_, C_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, L, \
+  ZPM_LAUNCH((KERN<LK_, M_, C_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, ds.X, L, \
                      pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, spec)
 #define ZPM_CONV_M(LK_, M_)                                                                    \
   if constexpr (LK_ >= ZPM_SPLIT_LOGK) {                                                       \
@@ -233,7 +251,7 @@ hipError_t launch_convolve(const Plan &pl, const DevState &ds, hipStream_t st, i
   // compile time
   const int lk = ilog2(pl.K);
 #define ZPM_CONV_LDS(LK_, LL1_)                                                                \
-  hipLaunchKernelGGL((k_convolve_rows<LK_, LL1_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, \
+  ZPM_LAUNCH((k_convolve_rows<LK_, LL1_>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, \
                      ds.X, L, pl.K, lk, pl.logL1, nz_a, nz_b, nl, ds.primes, ds.plan, mode, spec)
   if (!fixed_lds_kl1(lk, pl.logL1)) ZPM_CONV_LDS(-1, -1);
   else if (lk == 6) ZPM_CONV_LDS(6, 5);
@@ -256,11 +274,11 @@ hipError_t launch_recover(const Plan &pl, const DevState &ds, uint64_t *out, int
 #define ZPM_REC(NP_)                                                                           \
   case NP_:                                                                                    \
     if (staged)                                                                                \
-      hipLaunchKernelGGL((k_recovering_product<NP_, 1>), dim3((unsigned)blocks), dim3(BLOCK), lds, \
+      ZPM_LAUNCH((k_recovering_product<NP_, 1>), dim3((unsigned)blocks), dim3(BLOCK), lds, \
                          st, ds.X, L, pl.K, pl.M, pl.nout, nw32, wc, logTI, ds.primes, ds.plan, \
                          out);                                                                 \
     else                                                                                       \
-      hipLaunchKernelGGL((k_recovering_product<NP_, 0>), dim3((unsigned)blocks), dim3(BLOCK), lds, \
+      ZPM_LAUNCH((k_recovering_product<NP_, 0>), dim3((unsigned)blocks), dim3(BLOCK), lds, \
                          st, ds.X, L, pl.K, pl.M, pl.nout, nw32, wc, logTI, ds.primes, ds.plan, \
                          out);                                                                 \
     break;
@@ -288,40 +306,41 @@ hipError_t launch_mul(const Plan &pl, const DevState &ds, const uint64_t *a, con
   hipError_t e;
   Profiler dummy;
   Profiler &pr = prof ? *prof : dummy;
-  pr.begin(KK_CONVERT_IN, st);
-  e = launch_convert_in(pl, ds, a, pl.da, pl.Na, 0, st);
-  pr.end(st);
+  // each stage is one kernel launch; a recorded kind gets the launch's own events
+  auto timed = [&](int kind, auto &&launch) -> hipError_t {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (!pr.take_pair(kind, &ea, &eb)) return launch();
+    t_ev_start = ea;
+    t_ev_stop = eb;
+    const hipError_t r = launch();
+    if (t_ev_start) {   // nothing was launched: the span is empty
+      (void)hipEventRecord(ea, st);
+      (void)hipEventRecord(eb, st);
+      t_ev_start = t_ev_stop = nullptr;
+    }
+    return r;
+  };
+  e = timed(KK_CONVERT_IN, [&] { return launch_convert_in(pl, ds, a, pl.da, pl.Na, 0, st); });
   if (e != hipSuccess) return e;
   if (!pl.square) {    // a square transforms its one operand once
-    pr.begin(KK_CONVERT_IN, st);
-    e = launch_convert_in(pl, ds, b, pl.db, pl.Nb, pl.K, st);
-    pr.end(st);
+    e = timed(KK_CONVERT_IN, [&] { return launch_convert_in(pl, ds, b, pl.db, pl.Nb, pl.K, st); });
     if (e != hipSuccess) return e;
   }
   if (stop_after == 1) return hipSuccess;
   for (int cidx = 0; cidx < pl.ncol; ++cidx) {
-    pr.begin(KK_COL_FWD, st);
-    e = launch_col(pl, ds, cidx, false, st);
-    pr.end(st);
+    e = timed(KK_COL_FWD, [&] { return launch_col(pl, ds, cidx, false, st); });
     if (e != hipSuccess) return e;
   }
   if (stop_after == 2) return hipSuccess;
-  pr.begin(KK_CONVOLVE, st);
-  e = launch_convolve(pl, ds, st);
-  pr.end(st);
+  e = timed(KK_CONVOLVE, [&] { return launch_convolve(pl, ds, st); });
   if (e != hipSuccess) return e;
   if (stop_after == 3) return hipSuccess;
   for (int cidx = pl.ncol - 1; cidx >= 0; --cidx) {
-    pr.begin(KK_COL_INV, st);
-    e = launch_col(pl, ds, cidx, true, st);
-    pr.end(st);
+    e = timed(KK_COL_INV, [&] { return launch_col(pl, ds, cidx, true, st); });
     if (e != hipSuccess) return e;
   }
   if (stop_after == 4) return hipSuccess;
-  pr.begin(KK_RECOVER, st);
-  e = launch_recover(pl, ds, c, wc, st);
-  pr.end(st);
-  return e;
+  return timed(KK_RECOVER, [&] { return launch_recover(pl, ds, c, wc, st); });
 }
 
 }  // namespace zpm

@@ -56,6 +56,17 @@ struct Profiler {
       open = true;
     }
   }
+  // A start/stop pair for a kind that is being recorded (false otherwise), for a launch
+  // that records the events itself.
+  bool take_pair(int kind, hipEvent_t *a, hipEvent_t *b) {
+    if (!on || !((mask >> kind) & 1u)) return false;
+    Rec r{kind, take(), take()};
+    if (!r.a || !r.b) return false;
+    recs.push_back(r);
+    *a = r.a;
+    *b = r.b;
+    return true;
+  }
   void end(hipStream_t st) {
     if (!on || !open) return;
     (void)hipEventRecord(recs.back().b, st);
