@@ -167,7 +167,12 @@ int zpm_mul(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint6
  * convert-in, the forward column passes, the row convolutions or the inverse
  * column passes, and copy the workspace (np*2K*L uint32 residues, column
  * (k, j) at [(k*2K + j)*L, ...)) to the device buffer ws_out, which must hold
- * zpm_plan_info.workspace_bytes. */
+ * zpm_plan_info.workspace_bytes.  Residues are kept below 2 p_k, not fully reduced.
+ * After convert-in, column j < K of prime k holds a's limbs a_{i,j} mod p_k (the
+ * top limb signed) for i < da, and column K + j b's; after the inverse column
+ * passes, column j < 2K - 1 holds c_{i,j} (2K L) 2^-32 mod p_k for i < da + db - 1
+ * (Section 2: the transforms are unnormalised and the pointwise product is a
+ * Montgomery product; the recovery applies 2^32 / (2K L) with its CRT constant). */
 int zpm_mul_ex(zpm_ctx *ctx, const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b,
                int64_t db, int32_t Nb, uint64_t *c, int32_t wc, int32_t K, int32_t np,
                int32_t stop_after, uint32_t *ws_out, void *stream);

@@ -274,11 +274,15 @@ void scale_constants(int np, int K, int M, int logL, PlanDev &pd) {
   const auto &T = prime_table();
   for (int k = 0; k < np; ++k) {
     uint32_t p = T[k].p;
-    // the inverse transforms are left unscaled; (2K L)^{-1} is applied once, times
-    // 2^32 to undo the 2^{-32} of the Montgomery pointwise product.
+    // The transforms are left unscaled and the pointwise product is a Montgomery
+    // product, so the row kernels leave c_{i,j} (2K L) 2^-32 mod p.  The normalisation
+    // 2^32 (2K L)^{-1} is folded into the recovery's first constant, (P/p_k)^{-1}
+    // (crt_constants must have run).
     uint64_t n = ((uint64_t)(2 * K) << logL) % p;
     uint32_t s = mulmod(invmod((uint32_t)n, p), T[k].c32, p);
     pd.scale[k] = make_uint2(s, shoup(s, p));
+    const uint32_t ci = mulmod(pd.crt_inv[k].x, s, p);
+    pd.crt_inv[k] = make_uint2(ci, shoup(ci, p));
     pd.pow2M[k] = powmod(2, (uint64_t)M, p);
   }
 }

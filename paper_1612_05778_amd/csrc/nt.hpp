@@ -29,6 +29,7 @@ void fill_heap(int k, int H, uint2 *hf, uint2 *hi);
 int bitlen_product(int np);
 bool primes_cover(int np, int64_t d, int64_t K, int64_t M);
 void crt_constants(int np, PlanDev &pd);
+// after crt_constants: also folds the transforms' normalisation into crt_inv
 void scale_constants(int np, int K, int M, int logL, PlanDev &pd);
 
 }  // namespace zpm

@@ -591,8 +591,10 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
 // halves then hold the cyclic (mod x^K - 1) and twisted (mod x^K + 1) spectra.
 // After the pointwise product the DIT inverse of length 2K undoes both transforms;
 // its last stage applies theta^-j (untwist) and forms c- + c+ and c- - c+, which
-// after the 1/(2K) in the scale constant are c_{i,j} and c_{i,j+K} (Section 2,
-// C+ and C- through Relation (recoveringC)).
+// times 1/(2K) are c_{i,j} and c_{i,j+K} (Section 2, C+ and C- through Relation
+// (recoveringC)).  The pointwise product is a plain Montgomery product: the
+// normalisation by 2^32 / (2K L) waits for the recovery, whose first multiplication
+// per residue takes it with the CRT constant.
 // ------------------------------------------------------------------------------------
 // CLOGK / CLOGL1 >= 0: K and L1 fixed at compile time (== the runtime values).
 template <int CLOGK = -1, int CLOGL1 = -1>
@@ -663,10 +665,9 @@ __device__ void body_convolve(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     });
     return;
   }
-  const uint2 sc = pd->scale[k];
   const uint32_t *F = mode == CM_SQUARE ? A : B;
   for (int idx = threadIdx.x; idx < (twoK << logL1); idx += BLOCK)
-    A[idx] = mul_shoup_lz(mont_mul_lz(A[idx], F[idx], p, pr.pinv), sc, p);
+    A[idx] = mont_mul_lz(A[idx], F[idx], p, pr.pinv);
   __syncthreads();
   if constexpr (fixed) {
     lds_dit_c<CShape<FL1, FK + 1, 1, (1 << FL1)>>(s, pr.hi, p);
@@ -778,7 +779,6 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
     }
     return;
   }
-  const uint2 sc = pd->scale[k];
   if constexpr (one) {
     // one forward transform per column, times itself or b's stored spectrum
     const uint32_t *sb = spec + (int64_t)k * K2 * L + rb * L1;
@@ -789,11 +789,11 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
       reg_dif<LOGK>(a, pr.hf, p);
       if constexpr (MODE == CM_SQUARE) {
 #pragma unroll
-        for (int j = 0; j < K2; ++j) a[j] = mul_shoup_lz(mont_mul_lz(a[j], a[j], p, pr.pinv), sc, p);
+        for (int j = 0; j < K2; ++j) a[j] = mont_mul_lz(a[j], a[j], p, pr.pinv);
       } else {
 #pragma unroll
         for (int j = 0; j < K2; ++j)
-          a[j] = mul_shoup_lz(mont_mul_lz(a[j], sb[j * L32 + e], p, pr.pinv), sc, p);
+          a[j] = mont_mul_lz(a[j], sb[j * L32 + e], p, pr.pinv);
       }
       reg_dit<LOGK>(a, pr.hi, p);
 #pragma unroll
@@ -816,7 +816,7 @@ __device__ void body_convolve_reg(uint32_t *s, int64_t bid, uint32_t *__restrict
     }
     reg_dif<LOGK>(b, pr.hf, p);
 #pragma unroll
-    for (int j = 0; j < K2; ++j) b[j] = mul_shoup_lz(mont_mul_lz(s[j * RS + e], b[j], p, pr.pinv), sc, p);
+    for (int j = 0; j < K2; ++j) b[j] = mont_mul_lz(s[j * RS + e], b[j], p, pr.pinv);
     reg_dit<LOGK>(b, pr.hi, p);
 #pragma unroll
     for (int j = 0; j < K2; ++j) s[j * RS + e] = b[j];
@@ -946,7 +946,6 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
     }
     return;
   }
-  const uint2 sc = pd->scale[k];
   const uint32_t *sb = spec + (int64_t)k * K2 * L + rb * L1;
   for (int e = threadIdx.x; e < L1; e += BLOCK) {
     uint32_t x[K];
@@ -971,10 +970,10 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
       twisted(x);
 #pragma unroll
       for (int j = 0; j < K; ++j)
-        s[(K + j) * RS + e] = mul_shoup_lz(mont_mul_lz(s[(K + j) * RS + e], x[j], p, pr.pinv), sc, p);
+        s[(K + j) * RS + e] = mont_mul_lz(s[(K + j) * RS + e], x[j], p, pr.pinv);
       reg_half_dif<LOGK>(b, hf, p);
 #pragma unroll
-      for (int j = 0; j < K; ++j) s[j * RS + e] = mul_shoup_lz(mont_mul_lz(s[j * RS + e], b[j], p, pr.pinv), sc, p);
+      for (int j = 0; j < K; ++j) s[j * RS + e] = mont_mul_lz(s[j * RS + e], b[j], p, pr.pinv);
     } else {
       // one operand transformed once: times itself, or times b's stored spectra
 #pragma unroll
@@ -983,7 +982,7 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const uint32_t f = MODE == CM_SQUARE ? x[j] : sb[(K + j) * L32 + e];
-        x[j] = mul_shoup_lz(mont_mul_lz(x[j], f, p, pr.pinv), sc, p);
+        x[j] = mont_mul_lz(x[j], f, p, pr.pinv);
       }
       uint32_t t[K];
 #pragma unroll
@@ -994,7 +993,7 @@ __device__ void body_convolve_split(uint32_t *s, int64_t bid, uint32_t *__restri
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const uint32_t f = MODE == CM_SQUARE ? t[j] : sb[j * L32 + e];
-        s[j * RS + e] = mul_shoup_lz(mont_mul_lz(t[j], f, p, pr.pinv), sc, p);
+        s[j * RS + e] = mont_mul_lz(t[j], f, p, pr.pinv);
       }
     }
     // inverse: the two K-point DITs, then the joining stage with theta^-j

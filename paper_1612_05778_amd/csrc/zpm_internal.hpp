@@ -56,8 +56,10 @@ struct PrimeDev {
 // Per-plan constants (np primes, transform sizes) resident on the device.
 struct PlanDev {
   uint2 scale[MAXNP];      // Montgomery-corrected 1/(2K L): 2^32 (2 K L)^{-1} mod p, Shoup pair
+                           // (already folded into crt_inv; kept for inspection)
   uint32_t pow2M[MAXNP];   // 2^M mod p (weight of the sign bit of the top limb)
-  uint2 crt_inv[MAXNP];    // (P/p_k)^{-1} mod p_k, Shoup pair
+  uint2 crt_inv[MAXNP];    // (P/p_k)^{-1} scale_k mod p_k, Shoup pair: the CRT constant times
+                           // the transforms' normalisation
   double crt_rcp[MAXNP];   // 1/p_k
   uint32_t crt_q[MAXNP][MAXW];  // P/p_k, little-endian 32-bit words
   uint32_t crt_p[MAXW];         // P
