@@ -13,7 +13,8 @@ whose first stage is the twist):
   2p (add, sub, min), u - v + 2p (2), its Shoup product with the twiddle (mul_hi,
   mul_lo and a multiply-add); one inverse (DIT) butterfly = 9: the Shoup product (3),
   u + v and u - v reduced below 2p (3 each);
-* one pointwise product = 9 (Montgomery product up to one p 6, Shoup scaling 3);
+* one pointwise product = 6 (Montgomery product up to one p; the normalisation by
+  2^32 / (2K L) is taken by the recovery's first Shoup product, counted there);
 * one four-step twiddle or twist product = 3 (Shoup product up to one p);
 * convert-in, per limb residue: 2 per 32-bit word of the limb (a multiply-add with
   the table entry 2^(32 t) mod p and its carry) plus 6 for the final reduction;
@@ -35,7 +36,7 @@ import math
 
 OPS_BFLY_DIF = 8
 OPS_BFLY_DIT = 9
-OPS_POINTWISE = 9
+OPS_POINTWISE = 6
 OPS_TWIDDLE = 3
 INT32_PEAK = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes x 2.4 GHz: int32 VALU op/s
 HBM_PEAK = 8.0e12                   # bytes/s
