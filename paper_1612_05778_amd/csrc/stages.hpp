@@ -327,7 +327,7 @@ __device__ __forceinline__ void mac_carry(uint64_t &lo, uint32_t &hi, uint32_t a
 
 // NP = np exactly: per-prime accumulators stay in registers, loops fully unrolled.
 template <int NP>
-__device__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__restrict__ src,
+__device__ __forceinline__ void body_convert_in(uint32_t *s, int64_t tile_id, const uint64_t *__restrict__ src,
                                 int64_t d, int32_t N, int32_t w, int32_t K, int32_t M, int32_t np,
                                 uint32_t *__restrict__ X, int64_t L, int32_t col_off, int32_t logTI,
                                 const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd) {
