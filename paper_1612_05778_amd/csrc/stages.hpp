@@ -337,6 +337,13 @@ __device__ __forceinline__ void body_convert_in(uint32_t *s, int64_t tile_id, co
   const int ti = (int)min<int64_t>(TI, d - i0);
   const int nw = 2 * w;
   const int stride = nw + 1;
+  const int nchunks = (M + 31) >> 5;
+  // 2^(32 t) mod p_k, [t][k], after the staged tile; read together with the tile
+  uint32_t *pw = s + (((ti * stride) + 1) & ~1);
+  for (int idx = threadIdx.x; idx < nchunks * np; idx += BLOCK) {
+    const int t = idx / np, k = idx - t * np;
+    pw[idx] = ld_tab(primes[k].pow32, t).x;
+  }
   // stage the tile's words (one contiguous block of ti * w words)
   const uint64_t *tile = src + i0 * w;
   staged<8, uint64_t>(ti * w, [&](int idx) { return tile[idx]; }, [&](int idx, uint64_t v) {
@@ -358,16 +365,8 @@ __device__ __forceinline__ void body_convert_in(uint32_t *s, int64_t tile_id, co
     for (int q = tq + 1; q < nw; ++q) row[q] = sgn;
   }
   __syncthreads();
-  const int nchunks = (M + 31) >> 5;
   const uint32_t lastmask = (M & 31) ? ((1u << (M & 31)) - 1u) : 0xFFFFFFFFu;
   const int64_t twoK = 2 * (int64_t)K;
-  // 2^(32 t) mod p_k, [t][k], after the staged tile
-  uint32_t *pw = s + (((ti * stride) + 1) & ~1);
-  for (int idx = threadIdx.x; idx < nchunks * np; idx += BLOCK) {
-    const int t = idx / np, k = idx - t * np;
-    pw[idx] = ld_tab(primes[k].pow32, t).x;
-  }
-  __syncthreads();
   uint32_t pk[NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) pk[k] = primes[k].p;
