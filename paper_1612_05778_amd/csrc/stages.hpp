@@ -484,17 +484,36 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
       // rows past nz (zero limbs) read as zero
       const int64_t nzr = std::min<int64_t>(std::max<int64_t>(nz - first, 0), L - first);
       const __amdgpu_buffer_rsrc_t rin = make_col_rsrc(base, (uint32_t)nzr * 4u);
+      if (nzr <= ((int64_t)(1 << (CLOGN - 1)) << logS)) {
+        // rows n/2 and up are zero (an operand shorter than half the transform, as in a
+        // product's outermost pass): the first DIF stage leaves row e as it is and makes
+        // row e + n/2 the row times w_n^e, so only the lower half is read
+        constexpr int NH = NI / 2, HN = 1 << (CLOGN - 1);
+        uint32_t v[NH];
 #pragma unroll
-      for (int k0 = 0; k0 < NI; k0 += LG) {
-        uint32_t v[LG];
+        for (int u = 0; u < NH; ++u)
+          v[u] = __builtin_amdgcn_raw_buffer_load_b32(rin, voff0 + u * vstep, 0, 0);
 #pragma unroll
-        for (int u = 0; u < LG; ++u)
-          v[u] = __builtin_amdgcn_raw_buffer_load_b32(rin, voff0 + (k0 + u) * vstep, 0, 0);
+        for (int u = 0; u < NH; ++u) {
+          const int e = e0 + u * de;                           // below n/2
+          s[threadIdx.x + u * BLOCK] = v[u];
+          s[threadIdx.x + (u + NH) * BLOCK] = mul_shoup_lz(v[u], ld_tab(pr.hf, HN + e), p);
+        }
+        __syncthreads();
+        lds_dif_c<CSH, CLOGN - 1>(s, pr.hf, p);
+      } else {
 #pragma unroll
-        for (int u = 0; u < LG; ++u) s[threadIdx.x + (k0 + u) * BLOCK] = v[u];
+        for (int k0 = 0; k0 < NI; k0 += LG) {
+          uint32_t v[LG];
+#pragma unroll
+          for (int u = 0; u < LG; ++u)
+            v[u] = __builtin_amdgcn_raw_buffer_load_b32(rin, voff0 + (k0 + u) * vstep, 0, 0);
+#pragma unroll
+          for (int u = 0; u < LG; ++u) s[threadIdx.x + (k0 + u) * BLOCK] = v[u];
+        }
+        __syncthreads();
+        lds_dif_c<CSH>(s, pr.hf, p);
       }
-      __syncthreads();
-      lds_dif_c<CSH>(s, pr.hf, p);
       const __amdgpu_buffer_rsrc_t rout = make_col_rsrc(base, col_bytes);
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
