@@ -141,6 +141,7 @@ hipError_t launch_group(const Group &gr, const JobDev *jobs, const GroupSeg *seg
   case I: hipLaunchKernelGGL((kg_col<LN, LT>), g8, blk, gr.lds, st, jobs, sg, ns, inv, primes, gr.blocks); break;
         ZPM_G(0, -1, -1) ZPM_G(1, 5, 6) ZPM_G(2, 6, 5) ZPM_G(3, 7, 4) ZPM_G(4, 8, 3) ZPM_G(5, 9, 3)
         ZPM_G(6, 10, 3) ZPM_G(7, 8, 4) ZPM_G(8, 9, 4) ZPM_G(9, 10, 4)
+        ZPM_G(10, 1, 8) ZPM_G(11, 2, 8) ZPM_G(12, 3, 8) ZPM_G(13, 4, 7)
 #undef ZPM_G
         default: return hipErrorInvalidValue;
       }

@@ -197,6 +197,8 @@ hipError_t launch_col(const Plan &pl, const DevState &ds, int c, bool inverse, h
     ZPM_COL_FIXED(1, 5, 6) ZPM_COL_FIXED(2, 6, 5) ZPM_COL_FIXED(3, 7, 4)
     ZPM_COL_FIXED(4, 8, 3) ZPM_COL_FIXED(5, 9, 3) ZPM_COL_FIXED(6, 10, 3)
     ZPM_COL_FIXED(7, 8, 4) ZPM_COL_FIXED(8, 9, 4) ZPM_COL_FIXED(9, 10, 4)
+    ZPM_COL_FIXED(10, 1, 8) ZPM_COL_FIXED(11, 2, 8) ZPM_COL_FIXED(12, 3, 8)
+    ZPM_COL_FIXED(13, 4, 7)
 #undef ZPM_COL_FIXED
     default: ZPM_LAUNCH_X((k_col_pass<-1, -1>), ZPM_COL_ARGS); break;
   }

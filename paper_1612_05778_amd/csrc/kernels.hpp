@@ -8,9 +8,10 @@
 namespace zpm {
 
 // Column-pass shapes with a compile-time kernel: the planner's default tile for each pass
-// length from 2^5 to 2^10 (log2 length, log2 tile).  Index + 1, or 0 for any other shape.
+// length from 2^1 to 2^10 (log2 length, log2 tile), and 8-column tiles for the longer
+// ones.  Index + 1, or 0 for any other shape.
 constexpr int FIXED_COL[][2] = {{5, 6}, {6, 5}, {7, 4}, {8, 3}, {9, 3}, {10, 3},
-                                 {8, 4}, {9, 4}, {10, 4}};
+                                 {8, 4}, {9, 4}, {10, 4}, {1, 8}, {2, 8}, {3, 8}, {4, 7}};
 inline int fixed_col_index(int logn, int logT) {
   for (int i = 0; i < (int)(sizeof(FIXED_COL) / sizeof(FIXED_COL[0])); ++i)
     if (FIXED_COL[i][0] == logn && FIXED_COL[i][1] == logT) return i + 1;

@@ -473,9 +473,10 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
     // in the scalar offset.
     constexpr int LDE = 8 - CLOGT;                  // log2(BLOCK / T)
     constexpr int LI = CLOGN - LDE;
-    constexpr int NI = 1 << LI;                     // rows per thread (>= 8)
+    constexpr int NI = 1 << LI;                     // rows per thread
     constexpr int LG = NI < 32 ? NI : 32;           // loads in flight per thread
-    static_assert(LI >= 3 && (BLOCK >> CLOGT) << LI == (1 << CLOGN), "column pass shape");
+    constexpr int G8 = NI < 8 ? NI : 8;             // LDS values per store group
+    static_assert(LI >= 1 && (BLOCK >> CLOGT) << LI == (1 << CLOGN), "column pass shape");
     const int voff0 = (t + (e0 << logS)) * 4;
     const int vstep = (de << logS) * 4;
     const uint32_t col_bytes = (uint32_t)(L - first) * 4u;
@@ -540,12 +541,12 @@ __device__ void body_col_pass(uint32_t *s, int64_t bid, uint32_t *__restrict__ X
       // rows with t + e S at or past lim_store are not stored
       const __amdgpu_buffer_rsrc_t rst = make_col_rsrc(base, (uint32_t)lim_store * 4u);
 #pragma unroll
-      for (int k0 = 0; k0 < NI; k0 += 8) {
-        uint32_t v[8];
+      for (int k0 = 0; k0 < NI; k0 += G8) {
+        uint32_t v[G8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = s[threadIdx.x + (k0 + u) * BLOCK];
+        for (int u = 0; u < G8; ++u) v[u] = s[threadIdx.x + (k0 + u) * BLOCK];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < G8; ++u)
           __builtin_amdgcn_raw_buffer_store_b32(v[u], rst, voff0 + (k0 + u) * vstep, 0, 0);
       }
     }

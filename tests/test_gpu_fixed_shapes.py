@@ -1,10 +1,12 @@
 """Products that reach the kernels with compile-time transform shapes.
 
 Long products use the row kernel with the inner y-factor L1 = 2^(12 - log2 K) fixed at
-compile time, and column passes of 2^5 ... 2^10 points with fixed tile widths.  Every K
+compile time, and column passes of 2^1 ... 2^10 points with fixed tile widths.  Every K
 of the register row kernels (2, 4, 8, 16) is run with a column pass of each length, as
-a product and as a square, and compared with the oracle at sampled output indices (the
-first, last and middle coefficients, the operand boundary and random ones).
+a product, as a square, and as a product whose first operand is longer than half the
+transform (the forward pass then reads both halves of each column; otherwise only the
+lower one), and compared with the oracle at sampled output indices (the first, last and
+middle coefficients, the operand boundary and random ones).
 """
 import numpy as np
 import pytest
@@ -24,7 +26,7 @@ def ctx():
     c.close()
 
 
-CASES = [(K, logn) for K in (2, 4, 8, 16) for logn in (5, 6, 7, 8, 9, 10)
+CASES = [(K, logn) for K in (2, 4, 8, 16) for logn in range(1, 11)
          if (12 - (K.bit_length() - 1)) + logn <= 21]
 
 
@@ -58,6 +60,13 @@ def test_fixed_shapes(ctx, K, logn):
     sq = synth.Product(a, N, a, N)
     got_sq = host(ctx.mul(A, N, A, N, K=K))
     sampled(sq, got_sq, logn + 1)
+    # a longer than half the transform (its forward pass reads both halves), b shorter
+    da2, db2 = (1 << (logL - 1)) + 3, 1 << (logL - 2)
+    a2, _ = synth.signed_words(r, da2, N - 1)
+    b2, _ = synth.signed_words(r, db2, N - 1)
+    pl2 = api.plan(da2, N, db2, N, K=K)
+    assert (pl2["log2_L"], pl2["col_log2n"]) == (logL, [logn])
+    sampled(synth.Product(a2, N, b2, N), host(ctx.mul(dev(a2), N, dev(b2), N, K=K)), logn + 2)
     del A, B
     torch.cuda.empty_cache()
 
