@@ -86,7 +86,11 @@ const char *zpm_strerror(int err);
 int32_t zpm_out_bits(int64_t da, int32_t Na, int64_t db, int32_t Nb);
 
 /* Planner (host only, needs no GPU).  K and np: 0 = choose, otherwise forced
- * (ZPM_EUNSUPPORTED if no feasible plan has them). */
+ * (ZPM_EUNSUPPORTED if no feasible plan has them).  Reports the plan zpm_mul takes for
+ * a product run alone: with K and np both chosen, a small product whose inner
+ * y-factor is 2^10 or more (x-transforms in registers, at most one column pass) has
+ * that factor shortened until the fused row kernel has at least 128 workgroups.
+ * Batches and resident operands keep the cost model's split. */
 int zpm_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np,
              zpm_plan_info *out);
 

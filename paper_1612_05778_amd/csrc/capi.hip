@@ -134,13 +134,16 @@ int Ctx::ensure_ws(int64_t words) {
 }
 
 int Ctx::get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np,
-                  Plan *out) {
-  auto key = std::make_tuple(da, Na, db, Nb, K, np, (int32_t)-2);   // -2: single-product plans
+                  Plan *out, bool alone) {
+  // -2: plans of products alone, -3: of resident operands
+  auto key = std::make_tuple(da, Na, db, Nb, K, np, (int32_t)(alone ? -2 : -3));
   auto it = plans.find(key);
   if (it != plans.end()) { *out = it->second; return ZPM_OK; }
   Plan pl;
   const char *why = nullptr;
-  if (!make_plan(da, Na, db, Nb, K, np, pl, &why)) return ZPM_EUNSUPPORTED;
+  PlanLimits lim;
+  lim.row_groups_min = alone ? ROW_GROUPS_MIN : 0;
+  if (!make_plan(da, Na, db, Nb, K, np, pl, &why, &lim)) return ZPM_EUNSUPPORTED;
   if (plans.size() > 65536) plans.clear();
   plans[key] = pl;
   *out = pl;
@@ -293,7 +296,9 @@ int zpm_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t 
   if (!out || da < 1 || db < 1 || Na < 1 || Nb < 1 || K < 0 || np < 0) return ZPM_EINVAL;
   Plan pl;
   const char *why = nullptr;
-  if (!make_plan(da, Na, db, Nb, K, np, pl, &why)) return ZPM_EUNSUPPORTED;
+  PlanLimits lim;
+  lim.row_groups_min = ROW_GROUPS_MIN;     // the plan zpm_mul takes
+  if (!make_plan(da, Na, db, Nb, K, np, pl, &why, &lim)) return ZPM_EUNSUPPORTED;
   fill_info(pl, out);
   return ZPM_OK;
 }
@@ -588,7 +593,7 @@ int zpm_operand_create(zpm_ctx *ctx, const uint64_t *b, int64_t db, int32_t Nb, 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if ((rc = cx->check_range(b, db, Nb, st)) != ZPM_OK) return rc;
   Plan pl;
-  if ((rc = cx->get_plan(da_max, Na_max, db, Nb, K, 0, &pl)) != ZPM_OK) return rc;
+  if ((rc = cx->get_plan(da_max, Na_max, db, Nb, K, 0, &pl, false)) != ZPM_OK) return rc;
   const int64_t H = std::max<int64_t>((int64_t)1 << pl.logL, 2 * (int64_t)pl.K);
   if ((rc = cx->ensure_tables(pl.np, H, (pl.M + 31) / 32 + 1)) != ZPM_OK) return rc;
   PlanDev *pd = nullptr;

@@ -120,7 +120,10 @@ struct Ctx {
   int ensure_kbuf(int64_t words);
   int mul_kronecker(const uint64_t *a, int64_t da, int32_t Na, const uint64_t *b, int64_t db,
                     int32_t Nb, uint64_t *c, int32_t wc, int32_t chunk_bits, hipStream_t st);
-  int get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np, Plan *out);
+  // alone: the plan of a product that runs by itself (the row-group floor applies);
+  // false for a resident operand, whose plan also serves batches
+  int get_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K, int32_t np, Plan *out,
+               bool alone = true);
   int prepare(const Plan &pl, DevState *ds, hipStream_t st = nullptr);
   int get_plan_batch(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force,
                      int32_t T_force, Plan *out);

@@ -55,7 +55,7 @@ static int64_t col_tile_max() {
   return v;
 }
 
-static bool split_y(Plan &pl, int reg_k_max, int col_tile) {
+static bool split_y(Plan &pl, int reg_k_max, int col_tile, int l1_cap = 64) {
   const int logK = ceil_log2(pl.K);
   int logcap = 0;
   pl.conv_reg = pl.K <= reg_k_max ? 1 : 0;
@@ -70,7 +70,7 @@ static bool split_y(Plan &pl, int reg_k_max, int col_tile) {
     // instead of two, which hides the LDS latency of the x-transforms
     if (logcap >= 1) --logcap;
   }
-  pl.logL1 = std::min(pl.logL, logcap);
+  pl.logL1 = std::min(pl.logL, std::min(logcap, l1_cap));
   int rest = pl.logL - pl.logL1;
   int npass = (rest + 9) / 10;
   if (npass > MAX_COL_PASSES) return false;
@@ -209,6 +209,24 @@ bool make_plan(int64_t da, int32_t Na, int64_t db, int32_t Nb, int32_t K_force, 
     if (!found || pl.cost < best.cost) { best = pl; found = true; }
   }
   if (!found) { *why = "no feasible (K, M, np) for these sizes"; return false; }
+  // A small product's fused row kernel runs one workgroup per prime and inner block of
+  // L1 rows: with a long inner factor that is a handful of workgroups, each working
+  // through log2 L1 LDS stages, while the rest of the chip idles.  For a product that
+  // runs alone, shorten the inner factor (K unchanged) until there are enough workgroups;
+  // the column pass that takes the difference costs two short launches.  Only deep inner
+  // transforms gain: at 2^9 or less, or with K >= 8, the pass costs more than it saves.
+  // A forced K or np keeps the cost model's split.
+  if (lim->row_groups_min > 0 && !K_force && !np_force && best.conv_reg && best.ncol <= 1 &&
+      best.logL1 >= 10) {
+    int cap = best.logL1;
+    while (cap > 5 && ((int64_t)best.np << (best.logL - cap)) < lim->row_groups_min) --cap;
+    Plan alt = best;
+    if (cap < best.logL1 && split_y(alt, lim->reg_k_max, lim->col_tile, cap) && alt.ncol <= 1 &&
+        finish(alt)) {
+      alt.cost = model_cost(alt);
+      best = alt;
+    }
+  }
   out = best;
   return true;
 }

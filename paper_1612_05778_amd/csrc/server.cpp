@@ -332,7 +332,9 @@ int Server::plan_req(SReq &r) {
                    plan_for_batch(tuned, j.da, j.Na, j.db, j.Nb, 0, 0, &pl) == ZPM_OK;
       if (!batch) {
         const char *why = nullptr;
-        if (!make_plan(j.da, j.Na, j.db, j.Nb, 0, 0, pl, &why, nullptr)) return ZPM_EUNSUPPORTED;
+        PlanLimits lim;
+        lim.row_groups_min = ROW_GROUPS_MIN;
+        if (!make_plan(j.da, j.Na, j.db, j.Nb, 0, 0, pl, &why, &lim)) return ZPM_EUNSUPPORTED;
       }
       if (plan_cache.size() > 65536) plan_cache.clear();
       plan_cache[key] = std::make_pair(pl, batch);

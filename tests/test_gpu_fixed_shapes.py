@@ -6,7 +6,9 @@ of the register row kernels (2, 4, 8, 16) is run with a column pass of each leng
 a product, as a square, and as a product whose first operand is longer than half the
 transform (the forward pass then reads both halves of each column; otherwise only the
 lower one), and compared with the oracle at sampled output indices (the first, last and
-middle coefficients, the operand boundary and random ones).
+middle coefficients, the operand boundary and random ones).  Small products run alone
+with a shortened inner factor (the planner's row-group floor) must give the words of
+the forced-K plan and of the oracle.
 """
 import numpy as np
 import pytest
@@ -131,5 +133,36 @@ def test_batch_eight_column_passes(K, logn, tmp_path):
     assert np.array_equal(got, single), "8-column batch passes differ from the single product"
     sampled(synth.Product(a, N, b, N), got, logn + 5)
     ctx.close()
+    del A, B
+    torch.cuda.empty_cache()
+
+
+# Small products that run alone shorten a deep inner factor so that the row kernel has
+# at least 128 workgroups; the forced-K product keeps the cost model's split.  Both must
+# give the same words, and match the oracle (every row of the smallest, sampled rows
+# otherwise); ragged sizes and unequal operands included.
+@pytest.mark.parametrize("da,Na,db,Nb", [
+    (1024, 64, 1024, 64), (4096, 64, 4096, 64), (2048, 128, 2048, 128), (16384, 64, 16384, 64),
+    (512, 1024, 512, 1024), (3001, 77, 1900, 51), (1500, 300, 20, 900),
+])
+def test_small_products_split_inner_factor(ctx, da, Na, db, Nb):
+    r = np.random.default_rng(da + 7 * Na)
+    a, Na = synth.signed_words(r, da, Na - 1)
+    b, Nb = synth.signed_words(r, db, Nb - 1)
+    pl = api.plan(da, Na, db, Nb)
+    base = api.plan(da, Na, db, Nb, K=pl["K"])
+    print(f"[alone split] {da}x{Na} * {db}x{Nb}: K={pl['K']} np={pl['np']} "
+          f"L1=2^{pl['log2_L1']} passes={pl['col_log2n']} (cost model: L1=2^{base['log2_L1']} "
+          f"passes={base['col_log2n']})", flush=True)
+    A, B = dev(a), dev(b)
+    got = host(ctx.mul(A, Na, B, Nb))
+    forced = host(ctx.mul(A, Na, B, Nb, K=pl["K"]))
+    assert np.array_equal(got, forced), "the split plan and the cost model's differ"
+    prod = synth.Product(a, Na, b, Nb)
+    if da * db <= 1 << 21:
+        want = oracle.polymul(a, da, Na, b, db, Nb, wc=got.shape[1])
+        assert np.array_equal(got, want), "differs from the oracle"
+    else:
+        sampled(prod, got, da)
     del A, B
     torch.cuda.empty_cache()

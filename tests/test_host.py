@@ -140,6 +140,29 @@ def test_forced_plans(nat):
         api.plan(0, 5, 3, 5)
 
 
+def test_small_products_alone_get_more_row_groups(nat):
+    """Products that run alone with a deep inner y-factor (2^10 or more, x-transforms in
+    registers) shorten it until the row kernel has at least 128 workgroups (np per inner
+    block of rows); K and the primes stay the cost model's, and a forced K keeps its split."""
+    from paper_1612_05778_amd import api
+    for (da, Na) in [(1024, 64), (4096, 64), (2048, 128), (16384, 64), (512, 1024), (3001, 77)]:
+        pl = api.plan(da, Na, da, Na)
+        base = api.plan(da, Na, da, Na, K=pl["K"])
+        assert base["log2_L1"] >= 10 and base["ncol"] <= 1, base
+        assert (pl["K"], pl["M"], pl["np"], pl["log2_L"]) == \
+            (base["K"], base["M"], base["np"], base["log2_L"])
+        assert pl["log2_L1"] < base["log2_L1"] and pl["ncol"] == 1, pl
+        assert pl["log2_L1"] + pl["col_log2n"][0] == pl["log2_L"]
+        groups = pl["np"] << (pl["log2_L"] - pl["log2_L1"])
+        assert groups >= 128 and (pl["log2_L1"] == 5 or groups < 256), pl
+        assert pl["workspace_bytes"] == base["workspace_bytes"]
+        check_col_tiles(pl)
+    # shallow inner factors, large K, and products that fill the device keep their plan
+    for (da, Na) in [(256, 256), (128, 4096), (64, 2048), (65536, 4096), (65536, 64)]:
+        pl = api.plan(da, Na, da, Na)
+        assert pl == api.plan(da, Na, da, Na, K=pl["K"]), pl
+
+
 def test_out_bits_extremes(nat):
     from paper_1612_05778_amd import api
     for da, Na, db, Nb in [(1, 1, 1, 1), (3, 64, 5, 64), (4, 10, 4, 10), (1024, 64, 1024, 64),
