@@ -34,6 +34,9 @@ namespace zpm {
 #endif
 
 static inline int64_t xcd_grid(int64_t ntiles) { return 8 * ((ntiles + 7) >> 3); }
+// Products whose two conversions together take at most this many workgroups convert
+// both operands in one launch.
+constexpr int64_t CONVERT_PAIR_BLOCKS = 2048;
 
 // Timing events for the next stage kernel this thread launches (set by launch_mul while
 // the profiler records that kind): hipExtLaunchKernelGGL records them in the kernel's own
@@ -60,6 +63,24 @@ __global__ __launch_bounds__(BLOCK) void k_bivariate_representation(
   extern __shared__ uint32_t s[];
   body_convert_in<NP>(s, xcd_tile((d + (1 << logTI) - 1) >> logTI), src, d, N, w, K, M, np, X, L,
                       col_off, logTI, primes, pd);
+}
+
+// Both operands in one launch (small products, where a launch takes longer than the
+// conversion): blocks below ga convert a into columns 0..K-1, the others b into columns
+// K..2K-1.  ga is a multiple of 8, so b's blocks keep the XCD order of a launch of their own.
+template <int NP>
+__global__ __launch_bounds__(BLOCK) void k_bivariate_representation_pair(
+    const uint64_t *__restrict__ a, int64_t da, int32_t Na, int32_t wa,
+    const uint64_t *__restrict__ b, int64_t db, int32_t Nb, int32_t wb, int64_t ga, int32_t K,
+    int32_t M, int32_t np, uint32_t *__restrict__ X, int64_t L, int32_t logTI,
+    const PrimeDev *__restrict__ primes, const PlanDev *__restrict__ pd) {
+  extern __shared__ uint32_t s[];
+  const bool second = (int64_t)blockIdx.x >= ga;
+  const int64_t bid = second ? (int64_t)blockIdx.x - ga : (int64_t)blockIdx.x;
+  const int64_t d = second ? db : da;
+  body_convert_in<NP>(s, xcd_tile_of(bid, (d + (1 << logTI) - 1) >> logTI), second ? b : a, d,
+                      second ? Nb : Na, second ? wb : wa, K, M, np, X, L, second ? K : 0, logTI,
+                      primes, pd);
 }
 
 // Neighbouring tiles of a column read the two halves of the same 128-byte lines when
@@ -167,6 +188,29 @@ hipError_t launch_convert_in(const Plan &pl, const DevState &ds, const uint64_t 
     default: return hipErrorInvalidValue;
   }
 #undef ZPM_CIN
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_in_pair(const Plan &pl, const DevState &ds, const uint64_t *a,
+                                  const uint64_t *b, hipStream_t st) {
+  const int wa = (pl.Na + 63) / 64, wb = (pl.Nb + 63) / 64;
+  const int logTI = pl.log_ti_in;
+  const int64_t ga = xcd_grid((pl.da + (1 << logTI) - 1) >> logTI);
+  const int64_t blocks = ga + xcd_grid((pl.db + (1 << logTI) - 1) >> logTI);
+  const int nchunks = (pl.M + 31) >> 5;
+  const size_t lds = sizeof(uint32_t) * ((((size_t)1 << logTI) * (2 * (wa > wb ? wa : wb) + 1) + 1) & ~(size_t)1) +
+                     sizeof(uint2) * (size_t)nchunks * pl.np;
+#define ZPM_CIN2(NP_)                                                                        \
+  case NP_:                                                                                  \
+    ZPM_LAUNCH(k_bivariate_representation_pair<NP_>, dim3((unsigned)blocks), dim3(BLOCK), lds, \
+               st, a, pl.da, pl.Na, wa, b, pl.db, pl.Nb, wb, ga, pl.K, pl.M, pl.np, ds.X,        \
+               (int64_t)1 << pl.logL, logTI, ds.primes, ds.plan);                              \
+    break;
+  switch (pl.np) {
+    ZPM_NP_CASES(ZPM_CIN2)
+    default: return hipErrorInvalidValue;
+  }
+#undef ZPM_CIN2
   return hipGetLastError();
 }
 
@@ -322,11 +366,21 @@ hipError_t launch_mul(const Plan &pl, const DevState &ds, const uint64_t *a, con
     }
     return r;
   };
-  e = timed(KK_CONVERT_IN, [&] { return launch_convert_in(pl, ds, a, pl.da, pl.Na, 0, st); });
-  if (e != hipSuccess) return e;
-  if (!pl.square) {    // a square transforms its one operand once
-    e = timed(KK_CONVERT_IN, [&] { return launch_convert_in(pl, ds, b, pl.db, pl.Nb, pl.K, st); });
+  // small products convert both operands in one launch (a square its one operand once)
+  const int logTI = pl.log_ti_in;
+  const bool pair = !pl.square && xcd_grid((pl.da + (1 << logTI) - 1) >> logTI) +
+                                          xcd_grid((pl.db + (1 << logTI) - 1) >> logTI) <=
+                                      CONVERT_PAIR_BLOCKS;
+  if (pair) {
+    e = timed(KK_CONVERT_IN, [&] { return launch_convert_in_pair(pl, ds, a, b, st); });
     if (e != hipSuccess) return e;
+  } else {
+    e = timed(KK_CONVERT_IN, [&] { return launch_convert_in(pl, ds, a, pl.da, pl.Na, 0, st); });
+    if (e != hipSuccess) return e;
+    if (!pl.square) {
+      e = timed(KK_CONVERT_IN, [&] { return launch_convert_in(pl, ds, b, pl.db, pl.Nb, pl.K, st); });
+      if (e != hipSuccess) return e;
+    }
   }
   if (stop_after == 1) return hipSuccess;
   for (int cidx = 0; cidx < pl.ncol; ++cidx) {

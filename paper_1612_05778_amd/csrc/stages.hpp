@@ -310,10 +310,11 @@ __device__ __forceinline__ uint32_t get32(const uint32_t *row, int nw, uint32_t 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run
 // of tiles so that neighbouring tiles share that XCD's L2.  The grid has 8 * chunk
 // blocks; tiles >= ntiles are idle.
-__device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
+__device__ __forceinline__ int64_t xcd_tile_of(int64_t bid, int64_t ntiles) {
   const int64_t chunk = (ntiles + 7) >> 3;
-  return (int64_t)(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  return (bid & 7) * chunk + (bid >> 3);
 }
+__device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) { return xcd_tile_of(blockIdx.x, ntiles); }
 
 // lo += a b over 64 bits, hi += the carry out: the multiply-add's own carry feeds one
 // add-with-carry (the compiler would compare and select instead).  Register-only ALU.
