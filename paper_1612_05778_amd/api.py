@@ -114,8 +114,15 @@ def to_ints(t: torch.Tensor) -> list[int]:
             for i in range(t.shape[0])]
 
 
+# torch's current stream as a raw handle without building a Stream object (a few
+# microseconds per call, which small products notice); the public route otherwise
+_current_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream_handle(stream) -> int | None:
     if stream is None:
+        if _current_raw_stream is not None:
+            return _current_raw_stream(torch.cuda.current_device())
         stream = torch.cuda.current_stream()
     return stream.cuda_stream
 

@@ -156,3 +156,25 @@ def test_repeat_is_deterministic(ctx):
     rows = [0, 1, 999, 1999, 2000, 3998]
     ref = oracle.polymul_rows(p.a, p.da, p.Na, p.b, p.db, p.Nb, rows, wc=o1.shape[1])
     assert np.array_equal(o1[rows], ref)
+
+
+def test_current_stream_is_used(ctx):
+    """Without an explicit stream the binding enqueues on torch's current stream: under a
+    side stream the product follows that stream's earlier work (a copy into the operand)
+    and precedes its later work (a copy of the result)."""
+    from paper_1612_05778_amd import api
+    p = synth.int64_1k()
+    a, b = dev(p.a), dev(p.b)
+    za = torch.zeros_like(a)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    print("[case] int64_1k on a side stream", flush=True)
+    with torch.cuda.stream(s):
+        assert api._stream_handle(None) == s.cuda_stream
+        za.copy_(a)
+        out = ctx.mul(za, p.Na, b, p.Nb)
+        res = out.clone()
+    s.synchronize()
+    assert api._stream_handle(None) == torch.cuda.current_stream().cuda_stream
+    ref = oracle.polymul(p.a, p.da, p.Na, p.b, p.db, p.Nb, wc=res.shape[1])
+    assert np.array_equal(host(res), ref)
