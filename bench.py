@@ -490,7 +490,8 @@ def served_leg(ctx, n_req: int, n_warm: int, load: float, budget: int, streams: 
 
 def latency_leg(ctx, n: int = 400) -> dict:
     """Latency of the small single product (d = 1024 coefficients of signed 64-bit
-    integers each, seed 1): one call at a time, each bracketed by events on its stream."""
+    integers each, seed 1): one call at a time, each bracketed by events on its stream;
+    then the same with the host kept ahead of the device (device time alone)."""
     import torch
     from paper_1612_05778_amd import synth
     from paper_1612_05778_amd.workmodel import product_bits
@@ -511,11 +512,24 @@ def latency_leg(ctx, n: int = 400) -> dict:
     torch.cuda.synchronize()
     wall = (time.perf_counter() - w0) / n
     lat = sorted(ev[i].elapsed_time(ev[i + 1]) * 1e3 for i in range(n))
+    # the same calls queued behind a device-side wait, so that the host is ahead of the
+    # device throughout: the intervals are the device's own time per product, free of
+    # host delays (which the run above includes whenever the host is the slower side)
+    torch.cuda.synchronize()
+    torch.cuda._sleep(int(2.4e9 * 40e-6 * n))      # about 40 us of the shader clock per call
+    ev[0].record(st)
+    for i in range(n):
+        ctx.mul(a, prod.Na, b, prod.Nb, out=out)
+        ev[i + 1].record(st)
+    torch.cuda.synchronize()
+    dev_lat = sorted(ev[i].elapsed_time(ev[i + 1]) * 1e3 for i in range(n))
     bits = product_bits(prod.da, prod.Na, prod.db, prod.Nb)
     med = lat[n // 2]
     return {"workload": "int64_1k", "calls": n, "median_us": med,
             "p99_us": lat[min(n - 1, int(0.99 * n))], "min_us": lat[0],
             "host_wall_us_per_call": wall * 1e6, "value": bits / (med / 1e6),
+            "device_median_us": dev_lat[n // 2],
+            "device_p99_us": dev_lat[min(n - 1, int(0.99 * n))],
             "t_star_us": t_star_of(prod.da, prod.Na, prod.db, prod.Nb) * 1e6}
 
 
